@@ -1,0 +1,248 @@
+"""FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Python side of the plain C oracle in ``mala_oracle.c``.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package.  The GPU library never links, loads or calls it, and
+the two share no code: only the seeded inputs of ``mala_synth`` serve both.
+
+Each function cites the passage of arXiv:2411.19617 it follows; the C file
+holds the arithmetic.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mala_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+KB_EV = 8.617333262e-5
+BISECT_TOL = 1e-12
+
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (plain -O2, OpenMP over grid points)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        d, i, i64, p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        L.oracle_cg.restype = d
+        L.oracle_cg.argtypes = [i] * 6
+        L.oracle_cayley_klein.argtypes = [d, d, d, d, p, p, p, p]
+        L.oracle_cutoff.restype = d
+        L.oracle_cutoff.argtypes = [d, d]
+        L.oracle_wigner_u.argtypes = [i, d, d, d, d, p]
+        L.oracle_u_size.restype = i
+        L.oracle_u_size.argtypes = [i]
+        L.oracle_ui.argtypes = [p, i, d, i, p]
+        L.oracle_n_triples.restype = i
+        L.oracle_n_triples.argtypes = [i]
+        L.oracle_triples.argtypes = [i, p]
+        L.oracle_bispectrum.argtypes = [p, i, p, p]
+        L.oracle_neighbours.restype = i
+        L.oracle_neighbours.argtypes = [p, i, p, p, d, i64, p, i]
+        L.oracle_descriptors.restype = i
+        L.oracle_descriptors.argtypes = [p, i, p, p, d, i, p, i64, p, p, i]
+        L.oracle_mlp.argtypes = [p, i64, i, p, p, p, p, p, p, p, d, i, p, i]
+        L.oracle_dos.argtypes = [p, i64, i, d, p]
+        L.oracle_li_neg.restype = d
+        L.oracle_li_neg.argtypes = [i, d]
+        L.oracle_fermi_weights.argtypes = [d, d, i, d, d, p, p]
+        L.oracle_fermi.restype = i
+        L.oracle_fermi.argtypes = [p, d, d, i, d, d, d, p, p]
+        L.oracle_density.argtypes = [p, i64, i, p, p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ pieces
+
+def cg(j1, m1, j2, m2, j, m):
+    """<j1 m1 j2 m2 | j m>, all arguments doubled (Racah closed form)."""
+    return lib().oracle_cg(j1, m1, j2, m2, j, m)
+
+
+def cayley_klein(d, rcut):
+    """(a, b) of g = exp(-i theta0 n.sigma), theta0 = 0.99363 pi r / rcut."""
+    out = [ctypes.c_double() for _ in range(4)]
+    lib().oracle_cayley_klein(float(d[0]), float(d[1]), float(d[2]), float(rcut),
+                              *[ctypes.byref(o) for o in out])
+    return complex(out[0].value, out[1].value), complex(out[2].value, out[3].value)
+
+
+def cutoff(r, rcut):
+    return lib().oracle_cutoff(float(r), float(rcut))
+
+
+def wigner_u(J, a, b):
+    """(J+1)x(J+1) complex spin-J/2 representation of [[a, b], [-b*, a*]]."""
+    out = np.zeros((J + 1) * (J + 1) * 2)
+    lib().oracle_wigner_u(J, a.real, a.imag, b.real, b.imag, _ptr(out))
+    return (out[0::2] + 1j * out[1::2]).reshape(J + 1, J + 1)
+
+
+def u_levels(disp, rcut, twojmax):
+    """List of u^J matrices (J = 0..twojmax) for one grid point (Eq. SNAPExpansion)."""
+    disp = _f64(disp).reshape(-1, 3)
+    size = lib().oracle_u_size(twojmax)
+    u = np.zeros(2 * size)
+    lib().oracle_ui(_ptr(disp), disp.shape[0], float(rcut), twojmax, _ptr(u))
+    u = u[0::2] + 1j * u[1::2]
+    out, o = [], 0
+    for J in range(twojmax + 1):
+        out.append(u[o:o + (J + 1) ** 2].reshape(J + 1, J + 1))
+        o += (J + 1) ** 2
+    return out
+
+
+def triples(twojmax):
+    n = lib().oracle_n_triples(twojmax)
+    t = np.zeros(3 * n, dtype=np.int32)
+    lib().oracle_triples(twojmax, _ptr(t))
+    return t.reshape(n, 3)
+
+
+def bispectrum_from_u(u_list, twojmax):
+    """B(j1,j2,j) from a list of u^J matrices; returns (B, max |Im|)."""
+    flat = np.concatenate([np.asarray(m, complex).reshape(-1) for m in u_list])
+    buf = np.empty(2 * flat.size)
+    buf[0::2], buf[1::2] = flat.real, flat.imag
+    n = lib().oracle_n_triples(twojmax)
+    B = np.zeros(n)
+    mi = ctypes.c_double()
+    lib().oracle_bispectrum(_ptr(buf), twojmax, _ptr(B), ctypes.byref(mi))
+    return B, mi.value
+
+
+def bispectrum_from_disp(disp, rcut, twojmax):
+    """B for one grid point given its neighbour vectors (neighbour - point)."""
+    return bispectrum_from_u(u_levels(disp, rcut, twojmax), twojmax)
+
+
+def neighbours(snap, p, max_nbr=4096):
+    pos = _f64(snap.positions)
+    L = _f64(snap.L)
+    N = np.ascontiguousarray(snap.N, dtype=np.int32)
+    disp = np.zeros(3 * max_nbr)
+    c = lib().oracle_neighbours(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N), float(snap.rcut),
+                                int(p), _ptr(disp), max_nbr)
+    return disp[:3 * min(c, max_nbr)].reshape(-1, 3)
+
+
+def descriptors(snap, points=None, nthreads=0, return_meta=False):
+    """B[n_pts][n_B] (float64) at flat grid indices `points` (default: all)."""
+    if points is None:
+        points = np.arange(snap.n_points, dtype=np.int64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    pos = _f64(snap.positions)
+    L = _f64(snap.L)
+    N = np.ascontiguousarray(snap.N, dtype=np.int32)
+    nt = lib().oracle_n_triples(snap.twojmax)
+    B = np.zeros((pts.shape[0], nt))
+    mi = ctypes.c_double()
+    worst = lib().oracle_descriptors(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N),
+                                     float(snap.rcut), int(snap.twojmax), _ptr(pts),
+                                     pts.shape[0], _ptr(B), ctypes.byref(mi), int(nthreads))
+    if worst < 0:
+        raise RuntimeError("oracle neighbour list overflow")
+    if return_meta:
+        return B, {"max_neighbours": worst, "max_imag": mi.value}
+    return B
+
+
+def mlp(B, net, nthreads=0):
+    """LDOS[n][n_e] = out_scale * net((B - mean)/std) + out_shift (Eq. ffnn)."""
+    B = _f64(B)
+    n = B.shape[0]
+    widths = np.ascontiguousarray(net["widths"], dtype=np.int32)
+    Wcat = np.concatenate([_f64(w).reshape(-1) for w in net["W"]])
+    bcat = np.concatenate([_f64(b) for b in net["b"]])
+    out = np.zeros((n, widths[-1]))
+    lib().oracle_mlp(_ptr(B), n, len(widths) - 1, _ptr(widths), _ptr(Wcat), _ptr(bcat),
+                     _ptr(_f64(net["in_mean"])), _ptr(_f64(net["in_std"])),
+                     _ptr(_f64(net["out_scale"])), _ptr(_f64(net["out_shift"])),
+                     float(net["slope"]), int(net["output_activation"]), _ptr(out), int(nthreads))
+    return out
+
+
+def dos(ldos, dV):
+    """D_e = dV * sum_p d_e(p) (Eq. DOS.from.ldos)."""
+    ldos = _f64(ldos)
+    out = np.zeros(ldos.shape[1])
+    lib().oracle_dos(_ptr(ldos), ldos.shape[0], ldos.shape[1], float(dV), _ptr(out))
+    return out
+
+
+def li_neg(s, y):
+    """Li_s(-y), 0 <= y <= 1 (s >= 1)."""
+    return lib().oracle_li_neg(int(s), float(y))
+
+
+def fermi_weights(egrid, mu, T):
+    """(w, v): int f D = w.D and int f e D = v.D for piecewise-linear D (Sec. 3.4)."""
+    e0, de, n = egrid
+    w, v = np.zeros(n), np.zeros(n)
+    lib().oracle_fermi_weights(float(e0), float(de), int(n), float(mu), KB_EV * float(T),
+                               _ptr(w), _ptr(v))
+    return w, v
+
+
+class NoRoot(Exception):
+    pass
+
+
+def fermi(dos_, egrid, T, n_electrons, tol=BISECT_TOL):
+    """E_F by bisection, band energy, N(E_F), iterations and final weights."""
+    e0, de, n = egrid
+    dos_ = _f64(dos_)
+    res = np.zeros(4)
+    w = np.zeros(n)
+    st = lib().oracle_fermi(_ptr(dos_), float(e0), float(de), int(n), float(T),
+                            float(n_electrons), float(tol), _ptr(res), _ptr(w))
+    if st != 0:
+        raise NoRoot("N_e outside the attainable range")
+    return {"e_fermi": res[0], "e_band": res[1], "n_found": res[2], "iters": int(res[3]),
+            "weights": w}
+
+
+def density(ldos, w):
+    """n(p) = sum_e w_e d_e(p) (Eq. density.from.ldos)."""
+    ldos = _f64(ldos)
+    out = np.zeros(ldos.shape[0])
+    lib().oracle_density(_ptr(ldos), ldos.shape[0], ldos.shape[1], _ptr(_f64(w)), _ptr(out))
+    return out
+
+
+def predict(snap, net, egrid, points=None, nthreads=0):
+    """Whole path on the listed points (all points by default): B, LDOS, DOS, E_F,
+    E_band and density.  DOS/E_F/E_band are only meaningful over all points."""
+    B = descriptors(snap, points, nthreads)
+    ld = mlp(B, net, nthreads)
+    D = dos(ld, snap.dV)
+    fr = fermi(D, egrid, snap.T, snap.n_electrons)
+    return {"B": B, "ldos": ld, "dos": D, "e_fermi": fr["e_fermi"], "e_band": fr["e_band"],
+            "n_found": fr["n_found"], "iters": fr["iters"], "weights": fr["weights"],
+            "density": density(ld, fr["weights"])}

@@ -1,0 +1,518 @@
+/*
+ * FP64 CPU oracle for the MALA grid-inference path -- TEST INFRASTRUCTURE.
+ *
+ * This file is the plain, slow, obviously-correct reference that the GPU
+ * library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header,
+ * table or constant with the GPU library.
+ *
+ * What it computes (arXiv:2411.19617, "MALA"):
+ *  - neighbour sets of each grid point (Sec. 3.2.2, Eq. ionicdensity): every
+ *    periodic image of every atom closer than the cutoff, self weight 1,
+ *    element weight 1 (single species), smooth cosine cutoff function;
+ *  - expansion coefficients u^j of the ionic density in hyperspherical
+ *    harmonics U^j (Eq. SNAPExpansion), U^j taken as the spin-j irreducible
+ *    representation of the SU(2) element fixed by the neighbour vector,
+ *    written out from its defining polynomial (no recursion);
+ *  - Clebsch-Gordan coefficients from the Racah closed form;
+ *  - bispectrum components B(j1,j2,j) as the rotation-invariant triple
+ *    products of u (Sec. 3.2.2, count of Eq. snap_dim);
+ *  - the feed-forward network x_{l+1} = sigma(W_l x_l + b_l) (Sec. 2.4,
+ *    Eq. ffnn) with input standardisation and an affine output transform;
+ *  - DOS as the spatial sum of the LDOS times the volume element
+ *    (Eq. DOS.from.ldos), energy integrals with Fermi-Dirac weights of a
+ *    piecewise-linear DOS written through polylogarithms
+ *    (Sec. 3.4, Eqs. ldosintegralsummation, fermidiracspecial), the Fermi
+ *    level as the root of the electron-count equation
+ *    (Eq. NumberElectrons_from_DOS) by bisection, the band energy
+ *    (Eq. band.energy) and the density (Eq. density.from.ldos).
+ *
+ * All arithmetic is double precision.  Loops follow the definitions with no
+ * blocking, symmetry folding or reordering.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+#define OR_KB_EV 8.617333262e-5     /* Boltzmann constant, eV/K (CODATA 2018) */
+#define OR_RFAC0 0.99363            /* theta0 = rfac0 * pi * r / rcut */
+#define OR_TJMAX 14
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------ factorials */
+static double fact(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; i++) f *= (double)i;
+    return f;
+}
+
+static double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    return fact(n) / (fact(k) * fact(n - k));
+}
+
+static cplx cpow_int(cplx z, int n)
+{
+    cplx r = 1.0;
+    for (int i = 0; i < n; i++) r *= z;
+    return r;
+}
+
+/* ------------------------------------------------------------ Clebsch-Gordan
+ * <j1 m1 j2 m2 | j m> in the Condon-Shortley convention from the Racah
+ * closed form.  All angular momenta are passed doubled (2j, 2m).          */
+double oracle_cg(int j1, int m1, int j2, int m2, int j, int m)
+{
+    if (m1 + m2 != m) return 0.0;
+    if (j < abs(j1 - j2) || j > j1 + j2 || ((j1 + j2 + j) & 1)) return 0.0;
+    if (abs(m1) > j1 || abs(m2) > j2 || abs(m) > j) return 0.0;
+    if (((j1 + m1) & 1) || ((j2 + m2) & 1) || ((j + m) & 1)) return 0.0;
+    /* integer factorial arguments */
+    int a = (j1 + j2 - j) / 2, b = (j1 - j2 + j) / 2, c = (-j1 + j2 + j) / 2;
+    int d = (j1 + j2 + j) / 2 + 1;
+    double pre = (j + 1.0) * fact(a) * fact(b) * fact(c) / fact(d);
+    pre *= fact((j1 + m1) / 2) * fact((j1 - m1) / 2) * fact((j2 + m2) / 2) *
+           fact((j2 - m2) / 2) * fact((j + m) / 2) * fact((j - m) / 2);
+    double s = 0.0;
+    for (int k = 0; k <= d; k++) {
+        int f1 = a - k, f2 = (j1 - m1) / 2 - k, f3 = (j2 + m2) / 2 - k;
+        int f4 = (j - j2 + m1) / 2 + k, f5 = (j - j1 - m2) / 2 + k;
+        if (f1 < 0 || f2 < 0 || f3 < 0 || f4 < 0 || f5 < 0) continue;
+        double t = 1.0 / (fact(k) * fact(f1) * fact(f2) * fact(f3) * fact(f4) * fact(f5));
+        s += (k & 1) ? -t : t;
+    }
+    return sqrt(pre) * s;
+}
+
+/* ------------------------------------------------------------ geometry
+ * Map a neighbour vector (relative to the grid point) to the Cayley-Klein
+ * parameters of g = exp(-i theta0 n.sigma) = [[a, b], [-conj(b), conj(a)]],
+ * theta0 = rfac0 * pi * r / rcut.  At r = 0 the element is the identity.  */
+void oracle_cayley_klein(double dx, double dy, double dz, double rcut,
+                         double *a_re, double *a_im, double *b_re, double *b_im)
+{
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r == 0.0) {
+        *a_re = 1.0; *a_im = 0.0; *b_re = 0.0; *b_im = 0.0;
+        return;
+    }
+    double th = OR_RFAC0 * OR_PI * r / rcut;
+    double nx = dx / r, ny = dy / r, nz = dz / r;
+    double c = cos(th), s = sin(th);
+    *a_re = c;
+    *a_im = -nz * s;
+    *b_re = -ny * s;
+    *b_im = -nx * s;
+}
+
+double oracle_cutoff(double r, double rcut)
+{
+    if (r >= rcut) return 0.0;
+    return 0.5 * (cos(OR_PI * r / rcut) + 1.0);
+}
+
+/* ------------------------------------------------------------ U^j
+ * Spin-j irrep of g, doubled index J = 2j, rows ma = j + m and columns
+ * mb = j + m' in 0..J: U[ma][mb] is the coefficient of xi^mb eta^(J-mb) in
+ * (a xi - conj(b) eta)^ma (b xi + conj(a) eta)^(J-ma), times
+ * sqrt(mb! (J-mb)! / (ma! (J-ma)!)).  out is (J+1)^2 complex, row-major.  */
+void oracle_wigner_u(int J, double a_re, double a_im, double b_re, double b_im,
+                     double *out /* [(J+1)^2][2] */)
+{
+    cplx a = a_re + I * a_im, b = b_re + I * b_im;
+    cplx mbc = -conj(b), ac = conj(a);
+    for (int ma = 0; ma <= J; ma++) {
+        for (int mb = 0; mb <= J; mb++) {
+            cplx coef = 0.0;
+            for (int s = 0; s <= ma; s++) {
+                int t = mb - s;                 /* power of xi from the second factor */
+                if (t < 0 || t > J - ma) continue;
+                coef += binom(ma, s) * binom(J - ma, t) * cpow_int(a, s) *
+                        cpow_int(mbc, ma - s) * cpow_int(b, t) * cpow_int(ac, J - ma - t);
+            }
+            double norm = sqrt(fact(mb) * fact(J - mb) / (fact(ma) * fact(J - ma)));
+            cplx v = coef * norm;
+            out[2 * (ma * (J + 1) + mb)] = creal(v);
+            out[2 * (ma * (J + 1) + mb) + 1] = cimag(v);
+        }
+    }
+}
+
+/* offset of level J inside the packed full-u array: sum_{J'<J} (J'+1)^2 */
+static int u_off(int J)
+{
+    int o = 0;
+    for (int k = 0; k < J; k++) o += (k + 1) * (k + 1);
+    return o;
+}
+
+int oracle_u_size(int twojmax) { return u_off(twojmax + 1); }
+
+/* u^J = I + sum_k fc(r_k) U^J(g_k) for J = 0..twojmax.  disp is [n][3]
+ * (neighbour minus grid point).  Only neighbours with r < rcut count.     */
+void oracle_ui(const double *disp, int n, double rcut, int twojmax, double *u /* [size][2] */)
+{
+    int size = u_off(twojmax + 1);
+    memset(u, 0, sizeof(double) * 2 * size);
+    for (int J = 0; J <= twojmax; J++)
+        for (int ma = 0; ma <= J; ma++) u[2 * (u_off(J) + ma * (J + 1) + ma)] = 1.0;
+    double *U = malloc(sizeof(double) * 2 * (twojmax + 1) * (twojmax + 1));
+    for (int k = 0; k < n; k++) {
+        double dx = disp[3 * k], dy = disp[3 * k + 1], dz = disp[3 * k + 2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r >= rcut) continue;
+        double fc = oracle_cutoff(r, rcut);
+        double ar, ai, br, bi;
+        oracle_cayley_klein(dx, dy, dz, rcut, &ar, &ai, &br, &bi);
+        for (int J = 0; J <= twojmax; J++) {
+            oracle_wigner_u(J, ar, ai, br, bi, U);
+            int o = u_off(J);
+            for (int e = 0; e < (J + 1) * (J + 1); e++) {
+                u[2 * (o + e)] += fc * U[2 * e];
+                u[2 * (o + e) + 1] += fc * U[2 * e + 1];
+            }
+        }
+    }
+    free(U);
+}
+
+/* ------------------------------------------------------------ bispectrum */
+int oracle_n_triples(int twojmax)
+{
+    int n = 0;
+    for (int j1 = 0; j1 <= twojmax; j1++)
+        for (int j2 = 0; j2 <= j1; j2++)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= twojmax; j += 2)
+                if (j >= j1) n++;
+    return n;
+}
+
+/* triples [n][3] in output order (doubled indices) */
+void oracle_triples(int twojmax, int *out)
+{
+    int n = 0;
+    for (int j1 = 0; j1 <= twojmax; j1++)
+        for (int j2 = 0; j2 <= j1; j2++)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= twojmax; j += 2)
+                if (j >= j1) {
+                    out[3 * n] = j1; out[3 * n + 1] = j2; out[3 * n + 2] = j;
+                    n++;
+                }
+}
+
+static cplx uel(const double *u, int J, int ma, int mb)
+{
+    int e = u_off(J) + ma * (J + 1) + mb;
+    return u[2 * e] + I * u[2 * e + 1];
+}
+
+/* B(j1,j2,j) = sum_{m,m'} conj(u^j_{m m'}) Z^j_{m m'}(j1,j2) with
+ * Z^j_{m m'} = sum_{m1,m1'} C^{j m}_{j1 m1 j2 m-m1} C^{j m'}_{j1 m1' j2 m'-m1'}
+ *              u^{j1}_{m1 m1'} u^{j2}_{m-m1, m'-m1'}.
+ * Indices are doubled; m runs over -j..j in steps of 2 (doubled units).
+ * Writes n_triples real parts to B and the largest |imag| to *max_imag.   */
+void oracle_bispectrum(const double *u, int twojmax, double *B, double *max_imag)
+{
+    int nt = oracle_n_triples(twojmax);
+    int *tr = malloc(sizeof(int) * 3 * nt);
+    oracle_triples(twojmax, tr);
+    double mi = 0.0;
+    for (int t = 0; t < nt; t++) {
+        int j1 = tr[3 * t], j2 = tr[3 * t + 1], j = tr[3 * t + 2];
+        cplx sum = 0.0;
+        for (int m = -j; m <= j; m += 2) {
+            for (int mp = -j; mp <= j; mp += 2) {
+                cplx z = 0.0;
+                for (int m1 = -j1; m1 <= j1; m1 += 2) {
+                    int m2 = m - m1;
+                    if (m2 < -j2 || m2 > j2) continue;
+                    double c1 = oracle_cg(j1, m1, j2, m2, j, m);
+                    for (int m1p = -j1; m1p <= j1; m1p += 2) {
+                        int m2p = mp - m1p;
+                        if (m2p < -j2 || m2p > j2) continue;
+                        double c2 = oracle_cg(j1, m1p, j2, m2p, j, mp);
+                        z += c1 * c2 * uel(u, j1, (j1 + m1) / 2, (j1 + m1p) / 2) *
+                             uel(u, j2, (j2 + m2) / 2, (j2 + m2p) / 2);
+                    }
+                }
+                sum += conj(uel(u, j, (j + m) / 2, (j + mp) / 2)) * z;
+            }
+        }
+        B[t] = creal(sum);
+        if (fabs(cimag(sum)) > mi) mi = fabs(cimag(sum));
+    }
+    if (max_imag) *max_imag = mi;
+    free(tr);
+}
+
+/* ------------------------------------------------------------ neighbours
+ * Grid point p = (i, j, k), flat index p = (i*Ny + j)*Nz + k, position
+ * (i Lx/Nx, j Ly/Ny, k Lz/Nz).  Neighbours: all periodic images R + n*L of
+ * all atoms with |R + n*L - r_p| < rcut, found by brute force over a box of
+ * image shifts that covers the cutoff sphere.                              */
+static void grid_point(const int *N, const double *L, int64_t p, double *r)
+{
+    int64_t k = p % N[2], j = (p / N[2]) % N[1], i = p / ((int64_t)N[1] * N[2]);
+    r[0] = (double)i * L[0] / N[0];
+    r[1] = (double)j * L[1] / N[1];
+    r[2] = (double)k * L[2] / N[2];
+}
+
+int oracle_neighbours(const double *pos, int n_atoms, const double *L, const int *N,
+                      double rcut, int64_t p, double *disp, int max_nbr)
+{
+    double r[3];
+    grid_point(N, L, p, r);
+    int nmax[3];
+    for (int d = 0; d < 3; d++) nmax[d] = (int)ceil(rcut / L[d]) + 1;
+    int cnt = 0;
+    for (int a = 0; a < n_atoms; a++) {
+        for (int nx = -nmax[0]; nx <= nmax[0]; nx++)
+            for (int ny = -nmax[1]; ny <= nmax[1]; ny++)
+                for (int nz = -nmax[2]; nz <= nmax[2]; nz++) {
+                    double dx = pos[3 * a] + nx * L[0] - r[0];
+                    double dy = pos[3 * a + 1] + ny * L[1] - r[1];
+                    double dz = pos[3 * a + 2] + nz * L[2] - r[2];
+                    if (dx * dx + dy * dy + dz * dz < rcut * rcut) {
+                        if (cnt < max_nbr) {
+                            disp[3 * cnt] = dx; disp[3 * cnt + 1] = dy; disp[3 * cnt + 2] = dz;
+                        }
+                        cnt++;
+                    }
+                }
+    }
+    return cnt;
+}
+
+/* B at the listed flat grid points; B_out is [n_pts][n_triples].
+ * Returns the largest neighbour count seen (or -1 if max_nbr overflowed). */
+int oracle_descriptors(const double *pos, int n_atoms, const double *L, const int *N,
+                       double rcut, int twojmax, const int64_t *pts, int64_t n_pts,
+                       double *B_out, double *max_imag_out, int nthreads)
+{
+    const int max_nbr = 4096;
+    int nt = oracle_n_triples(twojmax);
+    int usz = oracle_u_size(twojmax);
+    int worst = 0, overflow = 0;
+    double mi_all = 0.0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel reduction(max : worst, mi_all) reduction(| : overflow)
+#endif
+    {
+        double *disp = malloc(sizeof(double) * 3 * max_nbr);
+        double *u = malloc(sizeof(double) * 2 * usz);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+        for (int64_t q = 0; q < n_pts; q++) {
+            int cnt = oracle_neighbours(pos, n_atoms, L, N, rcut, pts[q], disp, max_nbr);
+            if (cnt > max_nbr) { overflow = 1; cnt = max_nbr; }
+            if (cnt > worst) worst = cnt;
+            oracle_ui(disp, cnt, rcut, twojmax, u);
+            double mi;
+            oracle_bispectrum(u, twojmax, B_out + q * nt, &mi);
+            if (mi > mi_all) mi_all = mi;
+        }
+        free(disp);
+        free(u);
+    }
+    if (max_imag_out) *max_imag_out = mi_all;
+    return overflow ? -1 : worst;
+}
+
+/* ------------------------------------------------------------ network
+ * x0 = (B - mean) / std; x_{l+1} = act(W_l x_l + b_l) for every layer
+ * (activation on the output layer too when out_act != 0), act = LeakyReLU
+ * with the given negative slope; then ldos = out_scale * y + out_shift.
+ * W[l] is [widths[l+1]][widths[l]] row-major; all pointers are concatenated
+ * per layer in Wcat / bcat.                                                */
+void oracle_mlp(const double *B, int64_t n_pts, int n_layers, const int *widths,
+                const double *Wcat, const double *bcat, const double *in_mean,
+                const double *in_std, const double *out_scale, const double *out_shift,
+                double slope, int out_act, double *ldos, int nthreads)
+{
+    int wmax = 0;
+    for (int l = 0; l <= n_layers; l++) if (widths[l] > wmax) wmax = widths[l];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        double *x = malloc(sizeof(double) * wmax), *y = malloc(sizeof(double) * wmax);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t p = 0; p < n_pts; p++) {
+            for (int i = 0; i < widths[0]; i++)
+                x[i] = (B[p * widths[0] + i] - in_mean[i]) / in_std[i];
+            const double *W = Wcat, *b = bcat;
+            for (int l = 0; l < n_layers; l++) {
+                int fin = widths[l], fout = widths[l + 1];
+                for (int o = 0; o < fout; o++) {
+                    double s = b[o];
+                    for (int i = 0; i < fin; i++) s += W[o * fin + i] * x[i];
+                    int act = (l < n_layers - 1) || out_act;
+                    y[o] = (act && s < 0.0) ? slope * s : s;
+                }
+                memcpy(x, y, sizeof(double) * fout);
+                W += fout * fin;
+                b += fout;
+            }
+            int nout = widths[n_layers];
+            for (int e = 0; e < nout; e++)
+                ldos[p * nout + e] = out_scale[e] * x[e] + out_shift[e];
+        }
+        free(x);
+        free(y);
+    }
+}
+
+/* ------------------------------------------------------------ DOS
+ * D_e = dV * sum_p d_e(p): the spatial integral of the LDOS as a sum over
+ * grid points times the volume element.                                    */
+void oracle_dos(const double *ldos, int64_t n_pts, int n_e, double dV, double *dos)
+{
+    for (int e = 0; e < n_e; e++) dos[e] = 0.0;
+    for (int64_t p = 0; p < n_pts; p++)
+        for (int e = 0; e < n_e; e++) dos[e] += ldos[p * n_e + e];
+    for (int e = 0; e < n_e; e++) dos[e] *= dV;
+}
+
+/* ------------------------------------------------------------ polylog
+ * Li_s(-y) for 0 <= y <= 1 and s >= 1 as the alternating series
+ * -sum_{k>=0} (-1)^k y^(k+1)/(k+1)^s, summed with the Cohen-Rodriguez
+ * Villegas-Zagier acceleration (Exp. Math. 9 (2000), Algorithm 1), valid
+ * because y^(k+1)/(k+1)^s is a moment sequence.  40 terms: error
+ * ~ (3+sqrt 8)^-40.                                                        */
+double oracle_li_neg(int s, double y)
+{
+    if (y == 0.0) return 0.0;
+    if (s == 1) return -log1p(y);
+    const int n = 40;
+    double d = pow(3.0 + sqrt(8.0), n);
+    d = 0.5 * (d + 1.0 / d);
+    double b = -1.0, c = -d, sum = 0.0, yk = y;
+    for (int k = 0; k < n; k++) {
+        c = b - c;
+        sum += c * yk / pow((double)(k + 1), s);
+        b = (double)(k + n) * (double)(k - n) * b / ((k + 0.5) * (k + 1.0));
+        yk *= y;
+    }
+    return -sum / d;
+}
+
+/* Antiderivatives in x = beta (e - mu) of f = 1/(1+e^x) times 1, x, x^2:
+ *   G0 = x - ln(1+e^x), G1 = x^2/2 - x ln(1+e^x) - Li2(-e^x),
+ *   G2 = x^3/3 - x^2 ln(1+e^x) - 2x Li2(-e^x) + 2 Li3(-e^x),
+ * from d/dx Li_s(-e^x) = Li_{s-1}(-e^x) and f = 1 + Li0(-e^x).  For x > 0
+ * the same functions are written with the inversion formulas of Li2, Li3
+ * so that only Li_s(-e^-x) appears.                                        */
+static void g012(double x, double *g0, double *g1, double *g2)
+{
+    if (x <= 0.0) {
+        double y = exp(x), Lg = log1p(y);
+        double l2 = oracle_li_neg(2, y), l3 = oracle_li_neg(3, y);
+        *g0 = x - Lg;
+        *g1 = 0.5 * x * x - x * Lg - l2;
+        *g2 = x * x * x / 3.0 - x * x * Lg - 2.0 * x * l2 + 2.0 * l3;
+    } else {
+        double y = exp(-x), Lg = log1p(y);
+        double l2 = oracle_li_neg(2, y), l3 = oracle_li_neg(3, y);
+        *g0 = -Lg;
+        *g1 = OR_PI * OR_PI / 6.0 - x * Lg + l2;
+        *g2 = -x * x * Lg + 2.0 * x * l2 + 2.0 * l3;
+    }
+}
+
+/* Weights of a piecewise-linear DOS on the uniform grid e_i = e0 + i de:
+ *   int f(e) D(e) de   = sum_i w_i D_i,
+ *   int f(e) e D(e) de = sum_i v_i D_i,
+ * exact for D linear between grid points and zero outside.  kT in eV.     */
+void oracle_fermi_weights(double e0, double de, int n, double mu, double kT,
+                          double *w, double *v)
+{
+    double beta = 1.0 / kT;
+    for (int i = 0; i < n; i++) { w[i] = 0.0; v[i] = 0.0; }
+    for (int i = 0; i + 1 < n; i++) {
+        double xa = beta * (e0 + i * de - mu), xb = beta * (e0 + (i + 1) * de - mu);
+        double a0, a1, a2, b0, b1, b2;
+        g012(xa, &a0, &a1, &a2);
+        g012(xb, &b0, &b1, &b2);
+        double D = xb - xa;                     /* = beta * de */
+        /* int f de over the interval, and int f (e - e_i)/de de           */
+        double I0 = (b0 - a0) / beta;
+        double I1 = ((b1 - a1) - xa * (b0 - a0)) / (beta * D);
+        /* int f x de and int f x (e - e_i)/de de, x = beta (e - mu)        */
+        double K0 = (b1 - a1) / beta;
+        double K1 = ((b2 - a2) - xa * (b1 - a1)) / (beta * D);
+        /* hat functions: phi_i = 1 - t, phi_{i+1} = t, t = (e - e_i)/de   */
+        w[i] += I0 - I1;
+        w[i + 1] += I1;
+        /* e = mu + x / beta */
+        v[i] += mu * (I0 - I1) + (K0 - K1) / beta;
+        v[i + 1] += mu * I1 + K1 / beta;
+    }
+}
+
+static double count_electrons(const double *dos, double e0, double de, int n, double mu,
+                              double kT, double *w, double *v)
+{
+    oracle_fermi_weights(e0, de, n, mu, kT, w, v);
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += w[i] * dos[i];
+    return s;
+}
+
+/* Fermi level by bisection on [e_0, e_{n-1}] (N(mu) < N_e -> raise lo),
+ * stopping at hi - lo < tol; then the band energy and the final weights.
+ * res = {E_F, E_band, N(E_F), iterations}.  Returns 0, or -4 when N_e is
+ * outside [N(e_0), N(e_{n-1})].                                            */
+int oracle_fermi(const double *dos, double e0, double de, int n, double T_K, double n_e,
+                 double tol, double *res, double *w_out)
+{
+    double kT = OR_KB_EV * T_K;
+    double *w = malloc(sizeof(double) * n), *v = malloc(sizeof(double) * n);
+    double lo = e0, hi = e0 + (n - 1) * de;
+    double nlo = count_electrons(dos, e0, de, n, lo, kT, w, v);
+    double nhi = count_electrons(dos, e0, de, n, hi, kT, w, v);
+    if (!(nlo <= n_e && n_e <= nhi)) {
+        free(w); free(v);
+        return -4;
+    }
+    int it = 0;
+    while (hi - lo >= tol && it < 200) {
+        double mid = 0.5 * (lo + hi);
+        if (count_electrons(dos, e0, de, n, mid, kT, w, v) < n_e) lo = mid; else hi = mid;
+        it++;
+    }
+    double ef = 0.5 * (lo + hi);
+    double ne = count_electrons(dos, e0, de, n, ef, kT, w, v);
+    double eb = 0.0;
+    for (int i = 0; i < n; i++) eb += v[i] * dos[i];
+    res[0] = ef; res[1] = eb; res[2] = ne; res[3] = it;
+    if (w_out) memcpy(w_out, w, sizeof(double) * n);
+    free(w); free(v);
+    return 0;
+}
+
+/* n(p) = sum_e w_e d_e(p) (Eq. density.from.ldos with the same weights). */
+void oracle_density(const double *ldos, int64_t n_pts, int n_e, const double *w, double *dens)
+{
+    for (int64_t p = 0; p < n_pts; p++) {
+        double s = 0.0;
+        for (int e = 0; e < n_e; e++) s += w[e] * ldos[p * n_e + e];
+        dens[p] = s;
+    }
+}
+
+double oracle_kb_ev(void) { return OR_KB_EV; }

@@ -1,0 +1,460 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself.
+
+Each test ties one oracle function to mathematics or to an independent
+library routine (sympy's Clebsch-Gordan and Wigner-d, mpmath's polylog and
+quadrature, numpy's matmul, Gauss-Legendre quadrature), chosen so that a
+plausible slip (dropped term, sign, transposed operand, wrong index) fails.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+RC = 4.67
+
+
+def rand_rot(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def rand_su2(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    return complex(q[0], q[1]), complex(q[2], q[3])
+
+
+def rand_disp(rng, n, rmax=RC * 0.98):
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    return d * (rng.uniform(0.5, rmax, size=n))[:, None]
+
+
+# ------------------------------------------------------------------ counts
+
+def test_triple_count_matches_paper_formula():
+    rows = np.loadtxt(os.path.join(GOLD, "snap_dim.txt"), comments="#", dtype=int)
+    for tj, count in rows:
+        assert oracle.triples(int(tj)).shape[0] == count
+        assert oracle.lib().oracle_n_triples(int(tj)) == count
+
+
+def test_paper_descriptor_parameters_give_91():
+    kv = dict(l.split() for l in open(os.path.join(GOLD, "paper_parameters.txt"))
+              if l.strip() and not l.startswith("#"))
+    assert oracle.triples(int(kv["twojmax"])).shape[0] == 91
+
+
+def test_triple_order_and_constraints():
+    t = oracle.triples(10)
+    for j1, j2, j in t:
+        assert j2 <= j1 <= j <= 10 and abs(j1 - j2) <= j <= j1 + j2 and (j1 + j2 + j) % 2 == 0
+    assert [tuple(x) for x in t] == sorted(set(tuple(x) for x in t))
+
+
+# ------------------------------------------------------------------ Clebsch-Gordan
+
+def test_cg_matches_sympy():
+    from sympy import Rational
+    from sympy.physics.wigner import clebsch_gordan
+    n = 0
+    for j1 in range(0, 7):
+        for j2 in range(0, 7):
+            for j in range(abs(j1 - j2), j1 + j2 + 1, 2):
+                for m1 in range(-j1, j1 + 1, 2):
+                    for m2 in range(-j2, j2 + 1, 2):
+                        m = m1 + m2
+                        if abs(m) > j:
+                            continue
+                        ref = float(clebsch_gordan(Rational(j1, 2), Rational(j2, 2), Rational(j, 2),
+                                                   Rational(m1, 2), Rational(m2, 2), Rational(m, 2)))
+                        assert abs(oracle.cg(j1, m1, j2, m2, j, m) - ref) < 1e-14
+                        n += 1
+    assert n > 1000
+
+
+def test_cg_orthonormality_up_to_twojmax_10():
+    for j1 in range(0, 11):
+        for j2 in range(0, j1 + 1):
+            js = list(range(j1 - j2, j1 + j2 + 1, 2))
+            for m in range(-(j1 + j2), j1 + j2 + 1, 2):
+                pairs = [(m1, m - m1) for m1 in range(-j1, j1 + 1, 2) if abs(m - m1) <= j2]
+                M = np.array([[oracle.cg(j1, m1, j2, m2, j, m) for (m1, m2) in pairs] for j in js
+                              if abs(m) <= j])
+                assert np.allclose(M @ M.T, np.eye(M.shape[0]), atol=1e-13)
+
+
+# ------------------------------------------------------------------ U^j
+
+def test_u_is_a_unitary_representation():
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        a1, b1 = rand_su2(rng)
+        a2, b2 = rand_su2(rng)
+        g1 = np.array([[a1, b1], [-np.conj(b1), np.conj(a1)]])
+        g2 = np.array([[a2, b2], [-np.conj(b2), np.conj(a2)]])
+        g = g1 @ g2
+        for J in range(0, 11):
+            U1, U2 = oracle.wigner_u(J, a1, b1), oracle.wigner_u(J, a2, b2)
+            U = oracle.wigner_u(J, g[0, 0], g[0, 1])
+            assert np.allclose(U1 @ U1.conj().T, np.eye(J + 1), atol=1e-13)
+            # the polynomial-substitution definition gives the transposed action,
+            # so U(g1 g2) = U(g2) U(g1): U^T is a homomorphism of SU(2)
+            assert np.allclose(U, U2 @ U1, atol=1e-12)
+
+
+def test_u_character_formula():
+    # trace of the spin-J/2 irrep of an SU(2) element with eigenvalues e^{+-i t}
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        a, b = rand_su2(rng)
+        t = np.arccos(a.real)
+        for J in range(0, 11):
+            chi = np.trace(oracle.wigner_u(J, a, b))
+            assert abs(chi - np.sin((J + 1) * t) / np.sin(t)) < 1e-11
+
+
+def test_u_rotation_about_y_matches_sympy_wigner_d():
+    from sympy import Rational, N as sN
+    from sympy.physics.quantum.spin import Rotation
+    r = 0.8
+    a, b = oracle.cayley_klein([0.0, r, 0.0], RC)
+    th0 = 0.99363 * np.pi * r / RC
+    for J in range(1, 7):
+        U = oracle.wigner_u(J, a, b)
+        D = np.zeros((J + 1, J + 1))
+        for ma in range(J + 1):
+            for mb in range(J + 1):
+                v = complex(sN(Rotation.d(Rational(J, 2), Rational(J - 2 * ma, 2),
+                                          Rational(J - 2 * mb, 2), 2 * th0).doit()))
+                D[ma, mb] = v.real
+        assert np.max(np.abs(U - D)) < 1e-12
+
+
+def test_u_rotation_about_z_is_diagonal_phase():
+    r = 1.3
+    a, b = oracle.cayley_klein([0.0, 0.0, r], RC)
+    th0 = 0.99363 * np.pi * r / RC
+    assert abs(b) == 0.0
+    for J in range(0, 11):
+        U = oracle.wigner_u(J, a, b)
+        phases = np.exp(-1j * th0 * (2 * np.arange(J + 1) - J))
+        assert np.allclose(U, np.diag(phases), atol=1e-13)
+
+
+def test_cayley_klein_and_cutoff():
+    a, b = oracle.cayley_klein([0.0, 0.0, 0.0], RC)
+    assert a == 1 and b == 0
+    rng = np.random.default_rng(3)
+    for d in rand_disp(rng, 10):
+        a, b = oracle.cayley_klein(d, RC)
+        assert abs(abs(a) ** 2 + abs(b) ** 2 - 1) < 1e-15
+    assert oracle.cutoff(0.0, RC) == 1.0
+    assert oracle.cutoff(RC, RC) == 0.0
+    assert abs(oracle.cutoff(RC / 2, RC) - 0.5) < 1e-15
+
+
+# ------------------------------------------------------------------ u and B
+
+def test_u_sums_identity_and_weighted_neighbours():
+    rng = np.random.default_rng(4)
+    d = rand_disp(rng, 3)
+    u = oracle.u_levels(d, RC, 4)
+    r = np.linalg.norm(d, axis=1)
+    assert abs(u[0][0, 0] - (1 + sum(oracle.cutoff(x, RC) for x in r))) < 1e-14
+    for J in range(5):
+        ref = np.eye(J + 1, dtype=complex)
+        for k in range(3):
+            a, b = oracle.cayley_klein(d[k], RC)
+            ref += oracle.cutoff(r[k], RC) * oracle.wigner_u(J, a, b)
+        assert np.allclose(u[J], ref, atol=1e-14)
+
+
+@pytest.mark.parametrize("tj", [4, 8, 10])
+def test_b_empty_neighbourhood_is_j_plus_1(tj):
+    B, mi = oracle.bispectrum_from_disp(np.zeros((0, 3)), RC, tj)
+    t = oracle.triples(tj)
+    assert np.max(np.abs(B - (t[:, 2] + 1))) < 1e-12 and mi < 1e-14
+
+
+def test_b_atom_on_grid_point():
+    # one atom exactly on the point: u = 2 I, so B = 8 (J+1)
+    B, _ = oracle.bispectrum_from_disp(np.zeros((1, 3)), RC, 8)
+    t = oracle.triples(8)
+    assert np.max(np.abs(B - 8 * (t[:, 2] + 1))) < 1e-11
+
+
+def test_b000_is_weighted_count_cubed():
+    rng = np.random.default_rng(5)
+    d = rand_disp(rng, 12)
+    B, _ = oracle.bispectrum_from_disp(d, RC, 6)
+    fc = sum(oracle.cutoff(np.linalg.norm(x), RC) for x in d)
+    assert abs(B[0] - (1 + fc) ** 3) < 1e-11 * B[0]
+
+
+@pytest.mark.parametrize("tj", [6, 10])
+def test_b_invariances(tj):
+    rng = np.random.default_rng(10 + tj)
+    d = rand_disp(rng, 9 if tj == 10 else 14)
+    B, mi = oracle.bispectrum_from_disp(d, RC, tj)
+    scale = np.max(np.abs(B))
+    assert mi < 1e-13 * scale
+    R = rand_rot(rng)
+    Br, _ = oracle.bispectrum_from_disp(d @ R.T, RC, tj)
+    Bi, _ = oracle.bispectrum_from_disp(-d, RC, tj)
+    Bp, _ = oracle.bispectrum_from_disp(d[rng.permutation(d.shape[0])], RC, tj)
+    for other in (Br, Bi, Bp):
+        assert np.max(np.abs(other - B)) < 1e-12 * scale
+    # a neighbour outside the cutoff changes nothing
+    Bo, _ = oracle.bispectrum_from_disp(np.vstack([d, [[0, 0, RC * 1.01]]]), RC, tj)
+    assert np.max(np.abs(Bo - B)) == 0.0
+
+
+def _b_any(u, j1, j2, j):
+    """B(j1,j2,j) for any admissible order, from u and the oracle's CG."""
+    tot = 0j
+    for m in range(-j, j + 1, 2):
+        for mp in range(-j, j + 1, 2):
+            z = 0j
+            for m1 in range(-j1, j1 + 1, 2):
+                for m1p in range(-j1, j1 + 1, 2):
+                    m2, m2p = m - m1, mp - m1p
+                    if abs(m2) > j2 or abs(m2p) > j2:
+                        continue
+                    z += (oracle.cg(j1, m1, j2, m2, j, m) * oracle.cg(j1, m1p, j2, m2p, j, mp) *
+                          u[j1][(j1 + m1) // 2, (j1 + m1p) // 2] * u[j2][(j2 + m2) // 2, (j2 + m2p) // 2])
+            tot += np.conj(u[j][(j + m) // 2, (j + mp) // 2]) * z
+    return tot.real
+
+
+def test_b_permutation_identities():
+    rng = np.random.default_rng(12)
+    d = rand_disp(rng, 6)
+    u = oracle.u_levels(d, RC, 6)
+    B, _ = oracle.bispectrum_from_u(u, 6)
+    idx = {tuple(t): k for k, t in enumerate(oracle.triples(6))}
+    for (j1, j2, j), k in idx.items():
+        assert abs(_b_any(u, j2, j1, j) - B[k]) < 1e-11 * abs(B).max()
+        # B(j1,j2,j) (j1+1) = B(j,j2,j1) (j+1)  (doubled indices)
+        lhs = B[k] * (j1 + 1)
+        rhs = _b_any(u, j, j2, j1) * (j + 1)
+        assert abs(lhs - rhs) < 1e-10 * abs(B).max()
+
+
+def test_b_single_neighbour_on_z_closed_form():
+    # neighbour on +z: U is diagonal, so B = sum_m conj(u_mm) sum_m1 C^2 u1_m1m1 u2_m2m2
+    from sympy import Rational
+    from sympy.physics.wigner import clebsch_gordan
+    r = 2.1
+    fc = oracle.cutoff(r, RC)
+    th0 = 0.99363 * np.pi * r / RC
+
+    def diag(J, ma):
+        return 1 + fc * np.exp(-1j * th0 * (2 * ma - J))
+
+    B, _ = oracle.bispectrum_from_disp(np.array([[0.0, 0.0, r]]), RC, 6)
+    for k, (j1, j2, j) in enumerate(oracle.triples(6)):
+        tot = 0j
+        for m in range(-j, j + 1, 2):
+            s = 0j
+            for m1 in range(-j1, j1 + 1, 2):
+                m2 = m - m1
+                if abs(m2) > j2:
+                    continue
+                c = float(clebsch_gordan(Rational(j1, 2), Rational(j2, 2), Rational(j, 2),
+                                         Rational(m1, 2), Rational(m2, 2), Rational(m, 2)))
+                s += c * c * diag(j1, (j1 + m1) // 2) * diag(j2, (j2 + m2) // 2)
+            tot += np.conj(diag(j, (j + m) // 2)) * s
+        assert abs(tot.real - B[k]) < 1e-12 * max(1.0, abs(B).max())
+    # the same closed form holds for the neighbour in any direction
+    R = rand_rot(np.random.default_rng(1))
+    Br, _ = oracle.bispectrum_from_disp(np.array([[0.0, 0.0, r]]) @ R.T, RC, 6)
+    assert np.max(np.abs(Br - B)) < 1e-12 * abs(B).max()
+
+
+# ------------------------------------------------------------------ grid geometry
+
+def test_neighbours_brute_force_periodic_images():
+    import mala_synth
+    s = mala_synth.small()                   # L = 8.1 < 2 rcut: several images per atom
+    for p in (0, 137, 7999):
+        d = oracle.neighbours(s, p)
+        k, j, i = p % 20, (p // 20) % 20, p // 400
+        r = np.array([i, j, k]) * s.L / s.N
+        ref = []
+        for a in s.positions:
+            for n in np.ndindex(5, 5, 5):
+                v = a + (np.array(n) - 2) * s.L - r
+                if np.dot(v, v) < RC * RC:
+                    ref.append(v)
+        ref = np.array(ref)
+        assert d.shape == ref.shape
+        key = lambda x: tuple(np.round(x, 9))
+        assert sorted(map(key, d)) == sorted(map(key, ref))
+
+
+def test_descriptor_field_translation():
+    import mala_synth
+    s = mala_synth.small()
+    shift = np.array([3, 1, 2])
+    t = mala_synth.Snapshot("shifted", np.mod(s.positions + shift * s.L / s.N, s.L), s.L, s.N,
+                            s.rcut, 6, s.T, s.n_electrons)
+    s6 = mala_synth.with_grid(s, s.N)
+    s6.twojmax = 6
+    pts = np.array([0, 21, 455, 7999])
+    ijk = np.stack([pts // 400, (pts // 20) % 20, pts % 20], 1)
+    moved = ((ijk + shift) % 20) @ np.array([400, 20, 1])
+    B0 = oracle.descriptors(s6, pts)
+    B1 = oracle.descriptors(t, moved)
+    assert np.max(np.abs(B0 - B1)) < 1e-9 * np.abs(B0).max()
+
+
+# ------------------------------------------------------------------ network
+
+def test_mlp_matches_numpy_chain():
+    import mala_synth
+    rng = np.random.default_rng(0)
+    for out_act in (1, 0):
+        net = mala_synth.make_net([7, 11, 5, 9], 3, 8, output_activation=out_act,
+                                  with_input_scaler=False, egrid=(-5.0, 0.1, 9))
+        net["in_mean"] = rng.normal(size=7)
+        net["in_std"] = rng.uniform(0.5, 2, size=7)
+        B = rng.normal(size=(13, 7)) * 3
+        x = (B - net["in_mean"]) / net["in_std"]
+        for l in range(3):
+            x = x @ net["W"][l].T + net["b"][l]
+            if l < 2 or out_act:
+                x = np.where(x < 0, 0.01 * x, x)
+        ref = net["out_scale"] * x + net["out_shift"]
+        assert np.allclose(oracle.mlp(B, net), ref, rtol=1e-13, atol=1e-14)
+
+
+def test_dos_is_scaled_sum():
+    rng = np.random.default_rng(2)
+    ld = rng.uniform(size=(50, 17))
+    assert np.allclose(oracle.dos(ld, 0.37), 0.37 * ld.sum(0), rtol=1e-14)
+
+
+# ------------------------------------------------------------------ integration
+
+def test_polylog_against_mpmath_and_closed_forms():
+    import mpmath
+    for s in (2, 3):
+        for y in (0.0, 1e-8, 0.05, 0.3, 0.5, 0.77, 0.999, 1.0):
+            ref = float(mpmath.polylog(s, -y))
+            assert abs(oracle.li_neg(s, y) - ref) < 1e-15 * max(1, abs(ref))
+    assert abs(oracle.li_neg(2, 1.0) + np.pi ** 2 / 12) < 1e-15
+    assert abs(oracle.li_neg(3, 1.0) + 0.75 * 1.2020569031595942) < 1e-15
+    assert abs(oracle.li_neg(1, 0.4) + np.log1p(0.4)) < 1e-15
+
+
+def _fermi(e, mu, kT):
+    return 0.5 * (1 - np.tanh(0.5 * (e - mu) / kT))
+
+
+@pytest.mark.parametrize("T,mu", [(298.0, 6.27), (933.0, 3.05), (298.0, -4.93), (5000.0, 19.8)])
+def test_weights_match_gauss_legendre(T, mu):
+    eg = (-5.0, 0.1, 250)
+    kT = oracle.KB_EV * T
+    w, v = oracle.fermi_weights(eg, mu, T)
+    e = eg[0] + eg[1] * np.arange(eg[2])
+    rng = np.random.default_rng(1)
+    D = rng.uniform(0.1, 2.0, size=eg[2])
+    xg, wg = np.polynomial.legendre.leggauss(64)
+    N = Eb = 0.0
+    for i in range(eg[2] - 1):
+        # split the interval at mu so the quadrature sees a smooth integrand
+        cuts = [e[i], e[i + 1]]
+        if e[i] < mu < e[i + 1]:
+            cuts = [e[i], mu, e[i + 1]]
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            x = 0.5 * (hi - lo) * xg + 0.5 * (hi + lo)
+            Dx = D[i] + (D[i + 1] - D[i]) * (x - e[i]) / eg[1]
+            f = _fermi(x, mu, kT)
+            N += 0.5 * (hi - lo) * np.sum(wg * f * Dx)
+            Eb += 0.5 * (hi - lo) * np.sum(wg * f * x * Dx)
+    assert abs(w @ D - N) < 1e-12 * N
+    assert abs(v @ D - Eb) < 1e-11 * max(1.0, abs(Eb))
+
+
+def test_weights_constant_dos_closed_form():
+    eg = (-5.0, 0.1, 250)
+    for T, mu in ((298.0, 6.0), (933.0, 0.123)):
+        kT = oracle.KB_EV * T
+        w, _ = oracle.fermi_weights(eg, mu, T)
+        a, b = eg[0], eg[0] + eg[1] * (eg[2] - 1)
+        F = lambda e: e - kT * np.logaddexp(0.0, (e - mu) / kT)
+        assert abs(w.sum() - (F(b) - F(a))) < 1e-12
+
+
+def test_weights_zero_temperature_limit_is_trapezoid():
+    eg = (-5.0, 0.1, 250)
+    mu = 2.0                                   # on a grid point: e_70
+    w, v = oracle.fermi_weights(eg, mu, 1e-3)
+    ref = np.zeros(250)
+    ref[:71] = 0.1
+    ref[0] = ref[70] = 0.05
+    assert np.max(np.abs(w - ref)) < 1e-9
+    e = eg[0] + eg[1] * np.arange(250)
+    # exact int_{e0}^{mu} e * (piecewise linear D = 1) de
+    assert abs(v.sum() - 0.5 * (mu * mu - 25.0)) < 1e-8
+
+
+def test_weights_mpmath_high_precision():
+    import mpmath
+    mpmath.mp.dps = 30
+    eg = (-5.0, 0.1, 20)
+    mu, T = -4.03, 933.0
+    kT = oracle.KB_EV * T
+    w, v = oracle.fermi_weights(eg, mu, T)
+    e = [eg[0] + eg[1] * i for i in range(eg[2])]
+    for i in (0, 5, 9, 10, 11, 19):
+        def hat(x):
+            if i > 0 and e[i - 1] <= x <= e[i]:
+                return (x - e[i - 1]) / eg[1]
+            if i < eg[2] - 1 and e[i] <= x <= e[i + 1]:
+                return (e[i + 1] - x) / eg[1]
+            return 0
+        f = lambda x: hat(x) / (1 + mpmath.exp((x - mu) / kT))
+        pts = [e[max(i - 1, 0)], e[i], e[min(i + 1, eg[2] - 1)]]
+        ref = float(mpmath.quad(f, pts))
+        refv = float(mpmath.quad(lambda x: x * f(x), pts))
+        assert abs(w[i] - ref) < 1e-14
+        assert abs(v[i] - refv) < 1e-13
+
+
+def test_fermi_root_monotone_and_no_root():
+    eg = (-5.0, 0.1, 250)
+    e = eg[0] + eg[1] * np.arange(250)
+    D = 40.0 * np.sqrt(e + 5.5)
+    for T in (298.0, 933.0):
+        r = oracle.fermi(D, eg, T, 768.0)
+        w, _ = oracle.fermi_weights(eg, r["e_fermi"], T)
+        assert abs(w @ D - 768.0) < 1e-8
+        lo, _ = oracle.fermi_weights(eg, r["e_fermi"] - 1e-6, T)
+        assert lo @ D < 768.0
+        assert r["iters"] <= 64
+    with pytest.raises(oracle.NoRoot):
+        oracle.fermi(D, eg, 298.0, 1e7)
+    with pytest.raises(oracle.NoRoot):
+        oracle.fermi(D, eg, 298.0, 0.0)
+
+
+def test_density_integrates_to_electron_count():
+    rng = np.random.default_rng(9)
+    eg = (-5.0, 0.1, 250)
+    e = eg[0] + eg[1] * np.arange(250)
+    ld = rng.uniform(0.5, 1.5, size=(300, 250)) * 0.007 * np.sqrt(e + 5.5)
+    dV = 0.3
+    D = oracle.dos(ld, dV)
+    ne = 0.5 * (w0 := oracle.fermi_weights(eg, 19.0, 298.0)[0]) @ D
+    r = oracle.fermi(D, eg, 298.0, ne)
+    n = oracle.density(ld, r["weights"])
+    assert abs(n.sum() * dV - ne) < 1e-9 * ne
