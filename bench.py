@@ -1,0 +1,189 @@
+"""Benchmark of the grid-inference path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload paper_solid]
+                    [--precision fp32|bf16] [--no-cpu-baseline]
+
+A step is one call of the fused path (mala_predict) on one synthetic
+snapshot: atom binning, bispectrum descriptors of every grid point, the
+network with the DOS reduced in its epilogue, Fermi level, band energy, and
+the second network pass that produces the density.  Inputs (positions are
+host data by the ABI; the B cache and outputs are preallocated in HBM) are
+in place before the timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import mala_synth  # noqa: E402
+
+METRIC = "grid points/s (bispectrum+MLP+LDOS reduce); p50/p99 snapshot latency"
+PEAK_FP32_VALU_TFLOPS = 157.3     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+WORKLOADS = {
+    "paper_solid": (mala_synth.paper_solid, mala_synth.paper_net),
+    "paper_liquid": (mala_synth.paper_liquid, mala_synth.paper_net),
+    "small": (mala_synth.small, mala_synth.small_net),
+    "slab": (mala_synth.slab, mala_synth.paper_net),
+}
+
+
+def index_counts(tj):
+    """Algorithmic term counts per grid point from the index sets."""
+    n_half = sum((J // 2 + 1) * (J + 1) for J in range(tj + 1))
+    z_terms = b_terms = 0
+    for j1 in range(tj + 1):
+        for j2 in range(j1 + 1):
+            for j in range(j1 - j2, min(tj, j1 + j2) + 1, 2):
+                if j < j1:
+                    continue
+                D, HR = (j1 + j2 - j) // 2, j // 2
+                b_terms += (HR + 1) * (j + 1)
+                for mb in range(j + 1):
+                    for mb1 in range(max(0, mb + D - j2), min(j1, mb + D) + 1):
+                        for ma in range(HR + 1):
+                            for ma1 in range(j1 + 1):
+                                if 0 <= ma - ma1 + D <= j2:
+                                    z_terms += 1
+    return n_half, z_terms, b_terms
+
+
+def mean_neighbours(snap, n_sample=4096, seed=99):
+    pts = mala_synth.sample_points(snap.n_points, n_sample, seed)
+    N, L = snap.N, snap.L
+    ijk = np.stack([pts // (N[1] * N[2]), (pts // N[2]) % N[1], pts % N[2]], 1)
+    r = ijk * (L / N)
+    nmax = np.ceil(snap.rcut / L).astype(int) + 1
+    shifts = np.array([[a, b, c] for a in range(-nmax[0], nmax[0] + 1)
+                       for b in range(-nmax[1], nmax[1] + 1) for c in range(-nmax[2], nmax[2] + 1)]) * L
+    tot = 0
+    for k in range(0, len(pts), 256):
+        d = snap.positions[None, :, None, :] + shifts[None, None, :, :] - r[k:k + 256, None, None, :]
+        tot += int(np.sum(np.einsum("pasx,pasx->pas", d, d) < snap.rcut ** 2))
+    return tot / len(pts)
+
+
+def flops_per_point(snap, widths):
+    n_half, z_terms, b_terms = index_counts(snap.twojmax)
+    nb = mean_neighbours(snap)
+    mlp = 2 * sum(widths[i] * widths[i + 1] for i in range(len(widths) - 1))
+    return {"u": 22.0 * n_half * nb, "zb": 10.0 * z_terms + 4.0 * b_terms, "mlp": float(mlp),
+            "mean_neighbours": nb, "z_terms": z_terms, "b_terms": b_terms, "n_half": n_half}
+
+
+def cpu_baseline(snap, net, n_sample):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    pts = mala_synth.sample_points(snap.n_points, n_sample, 1234)
+    t0 = time.time()
+    B = oracle.descriptors(snap, pts, nthreads=threads)
+    ld = oracle.mlp(B, net, nthreads=threads)
+    D = oracle.dos(ld, snap.dV) * (snap.n_points / n_sample)
+    fr = oracle.fermi(D, mala_synth.EGRID, snap.T, snap.n_electrons)
+    oracle.density(ld, fr["weights"])
+    dt = time.time() - t0
+    return {"value": n_sample / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded grid points of %s through the whole path (descriptors, network, DOS, "
+                      "E_F, E_band, density), %.1f s" % (n_sample, snap.name, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="paper_solid", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8192)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: the path shards by grid slabs with one 2 KB DOS all-reduce, "
+              "but multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_19617_amd as mala
+
+    mala.lib()
+    snap, net = WORKLOADS[a.workload][0](), WORKLOADS[a.workload][1]()
+    prec = mala.PREC_FP32 if a.precision == "fp32" else mala.PREC_BF16
+    ctx = mala.Context(0)
+    w = ctx.weights(mala_synth.net_to_blob(net), prec)
+    dev = torch.device("cuda", 0)
+    nB = mala.n_descriptors(snap.twojmax)
+    Bc = torch.empty((snap.n_points, nB), dtype=torch.float32, device=dev)
+    dos = torch.empty(mala_synth.EGRID[2], dtype=torch.float64, device=dev)
+    dens = torch.empty(snap.n_points, dtype=torch.float64, device=dev)
+    res = torch.zeros(mala.RESULT_BYTES, dtype=torch.uint8, device=dev)
+
+    def step():
+        ctx.mala_predict(w, snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, mala_synth.EGRID, snap.T,
+                         snap.n_electrons, B_cache=Bc, dos=dos, dens=dens, res=res)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.check_device_errors()
+    r = mala.read_result(res)
+    if r["status"] != 0:
+        raise RuntimeError("no Fermi level in warm-up: %s" % r)
+
+    ctx.profile_enable(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for k in range(a.steps):
+        step()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    elapsed = t1 - t0
+    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(a.steps)])
+    value = snap.n_points * a.steps / elapsed
+
+    fl = flops_per_point(snap, net["widths"])
+    zb_ms, zb_n, zb_pts = prof["zb"]
+    zb_avg_ms = zb_ms / max(zb_n, 1)
+    zb_flops_per_launch = fl["zb"] * zb_pts / max(zb_n, 1)
+    achieved = zb_flops_per_launch / (zb_avg_ms * 1e-3) / 1e12
+    stages = {k: {"ms_per_step": v[0] / a.steps, "launches_per_step": v[1] / a.steps}
+              for k, v in prof.items() if v[1]}
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1000.0 * elapsed / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == mala.PREC_FP32 else "bf16",
+        "data": "synthetic",
+        "config": {"workload": snap.name, "n_points": snap.n_points, "n_atoms": snap.n_atoms,
+                   "twojmax": snap.twojmax, "network": "-".join(map(str, net["widths"])),
+                   "network_precision": a.precision, "reductions": "f64", "T_K": snap.T,
+                   "n_electrons": snap.n_electrons},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "kind": "single snapshot, back-to-back"},
+        "roofline": {"kernel": "k_zb (Z/B contraction)", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "flops_per_point": fl["zb"], "points_per_launch": zb_pts / max(zb_n, 1),
+                     "avg_launch_ms": zb_avg_ms},
+        "stages": stages,
+        "algorithmic_kflop_per_point": {"u": fl["u"] / 1e3, "zb": fl["zb"] / 1e3, "mlp": fl["mlp"] / 1e3,
+                                        "mean_neighbours": fl["mean_neighbours"]},
+        "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(snap, net, a.cpu_sample)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

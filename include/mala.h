@@ -1,0 +1,187 @@
+/*
+ * mala.h -- C ABI of the MI355X (gfx950) grid-inference library.
+ *
+ * The library computes, for every point of a real-space grid around a
+ * periodic atomic snapshot, the path of the MALA method (arXiv:2411.19617):
+ *   bispectrum descriptors B(r, j)                 (Sec. 3.2.2, Eqs. ionicdensity,
+ *                                                   SNAPExpansion, snap_dim)
+ *   -> feed-forward network to the LDOS d(r, e)     (Sec. 2.4, Eq. ffnn)
+ *   -> DOS D(e) = integral of d over space          (Sec. 2.3, Eq. DOS.from.ldos)
+ *   -> Fermi level from N_e = int f D               (Sec. 3.4, Eq. NumberElectrons_from_DOS)
+ *   -> band energy E_b = int f e D                  (Sec. 2.3, Eq. band.energy)
+ *   -> density n(r) = int f d                       (Sec. 2.3, Eq. density.from.ldos)
+ * with the energy integrals done exactly for a piecewise-linear D through
+ * Fermi-Dirac weights (Sec. 3.4, Eqs. ldosintegralsummation, fermidiracspecial).
+ *
+ * Conventions shared by every call
+ *  - Units: Angstrom, eV, Kelvin; k_B = 8.617333262e-5 eV/K.  LDOS in
+ *    1/(eV A^3), DOS in 1/eV, density in 1/A^3.
+ *  - Cell: orthorhombic, edges L[3]; grid N[3]; point (i,j,k) sits at
+ *    (i Lx/Nx, j Ly/Ny, k Lz/Nz) and has flat index p = (i*Ny + j)*Nz + k.
+ *  - Descriptor order: for j1 = 0..twojmax, j2 = 0..j1, j = j1-j2 .. min(twojmax,
+ *    j1+j2) step 2, keep j >= j1 (all doubled); n_B = mala_n_descriptors(twojmax).
+ *  - Neighbours: every periodic image within rcut; cosine cutoff
+ *    f_c = (cos(pi r/rcut)+1)/2; theta0 = 0.99363 pi r/rcut; self weight 1.
+ *  - Buffers named "device" are device pointers (hipMalloc'd or torch CUDA
+ *    tensors) owned by the caller; "host" pointers are ordinary host memory
+ *    that is read before the call returns.  The library owns contexts and
+ *    weights and the scratch memory inside a context.
+ *  - Every compute call is asynchronous on the context's stream; outputs are
+ *    valid after the stream has been synchronised.  Calls on one context
+ *    must not overlap (they share its scratch).
+ *  - Errors: a negative status; mala_last_error() gives a message for the
+ *    calling thread.  Nothing is thrown across the ABI.  Argument errors are
+ *    detected before any work is enqueued.  Capacity overflows found on the
+ *    device (too many neighbours of one point) are reported by the next
+ *    call of mala_check_device_errors().
+ */
+#ifndef MALA_H
+#define MALA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mala_status;
+#define MALA_OK 0
+#define MALA_E_INVALID_ARG (-1)  /* bad pointer, size, or parameter            */
+#define MALA_E_UNSUPPORTED (-2)  /* valid but outside this build (e.g. twojmax) */
+#define MALA_E_OOM (-3)          /* device allocation failed                   */
+#define MALA_E_NO_ROOT (-4)      /* N_e outside [N(e_0), N(e_last)]            */
+#define MALA_E_HIP (-5)          /* a HIP runtime call failed                  */
+#define MALA_E_BUSY (-6)         /* serving: result not ready yet              */
+#define MALA_E_CAPACITY (-7)     /* a fixed per-tile capacity was exceeded      */
+
+#define MALA_PREC_FP32 0         /* network in FP32 on MFMA                    */
+#define MALA_PREC_BF16 1         /* network in BF16 on MFMA, FP32 accumulate    */
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* mala_last_error(void);
+const char* mala_version(void);
+
+/* Number of bispectrum components for twojmax (Eq. snap_dim with J_max =
+ * twojmax/2): (twojmax+2)(twojmax+3)(twojmax+4)/24.  -1 if twojmax < 0.     */
+int32_t mala_n_descriptors(int32_t twojmax);
+
+/* ---------------------------------------------------------------- context */
+typedef struct mala_ctx mala_ctx;
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a
+ * hipStream_t; NULL = the legacy default stream).  *out receives the handle. */
+mala_status mala_create(int32_t device, void* stream, mala_ctx** out);
+mala_status mala_destroy(mala_ctx* ctx);
+mala_status mala_set_stream(mala_ctx* ctx, void* stream);
+/* Blocks until the context's stream is idle. */
+mala_status mala_synchronize(mala_ctx* ctx);
+/* Synchronises, then returns MALA_E_CAPACITY if any kernel since the last
+ * check flagged a capacity overflow (and clears the flag), else MALA_OK.    */
+mala_status mala_check_device_errors(mala_ctx* ctx);
+
+/* ---------------------------------------------------------------- weights
+ * Weights blob (little endian, as written by the input generator):
+ *   char     magic[8] = "MALANET1"
+ *   int32    version (=1), n_layers, output_activation (1 = activation also on
+ *            the output layer, as in Eq. ffnn; 0 = identity), reserved
+ *   float64  leaky_slope                 (LeakyReLU negative slope)
+ *   int32    widths[n_layers+1], padded with one int32 if n_layers+1 is odd
+ *   float64  in_mean[w0], in_std[w0]     (x0 = (B - mean)/std)
+ *   per layer l: float64 W[w(l+1)][w(l)] row-major, float64 b[w(l+1)]
+ *   float64  out_scale[wL], out_shift[wL] (LDOS = out_scale*y + out_shift)
+ *   uint64   seed
+ * This build supports n_layers = 3, w0 <= 128, hidden widths <= 512 and
+ * wL <= 256.  The blob is copied; the caller may free it after the call.
+ * Weights live on the context's device but do not depend on the context
+ * afterwards; mala_weights_free synchronises that device before freeing.    */
+typedef struct mala_weights mala_weights;
+mala_status mala_weights_load(mala_ctx* ctx, const void* blob, size_t bytes,
+                              int32_t precision, mala_weights** out);
+mala_status mala_weights_free(mala_weights* w);
+
+typedef struct {
+    double L[3];      /* orthorhombic cell edges, Angstrom */
+    int32_t N[3];     /* grid points per edge              */
+} mala_cell_grid;
+
+typedef struct {
+    double e0;        /* first energy, eV   */
+    double de;        /* spacing, eV (> 0)  */
+    int32_t n;        /* number of energies */
+} mala_egrid;
+
+/* Device-resident result record written by mala_integrate / mala_predict. */
+typedef struct {
+    double e_fermi;       /* eV                                   */
+    double e_band;        /* eV (total; divide by N_atoms for per-atom) */
+    double n_found;       /* N(E_F) from the weights              */
+    double n_target;      /* requested N_e                        */
+    int32_t iterations;   /* bisection steps                      */
+    int32_t status;       /* MALA_OK or MALA_E_NO_ROOT            */
+    int32_t reserved[2];
+} mala_result;
+
+/* ---------------------------------------------------------------- compute */
+
+/* Bispectrum descriptors (Sec. 3.2.2) of grid points [pt_begin, pt_end).
+ *  positions: host float64 [n_atoms][3] (any values; wrapped into the cell)
+ *  rcut > 0; twojmax in {2, 4, 6, 8, 10}
+ *  B_out: device float32 [pt_end - pt_begin][n_B], row = point.
+ * Empty ranges are a no-op.                                                  */
+mala_status mala_descriptors(mala_ctx* ctx, const double* positions, int32_t n_atoms,
+                             const mala_cell_grid* cg, double rcut, int32_t twojmax,
+                             int64_t pt_begin, int64_t pt_end, float* B_out);
+
+/* LDOS of n_pts points through the network (Eq. ffnn) and the output
+ * transform.  B: device float32 [n_pts][w0]; ldos_out: device float32
+ * [n_pts][wL].                                                                */
+mala_status mala_ldos_infer(mala_ctx* ctx, const mala_weights* w, const float* B,
+                            int64_t n_pts, float* ldos_out);
+
+/* Observables from a stored LDOS (Sec. 3.4).
+ *  ldos: device float32 [n_pts][eg->n]; dV = cell volume / N_points;
+ *  T_kelvin > 0; n_electrons > 0.
+ *  dos_out: device float64 [eg->n]; density_out: device float64 [n_pts] or
+ *  NULL; result: device mala_result.  If N_e has no root, result->status is
+ *  MALA_E_NO_ROOT, E_F/E_b are NaN and the density is not written.          */
+mala_status mala_integrate(mala_ctx* ctx, const float* ldos, int64_t n_pts, double dV,
+                           const mala_egrid* eg, double T_kelvin, double n_electrons,
+                           double* dos_out, double* density_out, mala_result* result);
+
+/* Whole path, fused: descriptors of every grid point (cached as B in
+ * device memory), network with the DOS reduced in the epilogue (the LDOS is
+ * never stored), Fermi level, band energy, then a second network pass whose
+ * epilogue contracts the LDOS with the Fermi weights into the density.
+ *  B_cache: device float32 [N_points][n_B] or NULL (then context scratch).
+ *  Outputs as in mala_integrate; density_out may be NULL.                   */
+mala_status mala_predict(mala_ctx* ctx, const mala_weights* w, const double* positions,
+                         int32_t n_atoms, const mala_cell_grid* cg, double rcut,
+                         int32_t twojmax, const mala_egrid* eg, double T_kelvin,
+                         double n_electrons, double* dos_out, double* density_out,
+                         mala_result* result, float* B_cache);
+
+/* ---------------------------------------------------------------- timing
+ * Per-stage instrumentation (the method's cost breakdown by stage): while
+ * enabled, every kernel group is bracketed by HIP events recorded on the
+ * context stream (no synchronisation is added).  mala_profile_read()
+ * synchronises the stream and returns, per stage, the summed event time in
+ * milliseconds, the number of launches and the grid points they processed.
+ * Enabling (on != 0) resets the accumulators.                               */
+#define MALA_STAGE_BIN 0          /* atom cell list                          */
+#define MALA_STAGE_UI 1           /* neighbour gather + u expansion          */
+#define MALA_STAGE_ZB 2           /* Z/B contraction (bispectrum)            */
+#define MALA_STAGE_MLP_LDOS 3     /* network, LDOS stored                    */
+#define MALA_STAGE_MLP_DOS 4      /* network, DOS reduced in the epilogue    */
+#define MALA_STAGE_FERMI 5        /* DOS sum, E_F bisection, E_band, weights */
+#define MALA_STAGE_MLP_DENSITY 6  /* network, density in the epilogue        */
+#define MALA_STAGE_INTEGRATE 7    /* stored-LDOS column sums and density     */
+#define MALA_N_STAGES 8
+mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
+mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MALA_H */

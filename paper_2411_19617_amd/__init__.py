@@ -1,0 +1,248 @@
+"""Python binding of the gfx950 grid-inference library (include/mala.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libmala.so``.  PyTorch supplies device memory and the stream; the
+functions below take and return torch CUDA tensors.  If the library has not
+been built (``python -m paper_2411_19617_amd.build``) or no GPU is present,
+loading fails with an error -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmala.so")
+
+MALA_OK = 0
+MALA_E_INVALID_ARG = -1
+MALA_E_UNSUPPORTED = -2
+MALA_E_OOM = -3
+MALA_E_NO_ROOT = -4
+MALA_E_HIP = -5
+MALA_E_BUSY = -6
+MALA_E_CAPACITY = -7
+PREC_FP32 = 0
+PREC_BF16 = 1
+RESULT_BYTES = 48
+STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate"]
+
+_lib = None
+
+
+class MalaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("mala status %d: %s" % (status, msg))
+        self.status = status
+
+
+class CellGrid(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("N", ctypes.c_int32 * 3)]
+
+
+class EGrid(ctypes.Structure):
+    _fields_ = [("e0", ctypes.c_double), ("de", ctypes.c_double), ("n", ctypes.c_int32)]
+
+
+def lib():
+    """Load libmala.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmala.so not built; run python -m paper_2411_19617_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i32, i64, d, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        L.mala_last_error.restype = ctypes.c_char_p
+        L.mala_version.restype = ctypes.c_char_p
+        L.mala_n_descriptors.restype = i32
+        L.mala_n_descriptors.argtypes = [i32]
+        for name, args in [
+            ("mala_create", [i32, p, ctypes.POINTER(p)]),
+            ("mala_destroy", [p]),
+            ("mala_set_stream", [p, p]),
+            ("mala_synchronize", [p]),
+            ("mala_check_device_errors", [p]),
+            ("mala_weights_load", [p, p, sz, i32, ctypes.POINTER(p)]),
+            ("mala_weights_free", [p]),
+            ("mala_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p]),
+            ("mala_ldos_infer", [p, p, p, i64, p]),
+            ("mala_integrate", [p, p, i64, d, ctypes.POINTER(EGrid), d, d, p, p, p]),
+            ("mala_predict", [p, p, p, i32, ctypes.POINTER(CellGrid), d, i32, ctypes.POINTER(EGrid), d, d,
+                              p, p, p, p]),
+            ("mala_profile_enable", [p, i32]),
+            ("mala_profile_read", [p, p, p, p]),
+        ]:
+            fn = getattr(L, name)
+            fn.restype = i32
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def n_descriptors(twojmax):
+    return int(lib().mala_n_descriptors(int(twojmax)))
+
+
+def _check(st):
+    if st != MALA_OK:
+        raise MalaError(st, lib().mala_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _cell_grid(L, N):
+    cg = CellGrid()
+    for k in range(3):
+        cg.L[k] = float(L[k])
+        cg.N[k] = int(N[k])
+    return cg
+
+
+def _egrid(egrid):
+    e = EGrid()
+    e.e0, e.de, e.n = float(egrid[0]), float(egrid[1]), int(egrid[2])
+    return e
+
+
+def _positions(pos):
+    a = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+    return a, a.ctypes.data_as(ctypes.c_void_p), a.shape[0]
+
+
+def read_result(res):
+    """Decode a device mala_result (uint8 tensor of 48 bytes); synchronises."""
+    raw = res.cpu().numpy().tobytes()
+    d = np.frombuffer(raw[:32], dtype="<f8")
+    i = np.frombuffer(raw[32:40], dtype="<i4")
+    return {"e_fermi": float(d[0]), "e_band": float(d[1]), "n_found": float(d[2]),
+            "n_target": float(d[3]), "iterations": int(i[0]), "status": int(i[1])}
+
+
+class Weights:
+    def __init__(self, ctx, blob, precision):
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().mala_weights_load(ctx.handle, buf, len(blob), int(precision), ctypes.byref(h)))
+        self.handle = h
+        self.precision = precision
+
+    def free(self):
+        if self.handle:
+            lib().mala_weights_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context on one device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device=0):
+        import torch
+        self.device = int(device)
+        self.torch_device = torch.device("cuda", self.device)
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _check(lib().mala_create(self.device, _stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().mala_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().mala_set_stream(self.handle, _stream()))
+
+    def synchronize(self):
+        _check(lib().mala_synchronize(self.handle))
+
+    def check_device_errors(self):
+        _check(lib().mala_check_device_errors(self.handle))
+
+    def profile_enable(self, on=True):
+        _check(lib().mala_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self):
+        """Per stage: (milliseconds, launches, grid points) from the stage events."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        nl = (ctypes.c_int64 * n)()
+        npt = (ctypes.c_int64 * n)()
+        _check(lib().mala_profile_read(self.handle, ms, nl, npt))
+        return {STAGES[i]: (ms[i], nl[i], npt[i]) for i in range(n)}
+
+    def weights(self, blob, precision=PREC_FP32):
+        return Weights(self, blob, precision)
+
+    # -- the three calls of the method's problem statement, plus the fused path
+    def mala_descriptors(self, positions, L, N, rcut, twojmax, pt_begin=0, pt_end=None, out=None):
+        import torch
+        self._sync_stream()
+        pos, pp, n_at = _positions(positions)
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        pt_end = ntot if pt_end is None else int(pt_end)
+        nB = n_descriptors(twojmax)
+        if out is None:
+            out = torch.empty((max(pt_end - pt_begin, 0), nB), dtype=torch.float32, device=self.torch_device)
+        cg = _cell_grid(L, N)
+        _check(lib().mala_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(twojmax),
+                                      int(pt_begin), int(pt_end), _ptr(out)))
+        return out
+
+    def mala_ldos_infer(self, weights, B, n_out, out=None):
+        import torch
+        self._sync_stream()
+        n = int(B.shape[0])
+        if out is None:
+            out = torch.empty((n, n_out), dtype=torch.float32, device=self.torch_device)
+        _check(lib().mala_ldos_infer(self.handle, weights.handle, _ptr(B), n, _ptr(out)))
+        return out
+
+    def mala_integrate(self, ldos, dV, egrid, T, n_electrons, density=True):
+        import torch
+        self._sync_stream()
+        n = int(ldos.shape[0])
+        eg = _egrid(egrid)
+        dos = torch.empty(int(egrid[2]), dtype=torch.float64, device=self.torch_device)
+        dens = torch.empty(n, dtype=torch.float64, device=self.torch_device) if density else None
+        res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=self.torch_device)
+        _check(lib().mala_integrate(self.handle, _ptr(ldos), n, float(dV), ctypes.byref(eg), float(T),
+                                    float(n_electrons), _ptr(dos), _ptr(dens), _ptr(res)))
+        return dos, dens, res
+
+    def mala_predict(self, weights, positions, L, N, rcut, twojmax, egrid, T, n_electrons, density=True,
+                     B_cache=None, dos=None, dens=None, res=None):
+        import torch
+        self._sync_stream()
+        pos, pp, n_at = _positions(positions)
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        cg = _cell_grid(L, N)
+        eg = _egrid(egrid)
+        if dos is None:
+            dos = torch.empty(int(egrid[2]), dtype=torch.float64, device=self.torch_device)
+        if density and dens is None:
+            dens = torch.empty(ntot, dtype=torch.float64, device=self.torch_device)
+        if res is None:
+            res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=self.torch_device)
+        _check(lib().mala_predict(self.handle, weights.handle, pp, n_at, ctypes.byref(cg), float(rcut),
+                                  int(twojmax), ctypes.byref(eg), float(T), float(n_electrons), _ptr(dos),
+                                  _ptr(dens if density else None), _ptr(res), _ptr(B_cache)))
+        return dos, (dens if density else None), res

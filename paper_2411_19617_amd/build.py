@@ -1,0 +1,74 @@
+"""Build the gfx950 shared library libmala.so in-tree with hipcc.
+
+    python -m paper_2411_19617_amd.build [--jobs N]
+
+Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
+selection disabled (some packed forms are not trusted on this hardware).
+Objects go to paper_2411_19617_amd/_build/, the library to
+paper_2411_19617_amd/libmala.so.
+"""
+import argparse
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libmala.so")
+SOURCES = ["api.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "mlp.hip", "fermi.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
+def _stale(path, obj):
+    if not os.path.exists(obj):
+        return True
+    deps = [path, os.path.join(CSRC, "mala_internal.h"), os.path.join(ROOT, "include", "mala.h")]
+    return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
+
+
+def _compile(src, incremental=False):
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(OUT_DIR, src + ".o")
+    if incremental and not _stale(path, obj):
+        return obj
+    cmd = [HIPCC] + COMMON + (["-x", "hip"] if src.endswith(".hip") else []) + ["-c", path, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    return obj
+
+
+def build(jobs=None, verbose=False, incremental=False):
+    """Compile every source (or only stale ones with incremental=True) and link."""
+    os.makedirs(OUT_DIR, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true", help="recompile only stale objects")
+    a = ap.parse_args()
+    try:
+        build(a.jobs, verbose=True, incremental=a.incremental)
+    except RuntimeError as e:
+        print(e, file=sys.stderr)
+        sys.exit(1)

@@ -1,0 +1,625 @@
+// C ABI of the gfx950 grid-inference library: argument checks, scratch
+// management, weight packing and launch sequencing.  All arithmetic of the
+// path runs in the HIP kernels of this directory.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "mala.h"
+#include "mala_internal.h"
+
+using namespace mala;
+
+namespace {
+
+thread_local std::string g_err;
+
+mala_status fail(mala_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? MALA_E_OOM : MALA_E_HIP,             \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t cap = 0;   // elements
+};
+
+template <typename T>
+hipError_t ensure(DevBuf<T>& b, size_t n) {
+    if (n <= b.cap) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);    // synchronising: no kernel still uses it
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = n + n / 8 + 64;
+    hipError_t e = hipMalloc(&b.p, want * sizeof(T));
+    if (e != hipSuccess) return e;
+    b.cap = want;
+    return hipSuccess;
+}
+
+template <typename T>
+void release(DevBuf<T>& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+struct TjTables {
+    bool ready = false;
+    float* cg = nullptr;
+    int* cg_off = nullptr;
+    int* waves = nullptr;
+    int zb_waves = 0;
+};
+
+constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
+
+}  // namespace
+
+struct mala_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf<double> pos;
+    double* pos_stage = nullptr;         // pinned staging for positions
+    size_t pos_stage_cap = 0;
+    hipEvent_t stage_ev = nullptr;
+    DevBuf<int> cell_count, cell_start, cell_fill, atom_cell;
+    DevBuf<double4> atoms_tmp, atoms_sorted;
+    DevBuf<float2> u;
+    DevBuf<float> Bbuf;
+    DevBuf<double> partials;
+    DevBuf<double> fermi_w;
+    int* err = nullptr;
+    double* li_coef = nullptr;
+    TjTables tj[kMaxTwojmax + 1];
+    // stage timing
+    bool prof_on = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+        int64_t pts;
+    };
+    std::vector<Rec> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[MALA_N_STAGES] = {};
+    int64_t prof_n[MALA_N_STAGES] = {}, prof_pts[MALA_N_STAGES] = {};
+};
+
+struct mala_weights {
+    int device = 0;
+    MlpArgs args{};
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+hipEvent_t pool_event(mala_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` as one stage; with timing on, bracket it with events.
+template <typename F>
+hipError_t staged(mala_ctx* c, int stage, int64_t pts, F&& fn) {
+    if (!c->prof_on) return fn();
+    hipEvent_t a = pool_event(c), b = pool_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, c->stream);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    c->prof_pending.push_back({stage, a, b, pts});
+    return e;
+}
+
+mala_status ensure_tables(mala_ctx* c, int tj) {
+    TjTables& t = c->tj[tj];
+    if (t.ready) return MALA_OK;
+    std::vector<float> tab(32768);
+    std::vector<int> off(n_triples(tj));
+    int n = build_cg_table(tj, tab.data(), off.data(), (int)tab.size());
+    if (n < 0) return fail(MALA_E_UNSUPPORTED, "Clebsch-Gordan table too large");
+    t.zb_waves = tj >= 10 ? 16 : 8;
+    std::vector<int> waves(t.zb_waves * kMaxZbStride, 0);
+    plan_zb_waves(tj, t.zb_waves, waves.data(), kMaxZbStride);
+    HIP_TRY(hipMalloc(&t.cg, sizeof(float) * (n > 0 ? n : 1)));
+    HIP_TRY(hipMalloc(&t.cg_off, sizeof(int) * off.size()));
+    HIP_TRY(hipMalloc(&t.waves, sizeof(int) * waves.size()));
+    HIP_TRY(hipMemcpy(t.cg, tab.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.cg_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.waves, waves.data(), sizeof(int) * waves.size(), hipMemcpyHostToDevice));
+    t.ready = true;
+    return MALA_OK;
+}
+
+bool finite3(const double* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+mala_status check_geometry(const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
+                           double rcut, int32_t twojmax) {
+    if (!cg) return fail(MALA_E_INVALID_ARG, "cell_grid is NULL");
+    if (n_atoms < 0) return fail(MALA_E_INVALID_ARG, "n_atoms < 0");
+    if (n_atoms > 0 && !positions) return fail(MALA_E_INVALID_ARG, "positions is NULL");
+    for (int d = 0; d < 3; ++d) {
+        if (!(cg->L[d] > 0.0) || !isfinite(cg->L[d])) return fail(MALA_E_INVALID_ARG, "cell edge not positive");
+        if (cg->N[d] < 1) return fail(MALA_E_INVALID_ARG, "grid size < 1");
+    }
+    if (!(rcut > 0.0) || !isfinite(rcut)) return fail(MALA_E_INVALID_ARG, "rcut not positive");
+    if (twojmax < 2 || twojmax > kMaxTwojmax || (twojmax & 1))
+        return fail(MALA_E_UNSUPPORTED, "twojmax must be one of 2, 4, 6, 8, 10");
+    for (int i = 0; i < n_atoms; ++i)
+        if (!finite3(positions + 3 * i)) return fail(MALA_E_INVALID_ARG, "non-finite atom position");
+    return MALA_OK;
+}
+
+mala_status upload_positions(mala_ctx* c, const double* positions, int32_t n_atoms) {
+    const size_t n = (size_t)3 * (n_atoms > 0 ? n_atoms : 1);
+    HIP_TRY(ensure(c->pos, n));
+    if (n_atoms == 0) return MALA_OK;
+    HIP_TRY(hipEventSynchronize(c->stage_ev));          // previous copy out of the stage is done
+    if (c->pos_stage_cap < n) {
+        if (c->pos_stage) HIP_TRY(hipHostFree(c->pos_stage));
+        c->pos_stage = nullptr;
+        HIP_TRY(hipHostMalloc(&c->pos_stage, sizeof(double) * n, hipHostMallocDefault));
+        c->pos_stage_cap = n;
+    }
+    memcpy(c->pos_stage, positions, sizeof(double) * 3 * n_atoms);
+    HIP_TRY(hipMemcpyAsync(c->pos.p, c->pos_stage, sizeof(double) * 3 * n_atoms, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipEventRecord(c->stage_ev, c->stream));
+    return MALA_OK;
+}
+
+mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut,
+                            int32_t twojmax, int64_t pt_begin, int64_t pt_end, float* B_out) {
+    BinState bs{};
+    int nc_est = 1;
+    for (int d = 0; d < 3; ++d) {
+        int nc = (int)floor(cg->L[d] / (0.5 * rcut));
+        nc = nc < 1 ? 1 : (nc > 256 ? 256 : nc);
+        nc_est *= nc;
+    }
+    const size_t na = n_atoms > 0 ? n_atoms : 1;
+    HIP_TRY(ensure(c->cell_count, nc_est + 1));
+    HIP_TRY(ensure(c->cell_start, nc_est + 1));
+    HIP_TRY(ensure(c->cell_fill, nc_est + 1));
+    HIP_TRY(ensure(c->atom_cell, na));
+    HIP_TRY(ensure(c->atoms_tmp, na));
+    HIP_TRY(ensure(c->atoms_sorted, na));
+    HIP_TRY(staged(c, MALA_STAGE_BIN, 0, [&] {
+        return launch_bin(c->stream, c->pos.p, n_atoms, cg->L, rcut, c->cell_count.p, c->cell_start.p,
+                          c->cell_fill.p, c->atoms_tmp.p, c->atom_cell.p, c->atoms_sorted.p, &bs);
+    }));
+    const int nB = n_triples(twojmax);
+    const int64_t total = pt_end - pt_begin;
+    const int64_t chunk = total < kChunk ? total : kChunk;
+    const int64_t tiles = (chunk + kTile - 1) / kTile;
+    HIP_TRY(ensure(c->u, (size_t)tiles * n_half(twojmax) * kTile));
+    const TjTables& t = c->tj[twojmax];
+    for (int64_t off = 0; off < total; off += chunk) {
+        const int64_t n = (total - off) < chunk ? (total - off) : chunk;
+        HIP_TRY(staged(c, MALA_STAGE_UI, n, [&] {
+            return launch_ui(c->stream, twojmax, bs, cg->N, rcut, pt_begin + off, n, c->u.p, c->err);
+        }));
+        HIP_TRY(staged(c, MALA_STAGE_ZB, n, [&] {
+            return launch_zb(c->stream, twojmax, n, c->u.p, B_out + off * nB, t.cg, t.cg_off, t.waves,
+                             t.zb_waves);
+        }));
+    }
+    return MALA_OK;
+}
+
+mala_status check_egrid(const mala_egrid* eg, double T, double ne) {
+    if (!eg) return fail(MALA_E_INVALID_ARG, "egrid is NULL");
+    if (eg->n < 2 || eg->n > kMlpMaxOut) return fail(MALA_E_UNSUPPORTED, "energy grid size must be 2..256");
+    if (!(eg->de > 0.0) || !isfinite(eg->de) || !isfinite(eg->e0))
+        return fail(MALA_E_INVALID_ARG, "bad energy grid");
+    if (!(T > 0.0) || !isfinite(T)) return fail(MALA_E_INVALID_ARG, "temperature must be positive");
+    if (!(ne > 0.0) || !isfinite(ne)) return fail(MALA_E_INVALID_ARG, "n_electrons must be positive");
+    return MALA_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* mala_last_error(void) { return g_err.c_str(); }
+const char* mala_version(void) { return "mala-gfx950 0.1.0"; }
+
+int32_t mala_n_descriptors(int32_t twojmax) {
+    if (twojmax < 0) return -1;
+    return (twojmax + 2) * (twojmax + 3) * (twojmax + 4) / 24;
+}
+
+mala_status mala_create(int32_t device, void* stream, mala_ctx** out) {
+    if (!out) return fail(MALA_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(MALA_E_INVALID_ARG, "no such device");
+    DeviceGuard g(device);
+    mala_ctx* c = new mala_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&c->err, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(c->err, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->li_coef, sizeof(double) * 2 * kLiTerms);
+    if (e == hipSuccess) {
+        double coef[2 * kLiTerms];
+        polylog_coefficients(coef);
+        e = hipMemcpy(c->li_coef, coef, sizeof(coef), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->stage_ev, c->stream);
+    if (e != hipSuccess) {
+        mala_destroy(c);
+        return fail(MALA_E_HIP, std::string("context setup: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return MALA_OK;
+}
+
+mala_status mala_destroy(mala_ctx* c) {
+    if (!c) return MALA_OK;
+    DeviceGuard g(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    release(c->pos);
+    release(c->cell_count);
+    release(c->cell_start);
+    release(c->cell_fill);
+    release(c->atom_cell);
+    release(c->atoms_tmp);
+    release(c->atoms_sorted);
+    release(c->u);
+    release(c->Bbuf);
+    release(c->partials);
+    release(c->fermi_w);
+    if (c->pos_stage) (void)hipHostFree(c->pos_stage);
+    if (c->err) (void)hipFree(c->err);
+    if (c->li_coef) (void)hipFree(c->li_coef);
+    for (auto& t : c->tj) {
+        if (t.cg) (void)hipFree(t.cg);
+        if (t.cg_off) (void)hipFree(t.cg_off);
+        if (t.waves) (void)hipFree(t.waves);
+    }
+    if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+    for (auto& r : c->prof_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+    return MALA_OK;
+}
+
+mala_status mala_set_stream(mala_ctx* c, void* stream) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    c->stream = static_cast<hipStream_t>(stream);
+    return MALA_OK;
+}
+
+mala_status mala_synchronize(mala_ctx* c) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MALA_OK;
+}
+
+mala_status mala_check_device_errors(mala_ctx* c) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, c->err, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(c->err, 0, sizeof(int)));
+    if (flag & kErrCand) return fail(MALA_E_CAPACITY, "more than 1024 atom images near one 64-point tile");
+    if (flag & kErrNbr) return fail(MALA_E_CAPACITY, "more than 128 neighbours within rcut of a grid point");
+    return MALA_OK;
+}
+
+mala_status mala_profile_enable(mala_ctx* c, int32_t on) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    DeviceGuard g(c->device);
+    if (on) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (auto& r : c->prof_pending) {
+            c->ev_pool.push_back(r.a);
+            c->ev_pool.push_back(r.b);
+        }
+        c->prof_pending.clear();
+        for (int i = 0; i < MALA_N_STAGES; ++i) {
+            c->prof_ms[i] = 0.0;
+            c->prof_n[i] = c->prof_pts[i] = 0;
+        }
+    }
+    c->prof_on = on != 0;
+    return MALA_OK;
+}
+
+mala_status mala_profile_read(mala_ctx* c, double* ms, int64_t* launches, int64_t* points) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& r : c->prof_pending) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        c->prof_ms[r.stage] += t;
+        c->prof_n[r.stage] += 1;
+        c->prof_pts[r.stage] += r.pts;
+        c->ev_pool.push_back(r.a);
+        c->ev_pool.push_back(r.b);
+    }
+    c->prof_pending.clear();
+    for (int i = 0; i < MALA_N_STAGES; ++i) {
+        if (ms) ms[i] = c->prof_ms[i];
+        if (launches) launches[i] = c->prof_n[i];
+        if (points) points[i] = c->prof_pts[i];
+    }
+    return MALA_OK;
+}
+
+// ---------------------------------------------------------------- weights
+mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32_t precision,
+                              mala_weights** out) {
+    if (!c || !blob || !out) return fail(MALA_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (precision != MALA_PREC_FP32 && precision != MALA_PREC_BF16)
+        return fail(MALA_E_INVALID_ARG, "unknown precision");
+    const unsigned char* b = static_cast<const unsigned char*>(blob);
+    size_t pos = 0;
+    auto take = [&](void* dst, size_t n) {
+        if (pos + n > bytes) return false;
+        memcpy(dst, b + pos, n);
+        pos += n;
+        return true;
+    };
+    char magic[8];
+    int32_t hdr[4];
+    double slope;
+    if (!take(magic, 8) || memcmp(magic, "MALANET1", 8) != 0) return fail(MALA_E_INVALID_ARG, "bad blob magic");
+    if (!take(hdr, sizeof(hdr)) || hdr[0] != 1) return fail(MALA_E_INVALID_ARG, "bad blob version");
+    const int nl = hdr[1], out_act = hdr[2];
+    if (nl != 3) return fail(MALA_E_UNSUPPORTED, "only networks with 3 affine layers are supported");
+    if (!take(&slope, 8) || !isfinite(slope)) return fail(MALA_E_INVALID_ARG, "bad slope");
+    int32_t wid[4];
+    if (!take(wid, sizeof(int32_t) * 4)) return fail(MALA_E_INVALID_ARG, "truncated blob");
+    // 4 widths: (nl+1) even, no padding int
+    for (int i = 0; i < 4; ++i)
+        if (wid[i] < 1) return fail(MALA_E_INVALID_ARG, "bad layer width");
+    const int n_in = wid[0], h1 = wid[1], h2 = wid[2], n_out = wid[3];
+    if (n_in > kMlpMaxIn || h1 > kMlpMaxHidden || h2 > kMlpMaxHidden || n_out > kMlpMaxOut)
+        return fail(MALA_E_UNSUPPORTED, "layer width beyond this build's limits");
+    std::vector<double> mean(n_in), sd(n_in), W1((size_t)h1 * n_in), b1(h1), W2((size_t)h2 * h1), b2(h2),
+        W3((size_t)n_out * h2), b3(n_out), osc(n_out), osh(n_out);
+    bool ok = take(mean.data(), 8 * n_in) && take(sd.data(), 8 * n_in) && take(W1.data(), 8 * W1.size()) &&
+              take(b1.data(), 8 * h1) && take(W2.data(), 8 * W2.size()) && take(b2.data(), 8 * h2) &&
+              take(W3.data(), 8 * W3.size()) && take(b3.data(), 8 * n_out) && take(osc.data(), 8 * n_out) &&
+              take(osh.data(), 8 * n_out);
+    if (!ok) return fail(MALA_E_INVALID_ARG, "truncated blob");
+    for (double v : sd)
+        if (!(v > 0.0) || !isfinite(v)) return fail(MALA_E_INVALID_ARG, "input std must be positive");
+
+    // padded shape for the precision: K multiple of the MFMA K (4 or 32)
+    const bool bf = precision == MALA_PREC_BF16;
+    auto ceil_div = [](int a, int b) { return (a + b - 1) / b; };
+    const int KK = bf ? 32 : 4;
+    const int in_pad = KK * ceil_div(n_in, KK);
+    const int h1t = bf ? 2 * ceil_div(h1, 32) : ceil_div(h1, 16);
+    const int h2t = bf ? 2 * ceil_div(h2, 32) : ceil_div(h2, 16);
+    const int ot = ceil_div(n_out, 16);
+    const int KS1 = in_pad / KK, KS2 = h1t * 16 / KK, KS3 = h2t * 16 / KK;
+    // A operand of MFMA tile (mt, s): lane l holds row 16 mt + l%16 and
+    // k = KK s + (l/16) * (KK/4) + q, q < KK/4 (natural K order).
+    auto pack = [&](const std::vector<double>& W, int fout, int fin, int mtiles, int ks, std::vector<float>& o) {
+        const int per = KK / 4;
+        o.assign((size_t)mtiles * ks * 64 * per, 0.f);
+        for (int mt = 0; mt < mtiles; ++mt)
+            for (int s = 0; s < ks; ++s)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int q = 0; q < per; ++q) {
+                        const int row = 16 * mt + (lane & 15);
+                        const int k = KK * s + (lane >> 4) * per + q;
+                        float v = 0.f;
+                        if (row < fout && k < fin) v = (float)W[(size_t)row * fin + k];
+                        o[(((size_t)mt * ks + s) * 64 + lane) * per + q] = v;
+                    }
+    };
+    std::vector<float> P1, P2, P3;
+    pack(W1, h1, n_in, h1t, KS1, P1);
+    pack(W2, h2, h1, h2t, KS2, P2);
+    pack(W3, n_out, h2, ot, KS3, P3);
+    auto padv = [](const std::vector<double>& v, int n) {
+        std::vector<float> o(n, 0.f);
+        for (size_t i = 0; i < v.size() && (int)i < n; ++i) o[i] = (float)v[i];
+        return o;
+    };
+    std::vector<float> pb1 = padv(b1, 16 * h1t), pb2 = padv(b2, 16 * h2t), pb3 = padv(b3, 16 * ot);
+    std::vector<float> pm = padv(mean, n_in), prs(n_in), psc = padv(osc, kMlpMaxOut), psh = padv(osh, kMlpMaxOut);
+    for (int i = 0; i < n_in; ++i) prs[i] = (float)(1.0 / sd[i]);
+
+    DeviceGuard g(c->device);
+    mala_weights* w = new mala_weights();
+    w->device = c->device;
+    auto upload_f = [&](const std::vector<float>& v) -> void* {
+        void* d = nullptr;
+        if (hipMalloc(&d, sizeof(float) * (v.size() ? v.size() : 1)) != hipSuccess) return nullptr;
+        w->allocs.push_back(d);
+        if (hipMemcpy(d, v.data(), sizeof(float) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        return d;
+    };
+    auto upload_bf = [&](const std::vector<float>& v) -> void* {
+        std::vector<uint16_t> h(v.size());
+        for (size_t i = 0; i < v.size(); ++i) {   // round to nearest even
+            uint32_t x;
+            memcpy(&x, &v[i], 4);
+            const uint32_t lsb = (x >> 16) & 1u;
+            h[i] = (uint16_t)((x + 0x7FFFu + lsb) >> 16);
+        }
+        void* d = nullptr;
+        if (hipMalloc(&d, sizeof(uint16_t) * (h.size() ? h.size() : 1)) != hipSuccess) return nullptr;
+        w->allocs.push_back(d);
+        if (hipMemcpy(d, h.data(), sizeof(uint16_t) * h.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        return d;
+    };
+    MlpArgs& a = w->args;
+    a.precision = bf ? 1 : 0;
+    a.n_in = n_in; a.n_h1 = h1; a.n_h2 = h2; a.n_out = n_out;
+    a.in_pad = in_pad; a.h1_tiles = h1t; a.h2_tiles = h2t; a.out_tiles = ot;
+    a.slope = (float)slope;
+    a.out_act = out_act ? 1 : 0;
+    a.W1 = bf ? upload_bf(P1) : upload_f(P1);
+    a.W2 = bf ? upload_bf(P2) : upload_f(P2);
+    a.W3 = bf ? upload_bf(P3) : upload_f(P3);
+    a.b1 = (const float*)upload_f(pb1);
+    a.b2 = (const float*)upload_f(pb2);
+    a.b3 = (const float*)upload_f(pb3);
+    a.in_mean = (const float*)upload_f(pm);
+    a.in_rstd = (const float*)upload_f(prs);
+    a.out_scale = (const float*)upload_f(psc);
+    a.out_shift = (const float*)upload_f(psh);
+    if (!a.W1 || !a.W2 || !a.W3 || !a.b1 || !a.b2 || !a.b3 || !a.in_mean || !a.in_rstd || !a.out_scale ||
+        !a.out_shift) {
+        mala_weights_free(w);
+        return fail(MALA_E_OOM, "weight upload failed");
+    }
+    *out = w;
+    return MALA_OK;
+}
+
+mala_status mala_weights_free(mala_weights* w) {
+    if (!w) return MALA_OK;
+    DeviceGuard g(w->device);
+    (void)hipDeviceSynchronize();     // no kernel of any stream may still read the weights
+    for (void* p : w->allocs) (void)hipFree(p);
+    delete w;
+    return MALA_OK;
+}
+
+// ---------------------------------------------------------------- compute
+mala_status mala_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
+                             double rcut, int32_t twojmax, int64_t pt_begin, int64_t pt_end, float* B_out) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    mala_status st = check_geometry(positions, n_atoms, cg, rcut, twojmax);
+    if (st) return st;
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    if (pt_begin < 0 || pt_end < pt_begin || pt_end > ntot) return fail(MALA_E_INVALID_ARG, "bad point range");
+    if (pt_end == pt_begin) return MALA_OK;
+    if (!B_out) return fail(MALA_E_INVALID_ARG, "B_out is NULL");
+    DeviceGuard g(c->device);
+    if ((st = ensure_tables(c, twojmax))) return st;
+    if ((st = upload_positions(c, positions, n_atoms))) return st;
+    return run_descriptors(c, n_atoms, cg, rcut, twojmax, pt_begin, pt_end, B_out);
+}
+
+mala_status mala_ldos_infer(mala_ctx* c, const mala_weights* w, const float* B, int64_t n_pts, float* ldos_out) {
+    if (!c || !w) return fail(MALA_E_INVALID_ARG, "NULL argument");
+    if (n_pts < 0) return fail(MALA_E_INVALID_ARG, "n_pts < 0");
+    if (n_pts == 0) return MALA_OK;
+    if (!B || !ldos_out) return fail(MALA_E_INVALID_ARG, "NULL buffer");
+    DeviceGuard g(c->device);
+    HIP_TRY(staged(c, MALA_STAGE_MLP_LDOS, n_pts, [&] {
+        return launch_mlp(c->stream, w->args, kModeLdos, B, n_pts, ldos_out, nullptr, mlp_blocks(n_pts), nullptr,
+                          nullptr, nullptr);
+    }));
+    return MALA_OK;
+}
+
+mala_status mala_integrate(mala_ctx* c, const float* ldos, int64_t n_pts, double dV, const mala_egrid* eg,
+                           double T, double ne, double* dos_out, double* density_out, mala_result* result) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    mala_status st = check_egrid(eg, T, ne);
+    if (st) return st;
+    if (n_pts < 0) return fail(MALA_E_INVALID_ARG, "n_pts < 0");
+    if (!(dV > 0.0) || !isfinite(dV)) return fail(MALA_E_INVALID_ARG, "dV must be positive");
+    if (!dos_out || !result || (n_pts > 0 && !ldos)) return fail(MALA_E_INVALID_ARG, "NULL buffer");
+    DeviceGuard g(c->device);
+    const int nb = n_pts < 2048 ? (int)(n_pts > 0 ? n_pts : 1) : 2048;
+    HIP_TRY(ensure(c->partials, (size_t)nb * kMlpMaxOut));
+    HIP_TRY(ensure(c->fermi_w, kMlpMaxOut));
+    HIP_TRY(staged(c, MALA_STAGE_INTEGRATE, n_pts,
+                   [&] { return launch_ldos_colsum(c->stream, ldos, n_pts, eg->n, c->partials.p, nb); }));
+    HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
+        return launch_fermi(c->stream, c->partials.p, nb, eg->n, dV, eg->e0, eg->de, kBoltzmannEv * T, ne,
+                            dos_out, c->fermi_w.p, result, c->li_coef);
+    }));
+    if (density_out && n_pts > 0)
+        HIP_TRY(staged(c, MALA_STAGE_INTEGRATE, n_pts, [&] {
+            return launch_density_from_ldos(c->stream, ldos, n_pts, eg->n, c->fermi_w.p, result, density_out);
+        }));
+    return MALA_OK;
+}
+
+mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* positions, int32_t n_atoms,
+                         const mala_cell_grid* cg, double rcut, int32_t twojmax, const mala_egrid* eg, double T,
+                         double ne, double* dos_out, double* density_out, mala_result* result, float* B_cache) {
+    if (!c || !w) return fail(MALA_E_INVALID_ARG, "NULL argument");
+    mala_status st = check_geometry(positions, n_atoms, cg, rcut, twojmax);
+    if (st) return st;
+    if ((st = check_egrid(eg, T, ne))) return st;
+    if (!dos_out || !result) return fail(MALA_E_INVALID_ARG, "NULL buffer");
+    if (w->args.n_in != n_triples(twojmax))
+        return fail(MALA_E_INVALID_ARG, "network input width does not match twojmax");
+    if (w->args.n_out != eg->n) return fail(MALA_E_INVALID_ARG, "network output width != energy grid size");
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    DeviceGuard g(c->device);
+    if ((st = ensure_tables(c, twojmax))) return st;
+    float* B = B_cache;
+    if (!B) {
+        HIP_TRY(ensure(c->Bbuf, (size_t)ntot * n_triples(twojmax)));
+        B = c->Bbuf.p;
+    }
+    if ((st = upload_positions(c, positions, n_atoms))) return st;
+    if ((st = run_descriptors(c, n_atoms, cg, rcut, twojmax, 0, ntot, B))) return st;
+    const int nw = mlp_blocks(ntot);
+    HIP_TRY(ensure(c->partials, (size_t)nw * kMlpMaxOut));
+    HIP_TRY(ensure(c->fermi_w, kMlpMaxOut));
+    const double dV = cg->L[0] * cg->L[1] * cg->L[2] / (double)ntot;
+    HIP_TRY(staged(c, MALA_STAGE_MLP_DOS, ntot, [&] {
+        return launch_mlp(c->stream, w->args, kModeDos, B, ntot, nullptr, c->partials.p, nw, nullptr, nullptr,
+                          nullptr);
+    }));
+    HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
+        return launch_fermi(c->stream, c->partials.p, nw, eg->n, dV, eg->e0, eg->de, kBoltzmannEv * T, ne,
+                            dos_out, c->fermi_w.p, result, c->li_coef);
+    }));
+    if (density_out)
+        HIP_TRY(staged(c, MALA_STAGE_MLP_DENSITY, ntot, [&] {
+            return launch_mlp(c->stream, w->args, kModeDensity, B, ntot, nullptr, nullptr, mlp_blocks(ntot),
+                              c->fermi_w.p, density_out, result);
+        }));
+    return MALA_OK;
+}
+
+}  // extern "C"

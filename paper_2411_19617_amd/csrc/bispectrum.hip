@@ -1,0 +1,516 @@
+// Grid bispectrum descriptors on gfx950 (Sec. 3.2.2: Eqs. ionicdensity,
+// SNAPExpansion and the triple products that give B(r, j), Eq. snap_dim).
+//
+// Two kernels per tile of 64 consecutive grid points (one point per lane):
+//
+//  k_ui  -- neighbour gather and the expansion coefficients
+//           u^J = I + sum_k f_c(r_k) U^J(g_k).  U^J is built level by level
+//           from U^0 = f_c: row 0 of level J from row 0 of level J-1, and row
+//           ma >= 1 of level J from row ma-1 of level J-1 (both follow from
+//           writing the spin-J/2 irrep as the polynomial action of g on
+//           (xi, eta)).  The rows that share J-ma form independent chains;
+//           the chains are split over the waves of the block so that each
+//           wave keeps its share of u in registers over the whole neighbour
+//           loop.  Only rows ma <= J/2 are formed; the rest follow from
+//           u_{J-ma,J-mb} = (-1)^(ma-mb) conj(u_{ma,mb}).
+//
+//  k_zb  -- the tile's half-u (271 complex per point at twojmax 10, 139 KB
+//           for 64 points) is staged in LDS; every wave of the block owns a
+//           balanced subset of the (j1,j2,j) triples and contracts
+//           Z^j_{m m'} = sum C C u^{j1} u^{j2} column by column (a column of
+//           u^{j1} and one of u^{j2} in registers, the Z column in
+//           registers), then B = sum Re(conj(u^j) Z) over the half rows.
+//           Clebsch-Gordan values come from a per-triple table in global
+//           memory read with wave-uniform (scalar) loads.
+#include "mala_internal.h"
+
+namespace mala {
+
+__host__ __device__ constexpr double ce_sqrt(double x) {
+    if (x <= 0.0) return 0.0;
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+// ------------------------------------------------------------------ chains
+// Chain q: rows k = 0..min(q, TJ-q) at level J = q + k, row index ma = k.
+__host__ __device__ constexpr int chain_rows(int tj, int q) { return (q < tj - q ? q : tj - q) + 1; }
+__host__ __device__ constexpr int chain_len(int tj, int q) {
+    int n = 0;
+    for (int k = 0; k < chain_rows(tj, q); ++k) n += q + k + 1;
+    return n;
+}
+__host__ __device__ constexpr int n_groups(int tj) { return tj >= 8 ? 2 : 1; }
+__host__ __device__ constexpr bool in_group(int tj, int g, int q) {
+    if (tj == 10) return g == 0 ? (q == 0 || q == 1 || q == 5 || q == 6 || q == 7)
+                                : (q == 2 || q == 3 || q == 4 || q == 8 || q == 9 || q == 10);
+    if (tj == 8) return g == 0 ? (q <= 4) : (q >= 5);
+    return g == 0;
+}
+__host__ __device__ constexpr int group_size(int tj, int g) {
+    int n = 0;
+    for (int q = 0; q <= tj; ++q)
+        if (in_group(tj, g, q)) n += chain_len(tj, q);
+    return n;
+}
+__host__ __device__ constexpr int group_qmax(int tj, int g) {
+    int m = 0;
+    for (int q = 0; q <= tj; ++q)
+        if (in_group(tj, g, q)) m = q;
+    return m;
+}
+__host__ __device__ constexpr int chain_slot(int tj, int g, int q) {
+    int n = 0;
+    for (int p = 0; p < q; ++p)
+        if (in_group(tj, g, p)) n += chain_len(tj, p);
+    return n;
+}
+__host__ __device__ constexpr int row_slot(int q, int k) {
+    int n = 0;
+    for (int i = 0; i < k; ++i) n += q + i + 1;
+    return n;
+}
+
+// Accumulate f_c * U(g) of one neighbour into the group's registers.
+template <int TJ, int G, int NACC>
+__device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float bi, float fc,
+                                             float (&accr)[NACC], float (&acci)[NACC]) {
+    constexpr int QMAX = group_qmax(TJ, G);
+    float r0r[TJ + 1], r0i[TJ + 1];
+    r0r[0] = fc;
+    r0i[0] = 0.f;
+    if constexpr (in_group(TJ, G, 0)) accr[chain_slot(TJ, G, 0)] += fc;
+    static_for<1, QMAX + 1>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        // row 0 of level J: b sqrt(mb/J) old[mb-1] + conj(a) sqrt((J-mb)/J) old[mb]
+        static_for<0, J + 1>([&](auto ic) {
+            constexpr int mb = J - decltype(ic)::value;
+            float nr = 0.f, ni = 0.f;
+            if constexpr (mb >= 1) {
+                constexpr float c = (float)ce_sqrt((double)mb / J);
+                const float orr = r0r[mb - 1], oi = r0i[mb - 1];
+                nr = c * (br * orr - bi * oi);
+                ni = c * (br * oi + bi * orr);
+            }
+            if constexpr (mb <= J - 1) {
+                constexpr float c = (float)ce_sqrt((double)(J - mb) / J);
+                const float orr = r0r[mb], oi = r0i[mb];
+                nr += c * (ar * orr + ai * oi);
+                ni += c * (ar * oi - ai * orr);
+            }
+            r0r[mb] = nr;
+            r0i[mb] = ni;
+        });
+        if constexpr (in_group(TJ, G, J)) {
+            constexpr int Q = J;
+            constexpr int base = chain_slot(TJ, G, Q);
+            float cr[TJ + 1], ci[TJ + 1];
+            static_for<0, Q + 1>([&](auto mc) {
+                constexpr int mb = decltype(mc)::value;
+                cr[mb] = r0r[mb];
+                ci[mb] = r0i[mb];
+                accr[base + mb] += cr[mb];
+                acci[base + mb] += ci[mb];
+            });
+            // rows k = 1..: level Jp = Q + k from the chain's previous row
+            static_for<1, chain_rows(TJ, Q)>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int Jp = Q + k;
+                static_for<0, Jp + 1>([&](auto ic) {
+                    constexpr int mb = Jp - decltype(ic)::value;
+                    float nr = 0.f, ni = 0.f;
+                    if constexpr (mb >= 1) {   // a sqrt(mb/k) old[mb-1]
+                        constexpr float c = (float)ce_sqrt((double)mb / k);
+                        const float orr = cr[mb - 1], oi = ci[mb - 1];
+                        nr = c * (ar * orr - ai * oi);
+                        ni = c * (ar * oi + ai * orr);
+                    }
+                    if constexpr (mb <= Jp - 1) {  // - conj(b) sqrt((Jp-mb)/k) old[mb]
+                        constexpr float c = (float)ce_sqrt((double)(Jp - mb) / k);
+                        const float orr = cr[mb], oi = ci[mb];
+                        nr -= c * (br * orr + bi * oi);
+                        ni -= c * (br * oi - bi * orr);
+                    }
+                    cr[mb] = nr;
+                    ci[mb] = ni;
+                });
+                constexpr int rb = base + row_slot(Q, k);
+                static_for<0, Jp + 1>([&](auto mc) {
+                    constexpr int mb = decltype(mc)::value;
+                    accr[rb + mb] += cr[mb];
+                    acci[rb + mb] += ci[mb];
+                });
+            });
+        }
+    });
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim <= 1024).
+__device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) tmp[wave] = x;
+    __syncthreads();
+    int wbase = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) wbase += tmp[w];
+        tot += tmp[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + x - v;
+}
+
+template <int TJ>
+__global__ __launch_bounds__(64 * n_groups(TJ)) void k_ui(BinState bins, int Nx, int Ny, int Nz,
+                                                          double rcut, int64_t pt_begin, int64_t n_pts,
+                                                          float2* __restrict__ u_out,
+                                                          int* __restrict__ err) {
+    constexpr int NG = n_groups(TJ);
+    constexpr int NH = n_half(TJ);
+    __shared__ float4 cand[kMaxCand];
+    __shared__ unsigned short nbr[kMaxNbr][kTile];
+    __shared__ int nnbr[kTile];
+    __shared__ int scan_tmp[16];
+    __shared__ int s_ncand;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t idx = tile * kTile + lane;
+    const bool valid = idx < n_pts;
+    const int64_t p = pt_begin + (valid ? idx : tile * kTile);
+    const int64_t pk = p % Nz, pj = (p / Nz) % Ny, pi = p / ((int64_t)Ny * Nz);
+    const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
+                 rz = (double)pk * bins.L[2] / Nz;
+    const int64_t p0 = pt_begin + tile * kTile;
+    const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
+    const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
+                 oz = (double)qk * bins.L[2] / Nz;
+    // bounding box of the tile's points
+    const double lox = wave_min_d(rx), hix = wave_max_d(rx);
+    const double loy = wave_min_d(ry), hiy = wave_max_d(ry);
+    const double loz = wave_min_d(rz), hiz = wave_max_d(rz);
+    const double rc2 = rcut * rcut;
+
+    // ---- candidate atom images: cells overlapping the box grown by rcut,
+    //      visited in a fixed order, compacted with a block scan.
+    int c_lo[3], c_n[3];
+    {
+        const double lo[3] = {lox - rcut, loy - rcut, loz - rcut};
+        const double hi[3] = {hix + rcut, hiy + rcut, hiz + rcut};
+        for (int d = 0; d < 3; ++d) {
+            c_lo[d] = (int)floor(lo[d] / bins.cs[d]);
+            c_n[d] = (int)floor(hi[d] / bins.cs[d]) - c_lo[d] + 1;
+        }
+    }
+    const int ncells = c_n[0] * c_n[1] * c_n[2];
+    int base = 0;
+    for (int c0 = 0; c0 < ncells; c0 += blockDim.x) {
+        const int c = c0 + threadIdx.x;
+        int cnt = 0, b = 0, e = 0;
+        double sx = 0, sy = 0, sz = 0;
+        if (c < ncells) {
+            const int cz = c % c_n[2], cy = (c / c_n[2]) % c_n[1], cx = c / (c_n[2] * c_n[1]);
+            const int gx = c_lo[0] + cx, gy = c_lo[1] + cy, gz = c_lo[2] + cz;
+            const int wx = ((gx % bins.nc[0]) + bins.nc[0]) % bins.nc[0];
+            const int wy = ((gy % bins.nc[1]) + bins.nc[1]) % bins.nc[1];
+            const int wz = ((gz % bins.nc[2]) + bins.nc[2]) % bins.nc[2];
+            sx = (double)((gx - wx) / bins.nc[0]) * bins.L[0];
+            sy = (double)((gy - wy) / bins.nc[1]) * bins.L[1];
+            sz = (double)((gz - wz) / bins.nc[2]) * bins.L[2];
+            const int cell = (wx * bins.nc[1] + wy) * bins.nc[2] + wz;
+            b = bins.cell_start[cell];
+            e = bins.cell_start[cell + 1];
+            for (int a = b; a < e; ++a) {
+                const double4 at = bins.atoms[a];
+                const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
+                const double dx = fmax(0.0, fmax(lox - X, X - hix));
+                const double dy = fmax(0.0, fmax(loy - Y, Y - hiy));
+                const double dz = fmax(0.0, fmax(loz - Z, Z - hiz));
+                cnt += (dx * dx + dy * dy + dz * dz < rc2);
+            }
+        }
+        int total;
+        int off = base + block_exclusive_scan(cnt, scan_tmp, &total);
+        for (int a = b; a < e; ++a) {
+            const double4 at = bins.atoms[a];
+            const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
+            const double dx = fmax(0.0, fmax(lox - X, X - hix));
+            const double dy = fmax(0.0, fmax(loy - Y, Y - hiy));
+            const double dz = fmax(0.0, fmax(loz - Z, Z - hiz));
+            if (dx * dx + dy * dy + dz * dz < rc2) {
+                if (off < kMaxCand)
+                    cand[off] = make_float4((float)(X - ox), (float)(Y - oy), (float)(Z - oz), 0.f);
+                ++off;
+            }
+        }
+        base += total;
+    }
+    if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
+    const int ncand = base < kMaxCand ? base : kMaxCand;
+    __syncthreads();
+
+    // ---- per-point neighbour lists (wave 0), in candidate order
+    const float px = (float)(rx - ox), py = (float)(ry - oy), pz = (float)(rz - oz);
+    const float rcf = (float)rcut;
+    if (wave == 0) {
+        int cnt = 0;
+        for (int c = 0; c < ncand; ++c) {
+            const float4 q = cand[c];
+            const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+            if (dx * dx + dy * dy + dz * dz < rcf * rcf) {
+                if (cnt < kMaxNbr) nbr[cnt][lane] = (unsigned short)c;
+                ++cnt;
+            }
+        }
+        if (cnt > kMaxNbr) atomicOr(err, kErrNbr);
+        nnbr[lane] = valid ? (cnt < kMaxNbr ? cnt : kMaxNbr) : 0;
+    }
+    __syncthreads();
+
+    // ---- expansion coefficients, this wave's chain group
+    static_for<0, NG>([&](auto gc) {
+        constexpr int G = decltype(gc)::value;
+        if (wave != G) return;
+        constexpr int NACC = group_size(TJ, G);
+        float accr[NACC], acci[NACC];
+        static_for<0, NACC>([&](auto ec) {
+            accr[decltype(ec)::value] = 0.f;
+            acci[decltype(ec)::value] = 0.f;
+        });
+        const int my_n = nnbr[lane];
+        const int n_iter = wave_max_int(my_n);
+        const float kpi = 3.14159265358979f;
+        for (int s = 0; s < n_iter; ++s) {
+            float ar = 1.f, ai = 0.f, br = 0.f, bi = 0.f, fc = 0.f;
+            if (s < my_n) {
+                const float4 q = cand[nbr[s][lane]];
+                const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+                const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+                const float inv = r > 0.f ? 1.f / r : 0.f;
+                float sn, cs;
+                sincosf(kRfac0 * kpi * r / rcf, &sn, &cs);
+                ar = cs;
+                ai = -dz * inv * sn;
+                br = -dy * inv * sn;
+                bi = -dx * inv * sn;
+                fc = 0.5f * (cosf(kpi * r / rcf) + 1.f);
+            }
+            ui_neighbour<TJ, G, NACC>(ar, ai, br, bi, fc, accr, acci);
+        }
+        // self term (identity on the diagonal) and write-out
+        static_for<0, TJ + 1>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (in_group(TJ, G, q)) {
+                static_for<0, chain_rows(TJ, q)>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    constexpr int J = q + k;
+                    constexpr int rb = chain_slot(TJ, G, q) + row_slot(q, k);
+                    accr[rb + k] += 1.f;
+                    static_for<0, J + 1>([&](auto mc) {
+                        constexpr int mb = decltype(mc)::value;
+                        constexpr int e = half_off(J) + k * (J + 1) + mb;
+                        u_out[(tile * NH + e) * kTile + lane] = make_float2(accr[rb + mb], acci[rb + mb]);
+                    });
+                });
+            }
+        });
+    });
+}
+
+// ------------------------------------------------------------------ Z / B
+struct Triple {
+    int j1, j2, j;
+};
+__host__ __device__ constexpr Triple triple_of(int tj, int idx) {
+    int n = 0;
+    for (int j1 = 0; j1 <= tj; ++j1)
+        for (int j2 = 0; j2 <= j1; ++j2)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= tj; j += 2)
+                if (j >= j1) {
+                    if (n == idx) return Triple{j1, j2, j};
+                    ++n;
+                }
+    return Triple{0, 0, 0};
+}
+
+// u element (J, row r [compile time], column c [runtime, uniform]) from the
+// half storage; rows past J/2 come from the conjugate symmetry.
+template <int J, int R>
+__device__ __forceinline__ float2 uload(const float2* __restrict__ su, int c, int lane) {
+    if constexpr (2 * R <= J) {
+        return su[(half_off(J) + R * (J + 1) + c) * kTile + lane];
+    } else {
+        const float2 v = su[(half_off(J) + (J - R) * (J + 1) + (J - c)) * kTile + lane];
+        const float sg = ((R - c) & 1) ? -1.f : 1.f;
+        return make_float2(sg * v.x, -sg * v.y);
+    }
+}
+
+template <int J1, int J2, int J>
+__device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int lane,
+                                           const float* __restrict__ cg) {
+    constexpr int D = (J1 + J2 - J) / 2;   // ma2 = ma - ma1 + D
+    constexpr int HR = J / 2;              // half rows 0..HR
+    constexpr int W = J + 1;               // cg row stride: cg[ma1*W + ma]
+    float bsum = 0.f;
+    for (int mb = 0; mb <= J; ++mb) {
+        float zr[HR + 1], zi[HR + 1];
+        static_for<0, HR + 1>([&](auto mc) {
+            zr[decltype(mc)::value] = 0.f;
+            zi[decltype(mc)::value] = 0.f;
+        });
+        const int lo = max(0, mb + D - J2), hi = min(J1, mb + D);
+        for (int mb1 = lo; mb1 <= hi; ++mb1) {
+            const int mb2 = mb + D - mb1;
+            const float c2 = cg[mb1 * W + mb];
+            float u2r[J2 + 1], u2i[J2 + 1];
+            static_for<0, J2 + 1>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                const float2 v = uload<J2, r>(su, mb2, lane);
+                u2r[r] = v.x;
+                u2i[r] = v.y;
+            });
+            static_for<0, J1 + 1>([&](auto r1c) {
+                constexpr int ma1 = decltype(r1c)::value;
+                // is row ma1 used by any half row ma?
+                constexpr bool used = (ma1 - D <= HR) && (ma1 - D + J2 >= 0);
+                if constexpr (used) {
+                    const float2 v = uload<J1, ma1>(su, mb1, lane);
+                    const float vr = c2 * v.x, vi = c2 * v.y;
+                    static_for<0, HR + 1>([&](auto mc) {
+                        constexpr int ma = decltype(mc)::value;
+                        constexpr int ma2 = ma - ma1 + D;
+                        if constexpr (ma2 >= 0 && ma2 <= J2) {
+                            const float c1 = cg[ma1 * W + ma];
+                            const float pr = vr * u2r[ma2] - vi * u2i[ma2];
+                            const float pi = vr * u2i[ma2] + vi * u2r[ma2];
+                            zr[ma] += c1 * pr;
+                            zi[ma] += c1 * pi;
+                        }
+                    });
+                }
+            });
+        }
+        static_for<0, HR + 1>([&](auto mc) {
+            constexpr int ma = decltype(mc)::value;
+            constexpr float w = (2 * ma < J) ? 2.f : 1.f;
+            const float2 uj = su[(half_off(J) + ma * (J + 1) + mb) * kTile + lane];
+            bsum += w * (uj.x * zr[ma] + uj.y * zi[ma]);
+        });
+    }
+    return bsum;
+}
+
+template <int TJ, int T>
+__device__ __forceinline__ float zb_dispatch(int t, const float2* __restrict__ su, int lane,
+                                             const float* __restrict__ cg_table,
+                                             const int* __restrict__ cg_off) {
+    if constexpr (T < n_triples(TJ)) {
+        if (t == T) {
+            constexpr Triple tr = triple_of(TJ, T);
+            return zb_triple<tr.j1, tr.j2, tr.j>(su, lane, cg_table + cg_off[T]);
+        }
+        return zb_dispatch<TJ, T + 1>(t, su, lane, cg_table, cg_off);
+    } else {
+        return 0.f;
+    }
+}
+
+template <int TJ>
+__global__ __launch_bounds__(1024) void k_zb(const float2* __restrict__ u, int64_t n_pts,
+                                             float* __restrict__ B, const float* __restrict__ cg_table,
+                                             const int* __restrict__ cg_off,
+                                             const int* __restrict__ wave_triples, int stride) {
+    constexpr int NH = n_half(TJ);
+    constexpr int NB = n_triples(TJ);
+    extern __shared__ float2 su[];
+    const int64_t tile = blockIdx.x;
+    {
+        const float4* src = reinterpret_cast<const float4*>(u + tile * NH * kTile);
+        float4* dst = reinterpret_cast<float4*>(su);
+        for (int i = threadIdx.x; i < NH * kTile / 2; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t idx = tile * kTile + lane;
+    const bool valid = idx < n_pts;
+    const int* list = wave_triples + wave * stride;
+    const int cnt = __builtin_amdgcn_readfirstlane(list[0]);
+    for (int i = 0; i < cnt; ++i) {
+        const int t = __builtin_amdgcn_readfirstlane(list[1 + i]);
+        const float b = zb_dispatch<TJ, 0>(t, su, lane, cg_table, cg_off);
+        if (valid) B[idx * NB + t] = b;
+    }
+}
+
+template <int TJ>
+static hipError_t ui_tj(hipStream_t s, const BinState& bins, const int N[3], double rcut, int64_t pt_begin,
+                        int64_t n_pts, float2* u_scratch, int* err_flag) {
+    const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ui<TJ>, dim3((unsigned)n_tiles), dim3(64 * n_groups(TJ)), 0, s, bins, N[0], N[1],
+                       N[2], rcut, pt_begin, n_pts, u_scratch, err_flag);
+    return hipGetLastError();
+}
+
+template <int TJ>
+static hipError_t zb_tj(hipStream_t s, int64_t n_pts, const float2* u_scratch, float* B_out,
+                        const float* cg_table, const int* cg_offsets, const int* wave_triples, int zb_waves) {
+    const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
+    if (n_tiles == 0) return hipSuccess;
+    const size_t lds = sizeof(float2) * n_half(TJ) * kTile;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zb<TJ>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_zb<TJ>, dim3((unsigned)n_tiles), dim3(64 * zb_waves), lds, s, u_scratch, n_pts, B_out,
+                       cg_table, cg_offsets, wave_triples, kMaxZbStride);
+    return hipGetLastError();
+}
+
+hipError_t launch_ui(hipStream_t s, int twojmax, const BinState& bins, const int N[3], double rcut,
+                     int64_t pt_begin, int64_t n_pts, float2* u_scratch, int* err_flag) {
+    switch (twojmax) {
+    case 2: return ui_tj<2>(s, bins, N, rcut, pt_begin, n_pts, u_scratch, err_flag);
+    case 4: return ui_tj<4>(s, bins, N, rcut, pt_begin, n_pts, u_scratch, err_flag);
+    case 6: return ui_tj<6>(s, bins, N, rcut, pt_begin, n_pts, u_scratch, err_flag);
+    case 8: return ui_tj<8>(s, bins, N, rcut, pt_begin, n_pts, u_scratch, err_flag);
+    case 10: return ui_tj<10>(s, bins, N, rcut, pt_begin, n_pts, u_scratch, err_flag);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zb(hipStream_t s, int twojmax, int64_t n_pts, const float2* u_scratch, float* B_out,
+                     const float* cg_table, const int* cg_offsets, const int* wave_triples, int zb_waves) {
+    switch (twojmax) {
+    case 2: return zb_tj<2>(s, n_pts, u_scratch, B_out, cg_table, cg_offsets, wave_triples, zb_waves);
+    case 4: return zb_tj<4>(s, n_pts, u_scratch, B_out, cg_table, cg_offsets, wave_triples, zb_waves);
+    case 6: return zb_tj<6>(s, n_pts, u_scratch, B_out, cg_table, cg_offsets, wave_triples, zb_waves);
+    case 8: return zb_tj<8>(s, n_pts, u_scratch, B_out, cg_table, cg_offsets, wave_triples, zb_waves);
+    case 10: return zb_tj<10>(s, n_pts, u_scratch, B_out, cg_table, cg_offsets, wave_triples, zb_waves);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mala

@@ -1,0 +1,256 @@
+// Energy-space observables in FP64 (Sec. 3.4): the DOS from its partial
+// sums (Eq. DOS.from.ldos), the Fermi level as the root of
+// N_e = int f D (Eq. NumberElectrons_from_DOS) found by bisection, the band
+// energy (Eq. band.energy) and the Fermi weights that turn an LDOS into the
+// density (Eq. density.from.ldos).
+//
+// D is taken piecewise linear between the energy grid points, and the
+// integrals of f, f*e against each linear piece are exact: with
+// x = (e - mu)/kT they are differences of the antiderivatives
+//   x - ln(1+e^x),  x^2/2 - x ln(1+e^x) - Li2(-e^x),
+//   x^3/3 - x^2 ln(1+e^x) - 2x Li2(-e^x) + 2 Li3(-e^x)
+// (f written through the polylogarithm as in Eq. fermidiracspecial), used in
+// the form that only needs Li_s(-y) with 0 < y <= 1.  Li_s(-y) is summed as
+// its power series for y <= 1/2 and as the Taylor series in ln y about y = 1
+// (coefficients -eta(s-n)/n!, computed on the host) otherwise.
+#include <math.h>
+
+#include "mala_internal.h"
+
+namespace mala {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ double li_neg(int s, double y, const double* __restrict__ coef) {
+    // Li_s(-y), s in {2, 3}, 0 <= y <= 1
+    if (y <= 0.5) {
+        double term = -y, sum = 0.0;
+        for (int k = 1; k <= 60; ++k) {
+            const double kk = (double)k;
+            sum += term / (s == 2 ? kk * kk : kk * kk * kk);
+            term *= -y;
+        }
+        return sum;
+    }
+    const double t = log(y);                    // in (-ln 2, 0]
+    const double* c = coef + (s - 2) * kLiTerms;
+    double acc = c[kLiTerms - 1];
+    for (int n = kLiTerms - 2; n >= 0; --n) acc = acc * t + c[n];
+    return acc;
+}
+
+// G0, G1, G2 at x (see the file comment).
+__device__ void gfun(double x, const double* coef, double& g0, double& g1, double& g2) {
+    if (x <= 0.0) {
+        const double y = exp(x), lg = log1p(y);
+        const double l2 = li_neg(2, y, coef), l3 = li_neg(3, y, coef);
+        g0 = x - lg;
+        g1 = 0.5 * x * x - x * lg - l2;
+        g2 = x * x * x / 3.0 - x * x * lg - 2.0 * x * l2 + 2.0 * l3;
+    } else {
+        const double y = exp(-x), lg = log1p(y);
+        const double l2 = li_neg(2, y, coef), l3 = li_neg(3, y, coef);
+        g0 = -lg;
+        g1 = kPi * kPi / 6.0 - x * lg + l2;
+        g2 = -x * x * lg + 2.0 * x * l2 + 2.0 * l3;
+    }
+}
+
+// Integrals over [e_i, e_i + de] of f and f*e against the two hat pieces:
+// (wl, wr) for int f (1-t), int f t and (vl, vr) for the e-weighted ones.
+__device__ void interval(double ea, double de, double mu, double kT, const double* coef, double& wl,
+                         double& wr, double& vl, double& vr) {
+    const double beta = 1.0 / kT;
+    const double xa = (ea - mu) * beta, xb = (ea + de - mu) * beta;
+    double a0, a1, a2, b0, b1, b2;
+    gfun(xa, coef, a0, a1, a2);
+    gfun(xb, coef, b0, b1, b2);
+    const double D = xb - xa;
+    const double I0 = (b0 - a0) * kT;
+    const double I1 = ((b1 - a1) - xa * (b0 - a0)) * kT / D;
+    const double K0 = (b1 - a1) * kT;
+    const double K1 = ((b2 - a2) - xa * (b1 - a1)) * kT / D;
+    wl = I0 - I1;
+    wr = I1;
+    vl = mu * (I0 - I1) + (K0 - K1) * kT;
+    vr = mu * I1 + K1 * kT;
+}
+
+// Fixed-shape tree sum over 256 threads.
+__device__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partials, int n_parts, int n_e,
+                                               double dV, double e0, double de, double kT,
+                                               double n_target, double* __restrict__ dos_out,
+                                               double* __restrict__ w_out, ResultRec* __restrict__ res,
+                                               const double* __restrict__ coef) {
+    __shared__ double D[256], red[256], wl_s[256], wr_s[256], vl_s[256], vr_s[256];
+    const int e = threadIdx.x;
+    double d = 0.0;
+    if (e < n_e) {
+        for (int w = 0; w < n_parts; ++w) d += partials[(size_t)w * kMlpMaxOut + e];
+        d *= dV;
+        dos_out[e] = d;
+    }
+    D[e] = d;
+    __syncthreads();
+    const double elast = e0 + (n_e - 1) * de;
+    auto count = [&](double mu) {
+        double c = 0.0;
+        if (e < n_e - 1) {
+            double wl, wr, vl, vr;
+            interval(e0 + e * de, de, mu, kT, coef, wl, wr, vl, vr);
+            c = wl * D[e] + wr * D[e + 1];
+        }
+        return block_sum(c, red);
+    };
+    const double nlo = count(e0), nhi = count(elast);
+    if (!(nlo <= n_target && n_target <= nhi)) {
+        if (e < n_e) w_out[e] = 0.0;
+        if (e == 0) {
+            res->e_fermi = NAN;
+            res->e_band = NAN;
+            res->n_found = NAN;
+            res->n_target = n_target;
+            res->iterations = 0;
+            res->status = -4;
+        }
+        return;
+    }
+    double lo = e0, hi = elast;
+    int it = 0;
+    while (hi - lo >= 1e-12 && it < 200) {
+        const double mid = 0.5 * (lo + hi);
+        if (count(mid) < n_target) lo = mid;
+        else hi = mid;
+        ++it;
+    }
+    const double ef = 0.5 * (lo + hi);
+    double wl = 0, wr = 0, vl = 0, vr = 0;
+    if (e < n_e - 1) interval(e0 + e * de, de, ef, kT, coef, wl, wr, vl, vr);
+    wl_s[e] = wl; wr_s[e] = wr; vl_s[e] = vl; vr_s[e] = vr;
+    __syncthreads();
+    double we = 0.0, ve = 0.0;
+    if (e < n_e) {
+        if (e < n_e - 1) { we += wl_s[e]; ve += vl_s[e]; }
+        if (e >= 1) { we += wr_s[e - 1]; ve += vr_s[e - 1]; }
+        w_out[e] = we;
+    }
+    const double nf = block_sum(we * D[e], red);
+    const double eb = block_sum(ve * D[e], red);
+    if (e == 0) {
+        res->e_fermi = ef;
+        res->e_band = eb;
+        res->n_found = nf;
+        res->n_target = n_target;
+        res->iterations = it;
+        res->status = 0;
+    }
+}
+
+// Column sums of a stored LDOS [n][n_e] into FP64 partial rows, one per block
+// over a fixed contiguous range of points.
+__global__ __launch_bounds__(256) void k_ldos_colsum(const float* __restrict__ ldos, int64_t n_pts, int n_e,
+                                                     double* __restrict__ partials, int n_blocks) {
+    const int e = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t p_begin = n_pts * b / n_blocks, p_end = n_pts * (b + 1) / n_blocks;
+    double s = 0.0;
+    if (e < n_e)
+        for (int64_t p = p_begin; p < p_end; ++p) s += (double)ldos[p * n_e + e];
+    partials[b * kMlpMaxOut + e] = e < n_e ? s : 0.0;
+}
+
+// n(p) = sum_e w_e d_e(p), one wave per point (grid-stride).
+__global__ __launch_bounds__(256) void k_density_ldos(const float* __restrict__ ldos, int64_t n_pts, int n_e,
+                                                      const double* __restrict__ w,
+                                                      const ResultRec* __restrict__ res,
+                                                      double* __restrict__ dens) {
+    if (res->status != 0) return;
+    const int lane = threadIdx.x & 63;
+    double wr[4];
+    for (int q = 0; q < 4; ++q) wr[q] = (lane + 64 * q < n_e) ? w[lane + 64 * q] : 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < n_pts; p += (int64_t)gridDim.x * 4) {
+        double s = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            const int e = lane + 64 * q;
+            if (e < n_e) s += wr[q] * (double)ldos[p * n_e + e];
+        }
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) dens[p] = s;
+    }
+}
+
+hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int n_e, double dV, double e0,
+                        double de, double kT, double n_target, double* dos_out, double* weights_out,
+                        void* result, const double* li_coef) {
+    hipLaunchKernelGGL(k_fermi, dim3(1), dim3(256), 0, s, partials, n_parts, n_e, dV, e0, de, kT, n_target,
+                       dos_out, weights_out, static_cast<ResultRec*>(result), li_coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_ldos_colsum(hipStream_t s, const float* ldos, int64_t n_pts, int n_e, double* partials,
+                              int n_blocks) {
+    hipLaunchKernelGGL(k_ldos_colsum, dim3(n_blocks), dim3(256), 0, s, ldos, n_pts, n_e, partials, n_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
+                                    const double* weights, const void* result, double* density) {
+    int64_t blocks = (n_pts + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_density_ldos, dim3((unsigned)blocks), dim3(256), 0, s, ldos, n_pts, n_e, weights,
+                       static_cast<const ResultRec*>(result), density);
+    return hipGetLastError();
+}
+
+// Taylor coefficients of Li_s(-e^t) about t = 0 for s = 2, 3:
+// c_{s,n} = Li_{s-n}(-1)/n! = -eta(s-n)/n!, with eta(1) = ln 2,
+// eta(2) = pi^2/12, eta(3) = 3 zeta(3)/4 and, for m >= 0,
+// eta(-m) = (2^(m+1) - 1) B_{m+1}/(m+1) (B_1 = +1/2; B_{2k} from zeta(2k)).
+void polylog_coefficients(double* coef) {
+    auto zeta_even = [](int n) {     // zeta(n), n >= 2 even: sum plus integral tail
+        if (n == 2) return kPi * kPi / 6.0;
+        const int K = 2000;
+        double s = pow((double)K, 1.0 - n) / (n - 1) - 0.5 * pow((double)K, -(double)n);
+        for (int k = K - 1; k >= 1; --k) s += pow((double)k, -(double)n);
+        return s;
+    };
+    auto bernoulli = [&](int n) {    // B_n with B_1 = +1/2
+        if (n == 0) return 1.0;
+        if (n == 1) return 0.5;
+        if (n & 1) return 0.0;
+        double f = 1.0;
+        for (int k = 2; k <= n; ++k) f *= k;
+        const double sign = ((n / 2) & 1) ? 1.0 : -1.0;      // (-1)^(n/2+1)
+        return sign * 2.0 * f * zeta_even(n) / pow(2.0 * kPi, n);
+    };
+    auto eta = [&](int s) {
+        if (s == 1) return log(2.0);
+        if (s == 2) return kPi * kPi / 12.0;
+        if (s == 3) return 0.75 * 1.2020569031595942854;   // zeta(3) (Apery's constant)
+        const int m = -s;                                      // s <= 0
+        return (pow(2.0, m + 1) - 1.0) * bernoulli(m + 1) / (m + 1);
+    };
+    for (int si = 0; si < 2; ++si) {
+        const int s = 2 + si;
+        double fact = 1.0;
+        for (int n = 0; n < kLiTerms; ++n) {
+            if (n > 0) fact *= n;
+            coef[si * kLiTerms + n] = -eta(s - n) / fact;
+        }
+    }
+}
+
+}  // namespace mala

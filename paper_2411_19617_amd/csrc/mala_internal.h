@@ -1,0 +1,127 @@
+// Internal declarations of the gfx950 library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace mala {
+
+constexpr int kTile = 64;            // grid points per bispectrum tile (one per lane)
+constexpr int kMaxTwojmax = 10;
+constexpr int kMaxCand = 1024;       // candidate atom images per tile
+constexpr int kMaxNbr = 128;         // neighbours per grid point
+constexpr int kMlpBlocks = 1024;     // fixed block count of the network kernels (deterministic partials)
+constexpr int kMaxZbStride = 64;     // per-wave triple list stride (count + indices)
+constexpr int kMlpMaxIn = 128;       // padded input width limit
+constexpr int kMlpMaxHidden = 512;   // hidden width limit
+constexpr int kMlpMaxOut = 256;      // output width limit
+constexpr double kBoltzmannEv = 8.617333262e-5;
+constexpr float kRfac0 = 0.99363f;
+
+// Device-side error bits (OR-ed into a flag word in device memory).
+constexpr int kErrCand = 1;          // tile candidate list overflow
+constexpr int kErrNbr = 2;           // per-point neighbour list overflow
+
+// ---------------------------------------------------------------- u indexing
+// u^J is stored for rows ma = 0..J/2 (the other rows follow from
+// u_{J-ma, J-mb} = (-1)^(ma-mb) conj(u_{ma, mb})), row-major, levels
+// concatenated: element (J, ma, mb) -> half_off(J) + ma*(J+1) + mb.
+__host__ __device__ constexpr int half_rows(int J) { return J / 2 + 1; }
+__host__ __device__ constexpr int half_size(int J) { return half_rows(J) * (J + 1); }
+__host__ __device__ constexpr int half_off(int J) {
+    int o = 0;
+    for (int k = 0; k < J; ++k) o += half_size(k);
+    return o;
+}
+__host__ __device__ constexpr int n_half(int tj) { return half_off(tj + 1); }
+
+// Descriptor triples (doubled indices) in output order.
+__host__ __device__ constexpr int n_triples(int tj) {
+    int n = 0;
+    for (int j1 = 0; j1 <= tj; ++j1)
+        for (int j2 = 0; j2 <= j1; ++j2)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= tj; j += 2)
+                if (j >= j1) ++n;
+    return n;
+}
+
+// compile-time loop helper
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (Begin < End) {
+        f(std::integral_constant<int, Begin>{});
+        static_for<Begin + 1, End>(std::forward<F>(f));
+    }
+}
+
+// ---------------------------------------------------------------- launches
+struct BinState {
+    int nc[3];            // cells per edge
+    double cs[3];         // cell size
+    double L[3];
+    int ncell;
+    int n_atoms;
+    const int* cell_start;      // [ncell+1]
+    const double4* atoms;       // [n_atoms] wrapped positions sorted by cell (w = index)
+};
+
+hipError_t launch_bin(hipStream_t s, const double* pos_dev, int n_atoms, const double L[3],
+                      double rcut, int* cell_count, int* cell_start, int* cell_fill,
+                      double4* atoms_tmp, int* atom_cell, double4* atoms_sorted, BinState* st);
+
+hipError_t launch_ui(hipStream_t s, int twojmax, const BinState& bins, const int N[3], double rcut,
+                     int64_t pt_begin, int64_t n_pts, float2* u_scratch, int* err_flag);
+hipError_t launch_zb(hipStream_t s, int twojmax, int64_t n_pts, const float2* u_scratch, float* B_out,
+                     const float* cg_table, const int* cg_offsets, const int* wave_triples, int zb_waves);
+
+struct MlpArgs {
+    int precision;               // 0 fp32, 1 bf16
+    int n_in, n_h1, n_h2, n_out; // logical widths
+    int in_pad, h1_tiles, h2_tiles, out_tiles;
+    float slope;
+    int out_act;
+    const void* W1;              // packed A operands
+    const void* W2;
+    const void* W3;
+    const float* b1;             // padded biases (zeros in the padding)
+    const float* b2;
+    const float* b3;
+    const float* in_mean;        // [n_in]
+    const float* in_rstd;        // [n_in] 1/std
+    const float* out_scale;      // [out_tiles*16] (zeros in the padding)
+    const float* out_shift;
+};
+
+enum MlpMode { kModeLdos = 0, kModeDos = 1, kModeDensity = 2 };
+
+// Mirrors mala_result of include/mala.h.
+struct ResultRec {
+    double e_fermi, e_band, n_found, n_target;
+    int32_t iterations, status, reserved[2];
+};
+
+int mlp_blocks(int64_t n_pts);
+hipError_t launch_mlp(hipStream_t s, const MlpArgs& a, int mode, const float* B, int64_t n_pts,
+                      float* ldos_out, double* dos_partials, int n_blocks, const double* fermi_w,
+                      double* density_out, const void* result);
+
+hipError_t launch_ldos_colsum(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
+                              double* partials, int n_blocks);
+
+hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
+                        double e0, double de, double kT, double n_target, double* dos_out,
+                        double* weights_out, void* result, const double* li_coef);
+
+hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
+                                    const double* weights, const void* result, double* density);
+
+// Host-side tables.
+int build_cg_table(int twojmax, float* table, int* offsets, int cap);
+void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride);
+void polylog_coefficients(double* coef);   // [2][kLiTerms] Taylor coefficients at x=0
+constexpr int kLiTerms = 32;
+
+}  // namespace mala

@@ -1,0 +1,166 @@
+// Host-side constant tables of the descriptor kernels.
+//
+// Clebsch-Gordan coefficients <j1 m1 j2 m2 | j m> are built by coupling:
+// the stretched state |j1+j2, j1+j2> = |j1 j1>|j2 j2> is lowered with
+// J- = J1- + J2-; each lower j starts from the vector of the M = j subspace
+// orthogonal to all states of larger j (Gram-Schmidt), with the
+// Condon-Shortley phase <j1 j1, j2 (j-j1) | j j> > 0, and is lowered in turn.
+// This is a different route from the closed Racah sum.
+//
+// Table layout per descriptor triple (J1, J2, J) (doubled): a dense
+// (J1+1) x (J+1) block c[ma1*(J+1) + ma] = <j1 m1 j2 m2 | j m> with
+// ma1 = j1 + m1, ma = j + m, m2 = m - m1 (zero where m2 is out of range).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mala_internal.h"
+
+namespace mala {
+
+namespace {
+
+// coupled[J][ma][ma1] for fixed (J1, J2): coefficient of |ma1, ma2 = ma - ma1 + (J1+J2-J)/2>
+struct Coupling {
+    int J1, J2;
+    // index (J, ma, ma1, ma2) flattened over the product basis
+    std::vector<std::vector<std::vector<double>>> vec;  // [Jidx][ma] -> product-basis vector
+};
+
+inline int pidx(int J2, int a1, int a2) { return a1 * (J2 + 1) + a2; }
+
+Coupling couple(int J1, int J2) {
+    Coupling c;
+    c.J1 = J1;
+    c.J2 = J2;
+    const int dim = (J1 + 1) * (J2 + 1);
+    const int nJ = std::min(J1, J2) + 1;   // J = J1+J2, J1+J2-2, ..., |J1-J2|
+    c.vec.assign(nJ, {});
+    // lowering: J-|j,m> = sqrt((j+m)(j-m+1)) |j,m-1>; doubled: ma = j+m, so
+    // (j+m)(j-m+1) = ma * (J - ma + 1) with J doubled.
+    auto lower = [&](const std::vector<double>& v) {
+        std::vector<double> out(dim, 0.0);
+        for (int a1 = 0; a1 <= J1; ++a1)
+            for (int a2 = 0; a2 <= J2; ++a2) {
+                const double x = v[pidx(J2, a1, a2)];
+                if (x == 0.0) continue;
+                if (a1 >= 1) out[pidx(J2, a1 - 1, a2)] += x * sqrt((double)a1 * (J1 - a1 + 1));
+                if (a2 >= 1) out[pidx(J2, a1, a2 - 1)] += x * sqrt((double)a2 * (J2 - a2 + 1));
+            }
+        return out;
+    };
+    for (int t = 0; t < nJ; ++t) {
+        const int J = J1 + J2 - 2 * t;
+        // top state: M = J/2, i.e. a1 + a2 = (J + J1 + J2)/2
+        const int S = (J + J1 + J2) / 2;
+        std::vector<double> top(dim, 0.0);
+        // start from the product state with a1 = J1 (m1 = j1), orthogonalise
+        top[pidx(J2, J1, S - J1)] = 1.0;
+        for (int u = 0; u < t; ++u) {
+            const int Ju = J1 + J2 - 2 * u;
+            const std::vector<double>& w = c.vec[u][(Ju + J) / 2];   // |Ju, M = J/2>: ma = Ju/2 + J/2
+            double dot = 0.0;
+            for (int i = 0; i < dim; ++i) dot += w[i] * top[i];
+            for (int i = 0; i < dim; ++i) top[i] -= dot * w[i];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < dim; ++i) nrm += top[i] * top[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < dim; ++i) top[i] /= nrm;
+        if (top[pidx(J2, J1, S - J1)] < 0)
+            for (int i = 0; i < dim; ++i) top[i] = -top[i];
+        c.vec[t].assign(J + 1, std::vector<double>());
+        c.vec[t][J] = top;
+        for (int ma = J; ma >= 1; --ma) {
+            std::vector<double> v = lower(c.vec[t][ma]);
+            const double f = sqrt((double)ma * (J - ma + 1));
+            for (int i = 0; i < dim; ++i) v[i] /= f;
+            c.vec[t][ma - 1] = v;
+        }
+    }
+    return c;
+}
+
+}  // namespace
+
+// Returns the number of floats written, or -1 if cap is too small.
+int build_cg_table(int twojmax, float* table, int* offsets, int cap) {
+    int n = 0, t = 0;
+    std::vector<Coupling> cache((twojmax + 1) * (twojmax + 1));
+    std::vector<bool> have(cache.size(), false);
+    for (int j1 = 0; j1 <= twojmax; ++j1)
+        for (int j2 = 0; j2 <= j1; ++j2)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= twojmax; j += 2) {
+                if (j < j1) continue;
+                const int key = j1 * (twojmax + 1) + j2;
+                if (!have[key]) {
+                    cache[key] = couple(j1, j2);
+                    have[key] = true;
+                }
+                const Coupling& c = cache[key];
+                const int tidx = (j1 + j2 - j) / 2;
+                const int D = (j1 + j2 - j) / 2;
+                offsets[t++] = n;
+                const int sz = (j1 + 1) * (j + 1);
+                if (n + sz > cap) return -1;
+                for (int ma1 = 0; ma1 <= j1; ++ma1)
+                    for (int ma = 0; ma <= j; ++ma) {
+                        const int ma2 = ma - ma1 + D;
+                        double v = 0.0;
+                        if (ma2 >= 0 && ma2 <= j2) v = c.vec[tidx][ma][pidx(j2, ma1, ma2)];
+                        table[n + ma1 * (j + 1) + ma] = (float)v;
+                    }
+                n += sz;
+            }
+    return n;
+}
+
+// Estimated work of one triple in the column-blocked contraction.
+static double triple_cost(int J1, int J2, int J) {
+    const int D = (J1 + J2 - J) / 2, HR = J / 2;
+    double tot = 0.0;
+    for (int mb = 0; mb <= J; ++mb) {
+        for (int mb1 = std::max(0, mb + D - J2); mb1 <= std::min(J1, mb + D); ++mb1) {
+            int terms = 0;
+            for (int ma = 0; ma <= HR; ++ma)
+                for (int ma1 = 0; ma1 <= J1; ++ma1) {
+                    const int ma2 = ma - ma1 + D;
+                    if (ma2 >= 0 && ma2 <= J2) ++terms;
+                }
+            tot += 6.0 * terms + 2.0 * (J1 + 1) + (J2 + 1) + 4.0;
+        }
+        tot += 3.0 * (HR + 1);
+    }
+    return tot;
+}
+
+// Longest-processing-time assignment of triples to the waves of a block.
+// wave_triples[w*stride] = count, followed by the triple indices.
+void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride) {
+    std::vector<std::pair<double, int>> jobs;
+    int t = 0;
+    for (int j1 = 0; j1 <= twojmax; ++j1)
+        for (int j2 = 0; j2 <= j1; ++j2)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= twojmax; j += 2)
+                if (j >= j1) jobs.push_back({triple_cost(j1, j2, j), t++});
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                         return a.first > b.first;
+                     });
+    std::vector<double> load(n_waves, 0.0);
+    std::vector<std::vector<int>> lists(n_waves);
+    for (auto& jb : jobs) {
+        int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[w] += jb.first;
+        lists[w].push_back(jb.second);
+    }
+    for (int w = 0; w < n_waves; ++w) {
+        std::sort(lists[w].begin(), lists[w].end());
+        wave_triples[w * stride] = (int)lists[w].size();
+        for (size_t i = 0; i < lists[w].size(); ++i) wave_triples[w * stride + 1 + i] = lists[w][i];
+    }
+}
+
+}  // namespace mala

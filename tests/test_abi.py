@@ -1,0 +1,63 @@
+"""C-ABI checks that need no GPU: the library loads and exports every symbol
+that include/mala.h declares, and the pure host functions behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mala.h")
+LIB = os.path.join(ROOT, "paper_2411_19617_amd", "libmala.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mala_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_path_entry_points():
+    names = declared_functions()
+    for n in ("mala_descriptors", "mala_ldos_infer", "mala_integrate", "mala_predict", "mala_create",
+              "mala_weights_load", "mala_last_error"):
+        assert n in names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libmala.so not built")
+    return ctypes.CDLL(LIB)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_n_descriptors_matches_paper_formula(lib):
+    lib.mala_n_descriptors.restype = ctypes.c_int32
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "snap_dim.txt"))
+            if l.strip() and not l.startswith("#")]
+    for tj, n in rows:
+        assert lib.mala_n_descriptors(int(tj)) == int(n)
+    assert lib.mala_n_descriptors(-1) == -1
+
+
+def test_null_arguments_are_rejected_without_a_device(lib):
+    lib.mala_last_error.restype = ctypes.c_char_p
+    lib.mala_create.restype = ctypes.c_int32
+    assert lib.mala_create(0, None, None) == -1
+    assert b"NULL" in lib.mala_last_error()
+    for name in ("mala_descriptors", "mala_ldos_infer", "mala_integrate", "mala_predict", "mala_synchronize"):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int32
+    assert lib.mala_synchronize(None) == -1
+    assert lib.mala_destroy(None) == 0
+    assert lib.mala_weights_free(None) == 0
+
+
+def test_version_string(lib):
+    lib.mala_version.restype = ctypes.c_char_p
+    assert lib.mala_version().startswith(b"mala-gfx950")
