@@ -119,7 +119,9 @@ typedef struct {
     double n_target;      /* requested N_e                        */
     int32_t iterations;   /* bisection steps                      */
     int32_t status;       /* MALA_OK or MALA_E_NO_ROOT            */
-    int32_t reserved[2];
+    int32_t density_from_window; /* mala_predict: 1 if the density came from
+                                    the stored energy window, 0 otherwise */
+    int32_t reserved;
 } mala_result;
 
 /* ---------------------------------------------------------------- compute */
@@ -150,9 +152,15 @@ mala_status mala_integrate(mala_ctx* ctx, const float* ldos, int64_t n_pts, doub
                            double* dos_out, double* density_out, mala_result* result);
 
 /* Whole path, fused: descriptors of every grid point (cached as B in
- * device memory), network with the DOS reduced in the epilogue (the LDOS is
- * never stored), Fermi level, band energy, then a second network pass whose
- * epilogue contracts the LDOS with the Fermi weights into the density.
+ * device memory), network with the DOS reduced in the epilogue (the full
+ * LDOS is never stored), Fermi level, band energy and density.
+ * The density needs E_F, which needs every point.  In the default mode a
+ * network pass over every 17th point first estimates E_F; the main pass then
+ * keeps per point only the FP64 sum of the fully occupied part below the
+ * window and the LDOS inside the window E_est +- (40 kT + 0.3 eV); once E_F
+ * is solved, the density is finished from those.  If the window does not
+ * contain E_F +- 40 kT, a second network pass recomputes the density
+ * (decided on the device, no host round trip).
  *  B_cache: device float32 [N_points][n_B] or NULL (then context scratch).
  *  Outputs as in mala_integrate; density_out may be NULL.                   */
 mala_status mala_predict(mala_ctx* ctx, const mala_weights* w, const double* positions,
@@ -160,6 +168,12 @@ mala_status mala_predict(mala_ctx* ctx, const mala_weights* w, const double* pos
                          int32_t twojmax, const mala_egrid* eg, double T_kelvin,
                          double n_electrons, double* dos_out, double* density_out,
                          mala_result* result, float* B_cache);
+
+/* How mala_predict obtains the density: from the stored energy window with
+ * recompute as fallback (default), or always by the recompute pass.         */
+#define MALA_DENSITY_WINDOW 0
+#define MALA_DENSITY_RECOMPUTE 1
+mala_status mala_set_density_mode(mala_ctx* ctx, int32_t mode);
 
 /* ---------------------------------------------------------------- timing
  * Per-stage instrumentation (the method's cost breakdown by stage): while
@@ -176,7 +190,9 @@ mala_status mala_predict(mala_ctx* ctx, const mala_weights* w, const double* pos
 #define MALA_STAGE_FERMI 5        /* DOS sum, E_F bisection, E_band, weights */
 #define MALA_STAGE_MLP_DENSITY 6  /* network, density in the epilogue        */
 #define MALA_STAGE_INTEGRATE 7    /* stored-LDOS column sums and density     */
-#define MALA_N_STAGES 8
+#define MALA_STAGE_ESTIMATE 8     /* E_F estimate on a point subsample       */
+#define MALA_STAGE_DENSITY_WINDOW 9 /* density from the stored energy window */
+#define MALA_N_STAGES 10
 mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
 mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
 

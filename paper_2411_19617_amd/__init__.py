@@ -25,7 +25,10 @@ MALA_E_CAPACITY = -7
 PREC_FP32 = 0
 PREC_BF16 = 1
 RESULT_BYTES = 48
-STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate"]
+STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
+          "density_window"]
+DENSITY_WINDOW = 0
+DENSITY_RECOMPUTE = 1
 
 _lib = None
 
@@ -70,6 +73,7 @@ def lib():
             ("mala_predict", [p, p, p, i32, ctypes.POINTER(CellGrid), d, i32, ctypes.POINTER(EGrid), d, d,
                               p, p, p, p]),
             ("mala_profile_enable", [p, i32]),
+            ("mala_set_density_mode", [p, i32]),
             ("mala_profile_read", [p, p, p, p]),
         ]:
             fn = getattr(L, name)
@@ -120,9 +124,10 @@ def read_result(res):
     """Decode a device mala_result (uint8 tensor of 48 bytes); synchronises."""
     raw = res.cpu().numpy().tobytes()
     d = np.frombuffer(raw[:32], dtype="<f8")
-    i = np.frombuffer(raw[32:40], dtype="<i4")
+    i = np.frombuffer(raw[32:44], dtype="<i4")
     return {"e_fermi": float(d[0]), "e_band": float(d[1]), "n_found": float(d[2]),
-            "n_target": float(d[3]), "iterations": int(i[0]), "status": int(i[1])}
+            "n_target": float(d[3]), "iterations": int(i[0]), "status": int(i[1]),
+            "density_from_window": int(i[2])}
 
 
 class Weights:
@@ -176,6 +181,9 @@ class Context:
 
     def check_device_errors(self):
         _check(lib().mala_check_device_errors(self.handle))
+
+    def set_density_mode(self, mode):
+        _check(lib().mala_set_density_mode(self.handle, int(mode)))
 
     def profile_enable(self, on=True):
         _check(lib().mala_profile_enable(self.handle, 1 if on else 0))

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -82,8 +83,12 @@ struct mala_ctx {
     DevBuf<double4> atoms_tmp, atoms_sorted;
     DevBuf<float2> u;
     DevBuf<float> Bbuf;
-    DevBuf<double> partials;
+    DevBuf<double> partials, est_partials;
     DevBuf<double> fermi_w;
+    DevBuf<float> window;
+    DevBuf<double> prefix;
+    WindowRec* win = nullptr;
+    int density_mode = 0;              // 0: stored energy window (recompute if not covered), 1: recompute
     int* err = nullptr;
     double* li_coef = nullptr;
     TjTables tj[kMaxTwojmax + 1];
@@ -141,6 +146,20 @@ hipError_t staged(mala_ctx* c, int stage, int64_t pts, F&& fn) {
     if (e == hipSuccess) e = hipEventRecord(b, c->stream);
     c->prof_pending.push_back({stage, a, b, pts});
     return e;
+}
+
+constexpr int kEstStride = 17;          // subsample stride of the E_F estimate
+
+__global__ void k_set_covered(WindowRec* w, int v) {
+    if (threadIdx.x == 0) {
+        w->covered = v;
+        w->valid = v;
+    }
+}
+
+hipError_t set_covered(mala_ctx* c, int v) {
+    hipLaunchKernelGGL(k_set_covered, dim3(1), dim3(64), 0, c->stream, c->win, v);
+    return hipGetLastError();
 }
 
 mala_status ensure_tables(mala_ctx* c, int tj) {
@@ -275,9 +294,10 @@ mala_status mala_create(int32_t device, void* stream, mala_ctx** out) {
     hipError_t e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&c->err, sizeof(int));
     if (e == hipSuccess) e = hipMemset(c->err, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&c->li_coef, sizeof(double) * 2 * kLiTerms);
+    if (e == hipSuccess) e = hipMalloc(&c->li_coef, sizeof(double) * kLiCoef);
+    if (e == hipSuccess) e = hipMalloc(&c->win, sizeof(WindowRec));
     if (e == hipSuccess) {
-        double coef[2 * kLiTerms];
+        double coef[kLiCoef];
         polylog_coefficients(coef);
         e = hipMemcpy(c->li_coef, coef, sizeof(coef), hipMemcpyHostToDevice);
     }
@@ -305,7 +325,11 @@ mala_status mala_destroy(mala_ctx* c) {
     release(c->u);
     release(c->Bbuf);
     release(c->partials);
+    release(c->est_partials);
     release(c->fermi_w);
+    release(c->window);
+    release(c->prefix);
+    if (c->win) (void)hipFree(c->win);
     if (c->pos_stage) (void)hipHostFree(c->pos_stage);
     if (c->err) (void)hipFree(c->err);
     if (c->li_coef) (void)hipFree(c->li_coef);
@@ -346,6 +370,13 @@ mala_status mala_check_device_errors(mala_ctx* c) {
     HIP_TRY(hipMemset(c->err, 0, sizeof(int)));
     if (flag & kErrCand) return fail(MALA_E_CAPACITY, "more than 1024 atom images near one 64-point tile");
     if (flag & kErrNbr) return fail(MALA_E_CAPACITY, "more than 128 neighbours within rcut of a grid point");
+    return MALA_OK;
+}
+
+mala_status mala_set_density_mode(mala_ctx* c, int32_t mode) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    if (mode != MALA_DENSITY_WINDOW && mode != MALA_DENSITY_RECOMPUTE) return fail(MALA_E_INVALID_ARG, "unknown density mode");
+    c->density_mode = mode;
     return MALA_OK;
 }
 
@@ -549,10 +580,10 @@ mala_status mala_ldos_infer(mala_ctx* c, const mala_weights* w, const float* B, 
     if (n_pts == 0) return MALA_OK;
     if (!B || !ldos_out) return fail(MALA_E_INVALID_ARG, "NULL buffer");
     DeviceGuard g(c->device);
-    HIP_TRY(staged(c, MALA_STAGE_MLP_LDOS, n_pts, [&] {
-        return launch_mlp(c->stream, w->args, kModeLdos, B, n_pts, ldos_out, nullptr, mlp_blocks(n_pts), nullptr,
-                          nullptr, nullptr);
-    }));
+    MlpOut o;
+    o.ldos = ldos_out;
+    HIP_TRY(staged(c, MALA_STAGE_MLP_LDOS, n_pts,
+                   [&] { return launch_mlp(c->stream, w->args, kModeLdos, B, n_pts, 1, mlp_blocks(n_pts), o); }));
     return MALA_OK;
 }
 
@@ -572,7 +603,7 @@ mala_status mala_integrate(mala_ctx* c, const float* ldos, int64_t n_pts, double
                    [&] { return launch_ldos_colsum(c->stream, ldos, n_pts, eg->n, c->partials.p, nb); }));
     HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
         return launch_fermi(c->stream, c->partials.p, nb, eg->n, dV, eg->e0, eg->de, kBoltzmannEv * T, ne,
-                            dos_out, c->fermi_w.p, result, c->li_coef);
+                            dos_out, c->fermi_w.p, result, nullptr, c->li_coef);
     }));
     if (density_out && n_pts > 0)
         HIP_TRY(staged(c, MALA_STAGE_INTEGRATE, n_pts, [&] {
@@ -602,23 +633,62 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
     }
     if ((st = upload_positions(c, positions, n_atoms))) return st;
     if ((st = run_descriptors(c, n_atoms, cg, rcut, twojmax, 0, ntot, B))) return st;
-    const int nw = mlp_blocks(ntot);
-    HIP_TRY(ensure(c->partials, (size_t)nw * kMlpMaxOut));
+    const int nb = mlp_blocks(ntot);
+    HIP_TRY(ensure(c->partials, (size_t)nb * kMlpMaxOut));
     HIP_TRY(ensure(c->fermi_w, kMlpMaxOut));
     const double dV = cg->L[0] * cg->L[1] * cg->L[2] / (double)ntot;
-    HIP_TRY(staged(c, MALA_STAGE_MLP_DOS, ntot, [&] {
-        return launch_mlp(c->stream, w->args, kModeDos, B, ntot, nullptr, c->partials.p, nw, nullptr, nullptr,
-                          nullptr);
-    }));
-    HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
-        return launch_fermi(c->stream, c->partials.p, nw, eg->n, dV, eg->e0, eg->de, kBoltzmannEv * T, ne,
-                            dos_out, c->fermi_w.p, result, c->li_coef);
-    }));
-    if (density_out)
-        HIP_TRY(staged(c, MALA_STAGE_MLP_DENSITY, ntot, [&] {
-            return launch_mlp(c->stream, w->args, kModeDensity, B, ntot, nullptr, nullptr, mlp_blocks(ntot),
-                              c->fermi_w.p, density_out, result);
+    const double kT = kBoltzmannEv * T;
+    MlpOut o;
+    o.partials = c->partials.p;
+    o.de = eg->de;
+    const bool window = density_out && c->density_mode == 0;
+    if (window) {
+        // E_F estimate from every kEstStride-th point -> energy window of the stored LDOS
+        const int64_t n_est = (ntot + kEstStride - 1) / kEstStride;
+        const int nbe = mlp_blocks(n_est);
+        const double margin = 0.3;                       // eV, covers the estimate's error
+        const int w_max = std::min(eg->n, (int)ceil(2.0 * (40.0 * kT + margin) / eg->de) + 3);
+        HIP_TRY(ensure(c->est_partials, (size_t)nbe * kMlpMaxOut));
+        HIP_TRY(ensure(c->window, (size_t)ntot * w_max));
+        HIP_TRY(ensure(c->prefix, (size_t)ntot));
+        MlpOut oe;
+        oe.partials = c->est_partials.p;
+        HIP_TRY(staged(c, MALA_STAGE_ESTIMATE, n_est, [&] {
+            hipError_t e = launch_mlp(c->stream, w->args, kModeDos, B, n_est, kEstStride, nbe, oe);
+            if (e != hipSuccess) return e;
+            return launch_fermi_estimate(c->stream, c->est_partials.p, nbe, eg->n, dV * kEstStride, eg->e0, eg->de,
+                                         kT, ne, c->win, c->li_coef, w_max, margin);
         }));
+        o.win = c->win;
+        o.window = c->window.p;
+        o.prefix = c->prefix.p;
+        HIP_TRY(staged(c, MALA_STAGE_MLP_DOS, ntot,
+                       [&] { return launch_mlp(c->stream, w->args, kModeDosWindow, B, ntot, 1, nb, o); }));
+    } else {
+        HIP_TRY(staged(c, MALA_STAGE_MLP_DOS, ntot,
+                       [&] { return launch_mlp(c->stream, w->args, kModeDos, B, ntot, 1, nb, o); }));
+    }
+    HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
+        return launch_fermi(c->stream, c->partials.p, nb, eg->n, dV, eg->e0, eg->de, kT, ne, dos_out, c->fermi_w.p,
+                            result, window ? c->win : nullptr, c->li_coef);
+    }));
+    if (density_out) {
+        if (window)
+            HIP_TRY(staged(c, MALA_STAGE_DENSITY_WINDOW, ntot, [&] {
+                return launch_density_window(c->stream, c->prefix.p, c->window.p, ntot, c->win, result,
+                                             c->fermi_w.p, density_out);
+            }));
+        else
+            HIP_TRY(set_covered(c, 0));
+        // recompute pass: a no-op on the device when the window covered E_F
+        MlpOut od;
+        od.fermi_w = c->fermi_w.p;
+        od.density = density_out;
+        od.res = static_cast<const ResultRec*>(static_cast<const void*>(result));
+        od.win = c->win;
+        HIP_TRY(staged(c, MALA_STAGE_MLP_DENSITY, ntot,
+                       [&] { return launch_mlp(c->stream, w->args, kModeDensity, B, ntot, 1, nb, od); }));
+    }
     return MALA_OK;
 }
 

@@ -21,13 +21,16 @@ namespace mala {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// Li_s(-y), s in {2, 3}, 0 <= y <= 1.  coef: [2][kLiTerms] Taylor
+// coefficients at y = 1, then [2][kLiPow] inverse powers 1/k^s.
 __device__ double li_neg(int s, double y, const double* __restrict__ coef) {
-    // Li_s(-y), s in {2, 3}, 0 <= y <= 1
     if (y <= 0.5) {
+        const double* ik = coef + 2 * kLiTerms + (s - 2) * kLiPow;
         double term = -y, sum = 0.0;
-        for (int k = 1; k <= 60; ++k) {
-            const double kk = (double)k;
-            sum += term / (s == 2 ? kk * kk : kk * kk * kk);
+        for (int k = 1; k < kLiPow; ++k) {
+            const double t = term * ik[k];
+            sum += t;
+            if (fabs(t) <= 1e-18 * fabs(sum)) break;
             term *= -y;
         }
         return sum;
@@ -56,26 +59,6 @@ __device__ void gfun(double x, const double* coef, double& g0, double& g1, doubl
     }
 }
 
-// Integrals over [e_i, e_i + de] of f and f*e against the two hat pieces:
-// (wl, wr) for int f (1-t), int f t and (vl, vr) for the e-weighted ones.
-__device__ void interval(double ea, double de, double mu, double kT, const double* coef, double& wl,
-                         double& wr, double& vl, double& vr) {
-    const double beta = 1.0 / kT;
-    const double xa = (ea - mu) * beta, xb = (ea + de - mu) * beta;
-    double a0, a1, a2, b0, b1, b2;
-    gfun(xa, coef, a0, a1, a2);
-    gfun(xb, coef, b0, b1, b2);
-    const double D = xb - xa;
-    const double I0 = (b0 - a0) * kT;
-    const double I1 = ((b1 - a1) - xa * (b0 - a0)) * kT / D;
-    const double K0 = (b1 - a1) * kT;
-    const double K1 = ((b2 - a2) - xa * (b1 - a1)) * kT / D;
-    wl = I0 - I1;
-    wr = I1;
-    vl = mu * (I0 - I1) + (K0 - K1) * kT;
-    vr = mu * I1 + K1 * kT;
-}
-
 // Fixed-shape tree sum over 256 threads.
 __device__ double block_sum(double v, double* red) {
     red[threadIdx.x] = v;
@@ -89,65 +72,137 @@ __device__ double block_sum(double v, double* red) {
     return r;
 }
 
+struct FermiShared {
+    double D[256], red[256], g0[256], g1[256], g2[256];
+};
+
+// Antiderivatives at every grid point for Fermi level mu (one per thread).
+__device__ void grid_g(FermiShared& sh, int n_e, double e0, double de, double mu, double kT, const double* coef,
+                       bool need_g2) {
+    const int e = threadIdx.x;
+    if (e < n_e) {
+        double g0, g1, g2;
+        gfun((e0 + e * de - mu) / kT, coef, g0, g1, g2);
+        sh.g0[e] = g0;
+        sh.g1[e] = g1;
+        sh.g2[e] = need_g2 ? g2 : 0.0;
+    }
+    __syncthreads();
+}
+
+// Hat-piece integrals over interval i = [e_i, e_i + de] from the shared G's:
+// wl = int f (1-t), wr = int f t; vl, vr the same with f*e.
+__device__ void interval(const FermiShared& sh, int i, double e0, double de, double mu, double kT, double& wl,
+                         double& wr, double& vl, double& vr) {
+    const double xa = (e0 + i * de - mu) / kT, D = de / kT;
+    const double d0 = sh.g0[i + 1] - sh.g0[i], d1 = sh.g1[i + 1] - sh.g1[i], d2 = sh.g2[i + 1] - sh.g2[i];
+    const double I0 = d0 * kT;
+    const double I1 = (d1 - xa * d0) * kT / D;
+    const double K0 = d1 * kT;
+    const double K1 = (d2 - xa * d1) * kT / D;
+    wl = I0 - I1;
+    wr = I1;
+    vl = mu * (I0 - I1) + (K0 - K1) * kT;
+    vr = mu * I1 + K1 * kT;
+}
+
+__device__ double electrons(FermiShared& sh, int n_e, double e0, double de, double mu, double kT,
+                            const double* coef) {
+    grid_g(sh, n_e, e0, de, mu, kT, coef, false);
+    const int e = threadIdx.x;
+    double c = 0.0;
+    if (e < n_e - 1) {
+        double wl, wr, vl, vr;
+        interval(sh, e, e0, de, mu, kT, wl, wr, vl, vr);
+        c = wl * sh.D[e] + wr * sh.D[e + 1];
+    }
+    return block_sum(c, sh.red);
+}
+
+// mode 0: exact solve (DOS, result, weights; window coverage if win != NULL)
+// mode 1: estimate from a subsample -> energy window for the stored LDOS
 __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partials, int n_parts, int n_e,
-                                               double dV, double e0, double de, double kT,
-                                               double n_target, double* __restrict__ dos_out,
-                                               double* __restrict__ w_out, ResultRec* __restrict__ res,
-                                               const double* __restrict__ coef) {
-    __shared__ double D[256], red[256], wl_s[256], wr_s[256], vl_s[256], vr_s[256];
+                                               double dV, double e0, double de, double kT, double n_target,
+                                               double* __restrict__ dos_out, double* __restrict__ w_out,
+                                               ResultRec* __restrict__ res, WindowRec* __restrict__ win,
+                                               const double* __restrict__ coef, int mode, int w_max,
+                                               double margin) {
+    __shared__ FermiShared sh;
     const int e = threadIdx.x;
     double d = 0.0;
     if (e < n_e) {
         for (int w = 0; w < n_parts; ++w) d += partials[(size_t)w * kMlpMaxOut + e];
         d *= dV;
-        dos_out[e] = d;
+        if (mode == 0) dos_out[e] = d;
     }
-    D[e] = d;
+    sh.D[e] = d;
     __syncthreads();
     const double elast = e0 + (n_e - 1) * de;
-    auto count = [&](double mu) {
-        double c = 0.0;
-        if (e < n_e - 1) {
-            double wl, wr, vl, vr;
-            interval(e0 + e * de, de, mu, kT, coef, wl, wr, vl, vr);
-            c = wl * D[e] + wr * D[e + 1];
-        }
-        return block_sum(c, red);
-    };
-    const double nlo = count(e0), nhi = count(elast);
-    if (!(nlo <= n_target && n_target <= nhi)) {
-        if (e < n_e) w_out[e] = 0.0;
+    const double nlo = electrons(sh, n_e, e0, de, e0, kT, coef);
+    const double nhi = electrons(sh, n_e, e0, de, elast, kT, coef);
+    const bool ok = nlo <= n_target && n_target <= nhi;
+    if (!ok) {
         if (e == 0) {
-            res->e_fermi = NAN;
-            res->e_band = NAN;
-            res->n_found = NAN;
-            res->n_target = n_target;
-            res->iterations = 0;
-            res->status = -4;
+            if (mode == 0) {
+                res->e_fermi = NAN;
+                res->e_band = NAN;
+                res->n_found = NAN;
+                res->n_target = n_target;
+                res->iterations = 0;
+                res->status = -4;
+                res->density_from_window = 0;
+                if (win) win->covered = 0;
+            } else {
+                win->lo = 0;
+                win->hi = n_e - 1;
+                win->valid = 0;
+                win->covered = 0;
+                win->e_fermi_est = NAN;
+            }
         }
+        if (mode == 0 && e < n_e) w_out[e] = 0.0;
         return;
     }
+    const double tol = mode == 0 ? 1e-12 : 1e-6;
     double lo = e0, hi = elast;
     int it = 0;
-    while (hi - lo >= 1e-12 && it < 200) {
+    while (hi - lo >= tol && it < 200) {
         const double mid = 0.5 * (lo + hi);
-        if (count(mid) < n_target) lo = mid;
+        if (electrons(sh, n_e, e0, de, mid, kT, coef) < n_target) lo = mid;
         else hi = mid;
         ++it;
     }
     const double ef = 0.5 * (lo + hi);
+    const double reach = 40.0 * kT;
+    if (mode == 1) {
+        if (e == 0) {
+            int wl = (int)floor((ef - reach - margin - e0) / de), wh = (int)ceil((ef + reach + margin - e0) / de);
+            wl = wl < 0 ? 0 : wl;
+            wh = wh > n_e - 1 ? n_e - 1 : wh;
+            win->lo = wl;
+            win->hi = wh;
+            win->valid = (wh - wl + 1) <= w_max ? 1 : 0;
+            win->covered = 0;
+            win->e_fermi_est = ef;
+        }
+        return;
+    }
+    grid_g(sh, n_e, e0, de, ef, kT, coef, true);
     double wl = 0, wr = 0, vl = 0, vr = 0;
-    if (e < n_e - 1) interval(e0 + e * de, de, ef, kT, coef, wl, wr, vl, vr);
-    wl_s[e] = wl; wr_s[e] = wr; vl_s[e] = vl; vr_s[e] = vr;
+    if (e < n_e - 1) interval(sh, e, e0, de, ef, kT, wl, wr, vl, vr);
+    __syncthreads();
+    // reuse the g arrays for the per-interval pieces
+    sh.g0[e] = wr;
+    sh.g1[e] = vr;
     __syncthreads();
     double we = 0.0, ve = 0.0;
     if (e < n_e) {
-        if (e < n_e - 1) { we += wl_s[e]; ve += vl_s[e]; }
-        if (e >= 1) { we += wr_s[e - 1]; ve += vr_s[e - 1]; }
+        if (e < n_e - 1) { we += wl; ve += vl; }
+        if (e >= 1) { we += sh.g0[e - 1]; ve += sh.g1[e - 1]; }
         w_out[e] = we;
     }
-    const double nf = block_sum(we * D[e], red);
-    const double eb = block_sum(ve * D[e], red);
+    const double nf = block_sum(we * sh.D[e], sh.red);
+    const double eb = block_sum(ve * sh.D[e], sh.red);
     if (e == 0) {
         res->e_fermi = ef;
         res->e_band = eb;
@@ -155,6 +210,34 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
         res->n_target = n_target;
         res->iterations = it;
         res->status = 0;
+        res->density_from_window = 0;
+        if (win) {
+            const bool lo_ok = win->lo == 0 || e0 + win->lo * de <= ef - reach;
+            const bool hi_ok = win->hi == n_e - 1 || e0 + win->hi * de >= ef + reach;
+            win->covered = (win->valid && lo_ok && hi_ok) ? 1 : 0;
+            res->density_from_window = win->covered;
+        }
+    }
+}
+
+// n(p) = prefix(p) + sum over the stored window of w_e d_e(p), when the
+// window covers E_F +- 40 kT (outside it the Fermi weights equal the full
+// trapezoid weights or vanish to within e^-40).
+__global__ __launch_bounds__(256) void k_density_window(const double* __restrict__ prefix,
+                                                        const float* __restrict__ window, int64_t n_pts,
+                                                        const WindowRec* __restrict__ win,
+                                                        const ResultRec* __restrict__ res,
+                                                        const double* __restrict__ w, double* __restrict__ dens) {
+    if (res->status != 0 || !win->covered) return;
+    __shared__ double sw[kMlpMaxOut];
+    const int lo = win->lo, W = win->hi - win->lo + 1;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) sw[i] = w[lo + i];
+    __syncthreads();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pts; p += (int64_t)gridDim.x * blockDim.x) {
+        double s = prefix[p];
+        const float* row = window + p * W;
+        for (int i = 0; i < W; ++i) s += sw[i] * (double)row[i];
+        dens[p] = s;
     }
 }
 
@@ -193,9 +276,28 @@ __global__ __launch_bounds__(256) void k_density_ldos(const float* __restrict__ 
 
 hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int n_e, double dV, double e0,
                         double de, double kT, double n_target, double* dos_out, double* weights_out,
-                        void* result, const double* li_coef) {
+                        void* result, WindowRec* win, const double* li_coef) {
     hipLaunchKernelGGL(k_fermi, dim3(1), dim3(256), 0, s, partials, n_parts, n_e, dV, e0, de, kT, n_target,
-                       dos_out, weights_out, static_cast<ResultRec*>(result), li_coef);
+                       dos_out, weights_out, static_cast<ResultRec*>(result), win, li_coef, 0, 0, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fermi_estimate(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
+                                 double e0, double de, double kT, double n_target, WindowRec* win,
+                                 const double* li_coef, int w_max, double margin) {
+    hipLaunchKernelGGL(k_fermi, dim3(1), dim3(256), 0, s, partials, n_parts, n_e, dV, e0, de, kT, n_target,
+                       nullptr, nullptr, nullptr, win, li_coef, 1, w_max, margin);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_window(hipStream_t s, const double* prefix, const float* window, int64_t n_pts,
+                                 const WindowRec* win, const void* result, const double* weights,
+                                 double* density) {
+    int64_t blocks = (n_pts + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_density_window, dim3((unsigned)blocks), dim3(256), 0, s, prefix, window, n_pts, win,
+                       static_cast<const ResultRec*>(result), weights, density);
     return hipGetLastError();
 }
 
@@ -215,11 +317,15 @@ hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_
     return hipGetLastError();
 }
 
-// Taylor coefficients of Li_s(-e^t) about t = 0 for s = 2, 3:
+// Taylor coefficients of Li_s(-e^t) about t = 0 for s = 2, 3, then the
+// inverse powers 1/k^s used by the power series:
 // c_{s,n} = Li_{s-n}(-1)/n! = -eta(s-n)/n!, with eta(1) = ln 2,
 // eta(2) = pi^2/12, eta(3) = 3 zeta(3)/4 and, for m >= 0,
 // eta(-m) = (2^(m+1) - 1) B_{m+1}/(m+1) (B_1 = +1/2; B_{2k} from zeta(2k)).
 void polylog_coefficients(double* coef) {
+    for (int si = 0; si < 2; ++si)
+        for (int k = 0; k < kLiPow; ++k)
+            coef[2 * kLiTerms + si * kLiPow + k] = k == 0 ? 0.0 : pow((double)k, -(double)(2 + si));
     auto zeta_even = [](int n) {     // zeta(n), n >= 2 even: sum plus integral tail
         if (n == 2) return kPi * kPi / 6.0;
         const int K = 2000;

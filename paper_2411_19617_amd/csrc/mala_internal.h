@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -95,25 +96,49 @@ struct MlpArgs {
     const float* out_shift;
 };
 
-enum MlpMode { kModeLdos = 0, kModeDos = 1, kModeDensity = 2 };
+enum MlpMode { kModeLdos = 0, kModeDos = 1, kModeDensity = 2, kModeDosWindow = 3 };
+constexpr size_t kMlpLdsBudget = 155000;   // dynamic LDS of one network block
 
 // Mirrors mala_result of include/mala.h.
 struct ResultRec {
     double e_fermi, e_band, n_found, n_target;
-    int32_t iterations, status, reserved[2];
+    int32_t iterations, status, density_from_window, reserved;
+};
+
+// Energy window of the stored LDOS (device scratch).
+struct WindowRec {
+    int32_t lo, hi, valid, covered;
+    double e_fermi_est;
+};
+
+struct MlpOut {
+    float* ldos = nullptr;            // LDOS mode
+    double* partials = nullptr;       // DOS modes: [blocks][kMlpMaxOut]
+    const double* fermi_w = nullptr;  // density mode
+    double* density = nullptr;
+    const ResultRec* res = nullptr;
+    const WindowRec* win = nullptr;   // window / density modes
+    float* window = nullptr;          // [n][hi-lo+1]
+    double* prefix = nullptr;         // [n]
+    double de = 0.0;
 };
 
 int mlp_blocks(int64_t n_pts);
-hipError_t launch_mlp(hipStream_t s, const MlpArgs& a, int mode, const float* B, int64_t n_pts,
-                      float* ldos_out, double* dos_partials, int n_blocks, const double* fermi_w,
-                      double* density_out, const void* result);
+hipError_t launch_mlp(hipStream_t s, const MlpArgs& a, int mode, const float* B, int64_t n_pts, int row_stride,
+                      int n_blocks, const MlpOut& o);
 
 hipError_t launch_ldos_colsum(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
                               double* partials, int n_blocks);
 
 hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
                         double e0, double de, double kT, double n_target, double* dos_out,
-                        double* weights_out, void* result, const double* li_coef);
+                        double* weights_out, void* result, WindowRec* win, const double* li_coef);
+hipError_t launch_fermi_estimate(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
+                                 double e0, double de, double kT, double n_target, WindowRec* win,
+                                 const double* li_coef, int w_max, double margin);
+hipError_t launch_density_window(hipStream_t s, const double* prefix, const float* window, int64_t n_pts,
+                                 const WindowRec* win, const void* result, const double* weights,
+                                 double* density);
 
 hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
                                     const double* weights, const void* result, double* density);
@@ -121,7 +146,9 @@ hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_
 // Host-side tables.
 int build_cg_table(int twojmax, float* table, int* offsets, int cap);
 void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride);
-void polylog_coefficients(double* coef);   // [2][kLiTerms] Taylor coefficients at x=0
 constexpr int kLiTerms = 32;
+constexpr int kLiPow = 64;
+constexpr int kLiCoef = 2 * kLiTerms + 2 * kLiPow;
+void polylog_coefficients(double* coef);   // [kLiCoef]: Taylor coefficients at y=1, inverse powers
 
 }  // namespace mala

@@ -1,25 +1,27 @@
 // Per-point feed-forward network (Sec. 2.4, Eq. ffnn) on MFMA, with the LDOS
 // reductions of Sec. 2.3 / 3.4 fused into the output epilogue.
 //
-// Each block of 8 waves takes 32 grid points at a time from its fixed,
+// A block of 8 waves takes NP = 16*NT grid points at a time from its fixed,
 // contiguous range.  Layers are computed transposed, H_out^T = W H_in^T:
-// output units are the MFMA M dimension, the points the N dimension (two
-// 16-point tiles).  Wave (mg, ng) of the 4 x 2 wave grid owns the M-tiles
-// mg, mg+4, ... of every layer for point tile ng.  Activations live in LDS
-// as [point][unit] rows padded to a stride of 4 (mod 64) dwords, so the B
-// operand reads and the result writes are free of bank conflicts; weights
-// are streamed from L2 in MFMA lane order (packed once at load time).
-// Layer 2 is produced four M-tiles at a time and consumed by layer 3 at
-// once, so only layer 1's activations stay resident.
+// output units are the MFMA M dimension, the points the N dimension (NT
+// tiles of 16).  Wave w owns M-tiles w, w+8, ... for all NT point tiles, so
+// every weight operand fetched from L2 feeds NT MFMAs; the tiles left over
+// after the full rounds are split as (M-tile, point-tile) items so the waves
+// stay balanced.  Weights stream through a small register ring (prefetch).
+// Activations live in LDS as [point][unit] rows with a stride of 4 (mod 64)
+// dwords (conflict-free B-operand reads and result writes).  Layer 2 is
+// produced eight M-tiles at a time and consumed by layer 3 at once.
 //
-// Epilogues (one per mode):
-//   LDOS    -- d = out_scale * y + out_shift stored as float32 [n][n_e];
-//   DOS     -- d summed over the 16 points of a tile in FP64 (lane shuffles)
-//              into a per-block FP64 row in LDS; each block writes one partial
-//              row for its fixed range, so the later fixed-order sum is
-//              deterministic;
-//   DENSITY -- n(p) = sum_e w_e d_e(p) in FP64 with the Fermi weights of the
-//              solved E_F, reduced over lane groups and the four M-groups.
+// Epilogues:
+//   LDOS       d = out_scale*y + out_shift stored as float32 [n][n_e]
+//   DOS        d summed over points in FP64 into a per-block FP64 row
+//              (fixed assignment: deterministic); optional row stride to run
+//              on a strided subsample of the points
+//   DOS_WINDOW DOS as above, plus per point the FP64 prefix sum of the fully
+//              occupied part sum_{e<lo} tw_e d_e and the float32 LDOS values
+//              of the energy window [lo, hi] around the estimated E_F
+//   DENSITY    n(p) = sum_e w_e d_e(p) (FP64) with the solved Fermi weights;
+//              runs only when the stored window did not cover E_F.
 #include "mala_internal.h"
 
 namespace mala {
@@ -28,9 +30,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNP = 32;         // points per block iteration
-constexpr int kWaves = 8;       // 4 M-groups x 2 point tiles
-constexpr int kChunk = 4;       // layer-2 M-tiles per chunk (one per M-group)
+constexpr int kWaves = 8;
 
 __device__ __forceinline__ float leaky(float x, float s) { return x < 0.f ? s * x : x; }
 __device__ __forceinline__ f4 act4(f4 v, float s) {
@@ -41,31 +41,36 @@ __device__ __forceinline__ f4 bias4(const float* b, int off) {
     return f4{v.x, v.y, v.z, v.w};
 }
 
-// Precision traits: element type in LDS, K per MFMA, operand loads.
 template <int PREC>
 struct Prec;
 
 template <>
 struct Prec<0> {
     using T = float;
+    using AT = float;
     static constexpr int K = 4;
-    // row stride (elements) for a width w: >= w, and stride/dword = 4 mod 64
-    __device__ static int stride(int w) { return ((w + 63) / 64) * 64 + 4; }
-    __device__ static f4 mma(const void* A, size_t idx, const T* row, int k0, f4 c) {
-        const float a = static_cast<const float*>(A)[idx];
+    static constexpr int PF = 8;
+    __host__ __device__ static int stride(int w) { return ((w + 63) / 64) * 64 + 4; }
+    __device__ static AT loadA(const void* A, size_t idx) { return static_cast<const float*>(A)[idx]; }
+    __device__ static f4 mma(AT a, const T* row, int k0, f4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, row[k0], c, 0, 0, 0);
     }
-    __device__ static void store4(T* dst, f4 v) { *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]); }
+    __device__ static void store4(T* dst, f4 v) {
+        *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+    }
     __device__ static T cvt(float x) { return x; }
+    __device__ static int kofs(int s, int g) { return 4 * s + g; }
 };
 
 template <>
 struct Prec<1> {
     using T = __bf16;
+    using AT = uint4;
     static constexpr int K = 32;
-    __device__ static int stride(int w) { return ((w + 127) / 128) * 128 + 8; }
-    __device__ static f4 mma(const void* A, size_t idx, const T* row, int k0, f4 c) {
-        const uint4 av = static_cast<const uint4*>(A)[idx];
+    static constexpr int PF = 4;
+    __host__ __device__ static int stride(int w) { return ((w + 127) / 128) * 128 + 8; }
+    __device__ static AT loadA(const void* A, size_t idx) { return static_cast<const uint4*>(A)[idx]; }
+    __device__ static f4 mma(AT av, const T* row, int k0, f4 c) {
         bf8 a, b;
         __builtin_memcpy(&a, &av, 16);
         const uint4 bv = *reinterpret_cast<const uint4*>(row + k0);
@@ -77,196 +82,271 @@ struct Prec<1> {
         *reinterpret_cast<bf4*>(dst) = h;
     }
     __device__ static T cvt(float x) { return (__bf16)x; }
+    __device__ static int kofs(int s, int g) { return 32 * s + 8 * g; }
 };
 
-// k offset of lane group g inside K-step s: fp32 -> 4s + g, bf16 -> 32s + 8g
-template <int PREC>
-__device__ __forceinline__ int kofs(int s, int g) {
-    return PREC == 0 ? 4 * s + g : 32 * s + 8 * g;
-}
-
-template <int PREC, int MODE>
-__global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __restrict__ B, int64_t n_pts,
-                                                     float* __restrict__ ldos, double* __restrict__ partials,
-                                                     int n_blocks, const double* __restrict__ fermi_w,
-                                                     double* __restrict__ density,
-                                                     const ResultRec* __restrict__ res) {
+// acc[n] += sum over K-steps s < KS of A(s) * B_n(s), A streamed from global
+// through a prefetch ring, B_n read from LDS row rows[n].
+template <int PREC, int NA>
+__device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const typename Prec<PREC>::T* const (&rows)[NA],
+                                      int g, f4 (&acc)[NA]) {
     using P = Prec<PREC>;
-    using T = typename P::T;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double s_dos[2][kMlpMaxOut];
-    __shared__ double s_dens[4][kNP];
-    __shared__ double s_ws[kMlpMaxOut];
-    __shared__ double s_wc;
-
-    if constexpr (MODE == kModeDensity) {
-        if (res->status != 0) return;     // no Fermi level: density not written
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = lane & 15, g = lane >> 4;
-    const int mg = wave & 3, ng = wave >> 2;
-
-    const int xs = P::stride(a.in_pad), hs = P::stride(a.h1_tiles * 16), cs = P::stride(kChunk * 16);
-    T* X0 = reinterpret_cast<T*>(smem);
-    T* H1 = X0 + kNP * xs;
-    T* H2 = H1 + kNP * hs;
-
-    if constexpr (MODE == kModeDensity) {
-        for (int e = threadIdx.x; e < kMlpMaxOut; e += blockDim.x)
-            s_ws[e] = e < a.n_out ? fermi_w[e] * (double)a.out_scale[e] : 0.0;
-        if (threadIdx.x == 0) {
-            double c = 0.0;
-            for (int e = 0; e < a.n_out; ++e) c += fermi_w[e] * (double)a.out_shift[e];
-            s_wc = c;
+    typename P::AT ring[P::PF];
+#pragma unroll
+    for (int p = 0; p < P::PF; ++p)
+        if (p < KS) ring[p] = P::loadA(A, base + (size_t)p * 64);
+    for (int s0 = 0; s0 < KS; s0 += P::PF) {
+#pragma unroll
+        for (int p = 0; p < P::PF; ++p) {
+            const int s = s0 + p;
+            if (s < KS) {
+                const typename P::AT a = ring[p];
+                if (s + P::PF < KS) ring[p] = P::loadA(A, base + (size_t)(s + P::PF) * 64);
+#pragma unroll
+                for (int n = 0; n < NA; ++n) acc[n] = P::mma(a, rows[n], P::kofs(s, g), acc[n]);
+            }
         }
     }
-    if constexpr (MODE == kModeDos)
-        for (int e = threadIdx.x; e < 2 * kMlpMaxOut; e += blockDim.x) (&s_dos[0][0])[e] = 0.0;
+}
+
+// One dense layer on the waves of the block: out[p][16 mt + u] = act(W x + b).
+// in: LDS rows (stride is), out: LDS rows (stride os) at column offset out_col
+// for tile mt (out_col(mt) = 16 * (mt - tile_base)).
+template <int PREC, int NT>
+__device__ __forceinline__ void layer(const void* W, const float* bias, int tiles, int tile_base, int KS,
+                                      const typename Prec<PREC>::T* in, int is, typename Prec<PREC>::T* out,
+                                      int os, float slope, int wave, int lane) {
+    using P = Prec<PREC>;
+    using T = typename P::T;
+    const int j = lane & 15, g = lane >> 4;
+    const int full = (tiles / kWaves) * kWaves;
+    for (int mt = wave; mt < full; mt += kWaves) {
+        f4 acc[NT];
+        const f4 b = bias4(bias, 16 * (tile_base + mt) + 4 * g);
+        const T* rows[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            acc[n] = b;
+            rows[n] = in + (16 * n + j) * is;
+        }
+        kloop<PREC, NT>(W, (size_t)(tile_base + mt) * KS * 64 + lane, KS, rows, g, acc);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) P::store4(out + (16 * n + j) * os + 16 * mt + 4 * g, act4(acc[n], slope));
+    }
+    const int rem_items = (tiles - full) * NT;
+    for (int it = wave; it < rem_items; it += kWaves) {
+        const int mt = full + it / NT, n = it % NT;
+        f4 acc[1] = {bias4(bias, 16 * (tile_base + mt) + 4 * g)};
+        const T* rows[1] = {in + (16 * n + j) * is};
+        kloop<PREC, 1>(W, (size_t)(tile_base + mt) * KS * 64 + lane, KS, rows, g, acc);
+        P::store4(out + (16 * n + j) * os + 16 * mt + 4 * g, act4(acc[0], slope));
+    }
+}
+
+template <int PREC, int MODE, int NT>
+__global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __restrict__ B, int64_t n_pts,
+                                                     int row_stride, MlpOut o) {
+    using P = Prec<PREC>;
+    using T = typename P::T;
+    constexpr int NP = 16 * NT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double s_dos[kMlpMaxOut];
+    __shared__ double s_part[kWaves][NP];
+    __shared__ double s_w[kMlpMaxOut];
+    __shared__ double s_c;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    int lo = 0, W = 0;
+    if constexpr (MODE == kModeDensity) {
+        if (o.res->status != 0 || o.win->covered) return;      // nothing to recompute
+    }
+    if constexpr (MODE == kModeDosWindow) {
+        lo = o.win->lo;
+        W = o.win->valid ? o.win->hi - o.win->lo + 1 : 0;
+    }
+    const int xs = P::stride(a.in_pad), hs = P::stride(a.h1_tiles * 16), cs = P::stride(128);
+    T* H1 = reinterpret_cast<T*>(smem);
+    T* X0 = H1 + NP * hs;          // layer-1 input, later the layer-2 chunk
+    T* H2 = X0;
+
+    if constexpr (MODE == kModeDensity || MODE == kModeDosWindow) {
+        // weights of the per-point energy sum: density -> w_e*s_e (+ sum w_e c_e),
+        // window prefix -> trapezoid weight de (de/2 at e = 0) below lo
+        for (int e = threadIdx.x; e < kMlpMaxOut; e += blockDim.x) {
+            double we = 0.0;
+            if (MODE == kModeDensity) we = e < a.n_out ? o.fermi_w[e] : 0.0;
+            else we = (e < lo) ? (e == 0 ? 0.5 * o.de : o.de) : 0.0;
+            s_w[e] = we;
+        }
+        if (threadIdx.x == 0 && MODE == kModeDensity) {
+            double c = 0.0;
+            for (int e = 0; e < a.n_out; ++e) c += o.fermi_w[e] * (double)a.out_shift[e];
+            s_c = c;
+        }
+    }
+    if constexpr (MODE == kModeDos || MODE == kModeDosWindow)
+        for (int e = threadIdx.x; e < kMlpMaxOut; e += blockDim.x) s_dos[e] = 0.0;
     __syncthreads();
 
-    const int64_t n_it = (n_pts + kNP - 1) / kNP;
-    const int64_t it_begin = n_it * blockIdx.x / n_blocks, it_end = n_it * (blockIdx.x + 1) / n_blocks;
+    const int64_t n_it = (n_pts + NP - 1) / NP;
+    const int nb = gridDim.x;
+    const int64_t it_begin = n_it * blockIdx.x / nb, it_end = n_it * (blockIdx.x + 1) / nb;
     const int KS1 = a.in_pad / P::K, KS2 = a.h1_tiles * 16 / P::K, KS3 = a.h2_tiles * 16 / P::K;
     const int n_in = a.n_in;
 
     for (int64_t it = it_begin; it < it_end; ++it) {
-        const int64_t p0 = it * kNP;
-        const int rows = (int)((n_pts - p0) < kNP ? (n_pts - p0) : kNP);
-        // ---- x0 = (B - mean)/std, zero padded, for the block's 32 points
-        for (int e = threadIdx.x; e < kNP * a.in_pad; e += blockDim.x) {
+        const int64_t p0 = it * NP;
+        const int rows = (int)((n_pts - p0) < NP ? (n_pts - p0) : NP);
+        for (int e = threadIdx.x; e < NP * a.in_pad; e += blockDim.x) {
             const int pj = e / a.in_pad, k = e - pj * a.in_pad;
             float v = 0.f;
-            if (pj < rows && k < n_in) v = (B[(p0 + pj) * n_in + k] - a.in_mean[k]) * a.in_rstd[k];
+            if (pj < rows && k < n_in)
+                v = (B[(p0 + pj) * row_stride * n_in + k] - a.in_mean[k]) * a.in_rstd[k];
             X0[pj * xs + k] = P::cvt(v);
         }
         __syncthreads();
-        // ---- layer 1
-        const T* xrow = X0 + (16 * ng + j) * xs;
-        for (int mt = mg; mt < a.h1_tiles; mt += 4) {
-            f4 acc = bias4(a.b1, 16 * mt + 4 * g);
-            const size_t base = (size_t)mt * KS1 * 64 + lane;
-#pragma unroll 4
-            for (int s = 0; s < KS1; ++s) acc = P::mma(a.W1, base + (size_t)s * 64, xrow, kofs<PREC>(s, g), acc);
-            P::store4(H1 + (16 * ng + j) * hs + 16 * mt + 4 * g, act4(acc, a.slope));
-        }
+        layer<PREC, NT>(a.W1, a.b1, a.h1_tiles, 0, KS1, X0, xs, H1, hs, a.slope, wave, lane);
         __syncthreads();
-        // ---- layer 2 in chunks of 4 M-tiles, consumed by layer 3 at once
-        f4 acc3[4];
-        for (int i = 0; i < 4; ++i) {
-            const int ot = mg + 4 * i;
-            acc3[i] = ot < a.out_tiles ? bias4(a.b3, 16 * ot + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
-        }
-        const T* hrow = H1 + (16 * ng + j) * hs;
-        const T* crow = H2 + (16 * ng + j) * cs;
-        for (int c0 = 0; c0 < a.h2_tiles; c0 += kChunk) {
-            const int mt = c0 + mg;
-            if (mt < a.h2_tiles) {
-                f4 acc = bias4(a.b2, 16 * mt + 4 * g);
-                const size_t base = (size_t)mt * KS2 * 64 + lane;
-#pragma unroll 4
-                for (int s = 0; s < KS2; ++s) acc = P::mma(a.W2, base + (size_t)s * 64, hrow, kofs<PREC>(s, g), acc);
-                P::store4(H2 + (16 * ng + j) * cs + 16 * mg + 4 * g, act4(acc, a.slope));
-            } else {
-                P::store4(H2 + (16 * ng + j) * cs + 16 * mg + 4 * g, f4{0.f, 0.f, 0.f, 0.f});
-            }
-            __syncthreads();
-            const int ks0 = c0 * 16 / P::K, ksn = kChunk * 16 / P::K;
-            for (int i = 0; i < 4; ++i) {
-                const int ot = mg + 4 * i;
-                if (ot >= a.out_tiles) break;
-                const size_t base = ((size_t)ot * KS3 + ks0) * 64 + lane;
+
+        // layer 2 in chunks of 8 M-tiles, each consumed by layer 3 at once
+        f4 acc3[2][NT];
 #pragma unroll
-                for (int s = 0; s < ksn; ++s) {
-                    if (ks0 + s < KS3) acc3[i] = P::mma(a.W3, base + (size_t)s * 64, crow, kofs<PREC>(s, g), acc3[i]);
-                }
+        for (int i = 0; i < 2; ++i) {
+            const int ot = wave + kWaves * i;
+            const f4 b = ot < a.out_tiles ? bias4(a.b3, 16 * ot + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc3[i][n] = b;
+        }
+        for (int c0 = 0; c0 < a.h2_tiles; c0 += 8) {
+            const int ct = (a.h2_tiles - c0) < 8 ? (a.h2_tiles - c0) : 8;
+            layer<PREC, NT>(a.W2, a.b2, ct, c0, KS2, H1, hs, H2, cs, a.slope, wave, lane);
+            __syncthreads();
+            const int ks0 = c0 * 16 / P::K, ksn = ct * 16 / P::K;
+            const T* rows[NT];
+#pragma unroll
+            for (int n = 0; n < NT; ++n) rows[n] = H2 + (16 * n + j) * cs;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int ot = wave + kWaves * i;
+                if (ot < a.out_tiles) kloop<PREC, NT>(a.W3, ((size_t)ot * KS3 + ks0) * 64 + lane, ksn, rows, g, acc3[i]);
             }
             __syncthreads();
         }
+
         // ---- epilogue
-        const int64_t p = p0 + 16 * ng + j;
-        const bool pv = p < n_pts;
-        double dens = 0.0;
-        for (int i = 0; i < 4; ++i) {
-            const int ot = mg + 4 * i;
+        double part[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) part[n] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int ot = wave + kWaves * i;
             if (ot >= a.out_tiles) break;
-            const f4 y = a.out_act ? act4(acc3[i], a.slope) : acc3[i];
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int e = 16 * ot + 4 * g + r;
                 const bool ev = e < a.n_out;
-                if constexpr (MODE == kModeLdos) {
-                    if (pv && ev) ldos[p * a.n_out + e] = a.out_scale[e] * y[r] + a.out_shift[e];
-                } else if constexpr (MODE == kModeDos) {
-                    double d = (pv && ev) ? (double)a.out_scale[e] * (double)y[r] + (double)a.out_shift[e] : 0.0;
-                    d += __shfl_xor(d, 1, 16);
-                    d += __shfl_xor(d, 2, 16);
-                    d += __shfl_xor(d, 4, 16);
-                    d += __shfl_xor(d, 8, 16);
-                    if (j == 0 && ev) s_dos[ng][e] += d;
-                } else {
-                    if (ev) dens += s_ws[e] * (double)y[r];
+                const double sc = ev ? (double)a.out_scale[e] : 0.0, sh = ev ? (double)a.out_shift[e] : 0.0;
+                double dsum = 0.0;
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const int64_t p = p0 + 16 * n + j;
+                    const bool pv = (16 * n + j) < rows;
+                    float yv = acc3[i][n][r];
+                    if (a.out_act) yv = leaky(yv, a.slope);
+                    if constexpr (MODE == kModeLdos) {
+                        if (pv && ev) o.ldos[p * a.n_out + e] = a.out_scale[e] * yv + a.out_shift[e];
+                    } else if constexpr (MODE == kModeDensity) {
+                        if (ev) part[n] += s_w[e] * (sc * (double)yv);
+                    } else {
+                        const double d = (pv && ev) ? sc * (double)yv + sh : 0.0;
+                        dsum += d;
+                        if constexpr (MODE == kModeDosWindow) {
+                            part[n] += s_w[e] * d;
+                            if (pv && e >= lo && e < lo + W) o.window[p * W + (e - lo)] = (float)d;
+                        }
+                    }
+                }
+                if constexpr (MODE == kModeDos || MODE == kModeDosWindow) {
+                    dsum += __shfl_xor(dsum, 1, 16);
+                    dsum += __shfl_xor(dsum, 2, 16);
+                    dsum += __shfl_xor(dsum, 4, 16);
+                    dsum += __shfl_xor(dsum, 8, 16);
+                    if (j == 0 && ev) s_dos[e] += dsum;
                 }
             }
         }
-        if constexpr (MODE == kModeDensity) {
-            dens += __shfl_xor(dens, 16, 64);
-            dens += __shfl_xor(dens, 32, 64);
-            if (g == 0) s_dens[mg][16 * ng + j] = dens;
+        if constexpr (MODE == kModeDensity || MODE == kModeDosWindow) {
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                double v = part[n];
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                if (g == 0) s_part[wave][16 * n + j] = v;
+            }
             __syncthreads();
-            if (threadIdx.x < kNP) {
+            if (threadIdx.x < NP && (int)threadIdx.x < rows) {
+                double v = 0.0;
+                for (int w = 0; w < kWaves; ++w) v += s_part[w][threadIdx.x];
                 const int64_t q = p0 + threadIdx.x;
-                if (q < n_pts)
-                    density[q] = ((s_dens[0][threadIdx.x] + s_dens[1][threadIdx.x]) +
-                                  (s_dens[2][threadIdx.x] + s_dens[3][threadIdx.x])) + s_wc;
+                if constexpr (MODE == kModeDensity) o.density[q] = v + s_c;
+                else o.prefix[q] = v;
             }
         }
         __syncthreads();
     }
-    if constexpr (MODE == kModeDos) {
+    if constexpr (MODE == kModeDos || MODE == kModeDosWindow) {
         for (int e = threadIdx.x; e < kMlpMaxOut; e += blockDim.x)
-            partials[(size_t)blockIdx.x * kMlpMaxOut + e] = s_dos[0][e] + s_dos[1][e];
+            o.partials[(size_t)blockIdx.x * kMlpMaxOut + e] = s_dos[e];
     }
 }
 
-template <int PREC>
+template <int PREC, int NT>
 static size_t lds_bytes(const MlpArgs& a) {
+    using P = Prec<PREC>;
     const size_t el = PREC == 0 ? 4 : 2;
-    auto stride = [&](int w) {
-        return PREC == 0 ? (size_t)(((w + 63) / 64) * 64 + 4) : (size_t)(((w + 127) / 128) * 128 + 8);
-    };
-    return el * kNP * (stride(a.in_pad) + stride(a.h1_tiles * 16) + stride(kChunk * 16));
+    const size_t x = (size_t)std::max(P::stride(a.in_pad), P::stride(128));
+    return el * 16 * NT * ((size_t)P::stride(a.h1_tiles * 16) + x);
 }
 
-template <int PREC, int MODE>
-static hipError_t launch_pm(hipStream_t s, const MlpArgs& a, const float* B, int64_t n_pts, float* ldos,
-                            double* partials, int n_blocks, const double* fermi_w, double* density,
-                            const ResultRec* res) {
-    const size_t lds = lds_bytes<PREC>(a);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp<PREC, MODE>),
+template <int PREC, int MODE, int NT>
+static hipError_t launch_pmn(hipStream_t s, const MlpArgs& a, const float* B, int64_t n_pts, int row_stride,
+                             int n_blocks, const MlpOut& o) {
+    const size_t lds = lds_bytes<PREC, NT>(a);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp<PREC, MODE, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_mlp<PREC, MODE>), dim3(n_blocks), dim3(kWaves * 64), lds, s, a, B, n_pts, ldos,
-                       partials, n_blocks, fermi_w, density, res);
+    hipLaunchKernelGGL((k_mlp<PREC, MODE, NT>), dim3(n_blocks), dim3(kWaves * 64), lds, s, a, B, n_pts,
+                       row_stride, o);
     return hipGetLastError();
 }
 
+// 64 points per block when the activations fit next to the epilogue's static
+// LDS, else 32.
+template <int PREC, int MODE>
+static hipError_t launch_pm(hipStream_t s, const MlpArgs& a, const float* B, int64_t n_pts, int row_stride,
+                            int n_blocks, const MlpOut& o) {
+    if (lds_bytes<PREC, 4>(a) <= kMlpLdsBudget) return launch_pmn<PREC, MODE, 4>(s, a, B, n_pts, row_stride, n_blocks, o);
+    return launch_pmn<PREC, MODE, 2>(s, a, B, n_pts, row_stride, n_blocks, o);
+}
+
 int mlp_blocks(int64_t n_pts) {
-    const int64_t it = (n_pts + kNP - 1) / kNP;
+    const int64_t it = (n_pts + 63) / 64;
     return (int)(it < kMlpBlocks ? (it > 0 ? it : 1) : kMlpBlocks);
 }
 
-hipError_t launch_mlp(hipStream_t s, const MlpArgs& a, int mode, const float* B, int64_t n_pts,
-                      float* ldos_out, double* dos_partials, int n_blocks, const double* fermi_w,
-                      double* density_out, const void* result) {
+hipError_t launch_mlp(hipStream_t s, const MlpArgs& a, int mode, const float* B, int64_t n_pts, int row_stride,
+                      int n_blocks, const MlpOut& o) {
     if (n_pts <= 0 || n_blocks <= 0) return hipSuccess;
-    const ResultRec* res = static_cast<const ResultRec*>(result);
-#define MALA_MLP_CASE(P, M) \
-    return launch_pm<P, M>(s, a, B, n_pts, ldos_out, dos_partials, n_blocks, fermi_w, density_out, res)
+#define MALA_MLP_CASE(P, M) return launch_pm<P, M>(s, a, B, n_pts, row_stride, n_blocks, o)
     if (a.precision == 0) {
         if (mode == kModeLdos) MALA_MLP_CASE(0, kModeLdos);
         if (mode == kModeDos) MALA_MLP_CASE(0, kModeDos);
+        if (mode == kModeDosWindow) MALA_MLP_CASE(0, kModeDosWindow);
         if (mode == kModeDensity) MALA_MLP_CASE(0, kModeDensity);
     } else {
         if (mode == kModeLdos) MALA_MLP_CASE(1, kModeLdos);
         if (mode == kModeDos) MALA_MLP_CASE(1, kModeDos);
+        if (mode == kModeDosWindow) MALA_MLP_CASE(1, kModeDosWindow);
         if (mode == kModeDensity) MALA_MLP_CASE(1, kModeDensity);
     }
 #undef MALA_MLP_CASE

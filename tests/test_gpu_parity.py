@@ -273,6 +273,25 @@ def test_predict_precision_form(ctx, mala, case, torch):
     _check_full(ctx, mala, torch, snap, net, gold, mala.PREC_BF16, 1.0, 5e-2, 5e-2)
 
 
+@pytest.mark.parametrize("case", ["small", "paper_liquid"])
+def test_density_window_equals_recompute(ctx, mala, case, torch):
+    snap = getattr(mala_synth, case)()
+    net = mala_synth.small_net() if case == "small" else mala_synth.paper_net()
+    w = ctx.weights(mala_synth.net_to_blob(net), mala.PREC_FP32)
+    out = {}
+    for mode in (mala.DENSITY_WINDOW, mala.DENSITY_RECOMPUTE):
+        ctx.set_density_mode(mode)
+        dos, dens, res = ctx.mala_predict(w, snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, EG,
+                                          snap.T, snap.n_electrons)
+        out[mode] = (dos.cpu().numpy(), dens.cpu().numpy(), mala.read_result(res))
+    ctx.set_density_mode(mala.DENSITY_WINDOW)
+    a, b = out[mala.DENSITY_WINDOW], out[mala.DENSITY_RECOMPUTE]
+    log(case, "window path", a[2]["density_from_window"], "recompute path", b[2]["density_from_window"])
+    assert a[2]["density_from_window"] == 1 and b[2]["density_from_window"] == 0
+    assert np.array_equal(a[0], b[0]) and a[2]["e_fermi"] == b[2]["e_fermi"]
+    assert np.max(np.abs(a[1] - b[1])) <= 1e-7 * np.max(np.abs(b[1]))
+
+
 def test_predict_deterministic_and_matches_unfused(ctx, mala, torch):
     snap, net = mala_synth.small(), mala_synth.small_net()
     w = ctx.weights(mala_synth.net_to_blob(net), mala.PREC_FP32)
