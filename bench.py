@@ -4,9 +4,9 @@
                     [--precision fp32|bf16] [--no-cpu-baseline]
 
 A step is one call of the fused path (mala_predict) on one synthetic
-snapshot: atom binning, bispectrum descriptors of every grid point, the
-network with the DOS reduced in its epilogue, Fermi level, band energy, and
-the second network pass that produces the density.  Inputs (positions are
+snapshot: atom binning, bispectrum descriptors of every grid point, an E_F
+estimate on a point subsample, the network with the DOS and the energy
+window reduced in its epilogue, Fermi level, band energy, and the density.  Inputs (positions are
 host data by the ABI; the B cache and outputs are preallocated in HBM) are
 in place before the timed region.  Prints one JSON line.
 """
@@ -54,10 +54,15 @@ def index_counts(tj):
 
 
 def mean_neighbours(snap, n_sample=4096, seed=99):
+    """Mean number of atom images within rcut over a seeded sample of points."""
     pts = mala_synth.sample_points(snap.n_points, n_sample, seed)
     N, L = snap.N, snap.L
     ijk = np.stack([pts // (N[1] * N[2]), (pts // N[2]) % N[1], pts % N[2]], 1)
     r = ijk * (L / N)
+    if np.min(L) > 2.0 * snap.rcut:          # minimum image suffices: periodic KD-tree
+        from scipy.spatial import cKDTree
+        tree = cKDTree(np.mod(snap.positions, L), boxsize=L)
+        return float(np.mean(tree.query_ball_point(np.mod(r, L), snap.rcut, return_length=True)))
     nmax = np.ceil(snap.rcut / L).astype(int) + 1
     shifts = np.array([[a, b, c] for a in range(-nmax[0], nmax[0] + 1)
                        for b in range(-nmax[1], nmax[1] + 1) for c in range(-nmax[2], nmax[2] + 1)]) * L
@@ -92,6 +97,50 @@ def cpu_baseline(snap, net, n_sample):
                       "E_F, E_band, density), %.1f s" % (n_sample, snap.name, dt)}
 
 
+def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5):
+    """Poisson stream of the serving mix through the library's request loop.
+
+    The saturation request rate of the mix is measured first (all requests
+    submitted at once); the stream then arrives at 0.7 x that rate.
+    Latency = completion - arrival (server clock).
+    """
+    rng = mala_synth.SplitMix64(seed)
+    reqs = [mala_synth.serving_request(rng) for _ in range(n_requests)]
+    blob = mala_synth.net_to_blob(mala_synth.paper_net())
+    sv = mala.Server(blob, prec, hbm_budget=budget_gb << 30, max_inflight=slots)
+
+    def submit(r):
+        return sv.submit(r.positions, r.L, r.N, r.rcut, r.twojmax, mala_synth.EGRID, r.T, r.n_electrons)
+
+    for r in reqs[:slots]:                      # warm-up: slot buffers reach their sizes
+        sv.wait(submit(r), 600)
+    t0 = time.perf_counter()
+    outs = [sv.wait(t, 600) for t in [submit(r) for r in reqs]]
+    sat = time.perf_counter() - t0
+    sat_rate = n_requests / sat
+    lam = 0.7 * sat_rate
+    gaps = -np.log(1.0 - rng.uniform(n_requests)) / lam
+    arrivals = np.cumsum(gaps)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, ta in zip(reqs, arrivals):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.0002)
+        tickets.append(submit(r))
+    outs = [sv.wait(t, 600) for t in tickets]
+    span = time.perf_counter() - t0
+    sv.close()
+    lat = np.array([o["t_done"] - o["t_submit"] for o in outs]) * 1000.0
+    pts = sum(r.n_points for r in reqs)
+    bad = sum(1 for o in outs if o["status"] != 0)
+    return {"requests": n_requests, "slots": slots, "hbm_budget_gb": budget_gb,
+            "points_total": pts, "saturation_req_per_s": sat_rate,
+            "saturation_points_per_s": pts / sat, "arrival_rate_req_per_s": lam,
+            "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+            "stream_points_per_s": pts / span, "failed": bad,
+            "mix": "fcc n^3*4 (n=2..8) or liquid N~U[32,2048], 298-933 K, ~2800 points/atom, seed %d" % seed}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,7 +149,8 @@ def main():
     ap.add_argument("--workload", default="paper_solid", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--serve-requests", type=int, default=48, help="0 disables the serving stream")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: the path shards by grid slabs with one 2 KB DOS all-reduce, "
@@ -179,6 +229,10 @@ def main():
                                         "mean_neighbours": fl["mean_neighbours"]},
         "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms},
     }
+    if a.serve_requests > 0:
+        out["serving"] = serving_bench(mala, prec, a.serve_requests)
+        out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]
+        out["latency_ms"]["serving_p99"] = out["serving"]["p99_latency_ms"]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(snap, net, a.cpu_sample)
     print(json.dumps(out), flush=True)

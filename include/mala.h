@@ -155,7 +155,7 @@ mala_status mala_integrate(mala_ctx* ctx, const float* ldos, int64_t n_pts, doub
  * device memory), network with the DOS reduced in the epilogue (the full
  * LDOS is never stored), Fermi level, band energy and density.
  * The density needs E_F, which needs every point.  In the default mode a
- * network pass over every 17th point first estimates E_F; the main pass then
+ * network pass over every 61st point first estimates E_F; the main pass then
  * keeps per point only the FP64 sum of the fully occupied part below the
  * window and the LDOS inside the window E_est +- (40 kT + 0.3 eV); once E_F
  * is solved, the density is finished from those.  If the window does not
@@ -174,6 +174,56 @@ mala_status mala_predict(mala_ctx* ctx, const mala_weights* w, const double* pos
 #define MALA_DENSITY_WINDOW 0
 #define MALA_DENSITY_RECOMPUTE 1
 mala_status mala_set_density_mode(mala_ctx* ctx, int32_t mode);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop for streams of snapshots of different sizes (MD-trajectory
+ * style use of the method).  The server owns the weights and max_inflight
+ * slots; each slot is a context with its own HIP stream and device state, so
+ * the work of requests in different slots overlaps on the device.  Requests
+ * are admitted strictly in arrival order whenever a slot is free and the
+ * device memory held by all slots plus what the request needs stays within
+ * hbm_budget (idle slots release cached buffers first).  A request that can
+ * never fit is rejected by submit with MALA_E_OOM.  Each request runs the
+ * single-snapshot path of mala_predict with its own fixed work partition, so
+ * its result is bitwise the same alone and among other requests.
+ *  - submit copies the positions; dos_out (and density_out, if not NULL) are
+ *    host buffers the server fills when the ticket completes; they must stay
+ *    valid until poll/wait has returned for the ticket.
+ *  - poll returns MALA_E_BUSY until the ticket is done, then the request's
+ *    status (MALA_OK, or its error) once, and forgets the ticket.
+ *  - times[3] = submit, start (admission), done, in seconds since creation.
+ *  - destroy waits for running requests and drops queued ones.             */
+typedef struct mala_server mala_server;
+typedef struct {
+    const double* positions;   /* host float64 [n_atoms][3]         */
+    int32_t n_atoms;
+    mala_cell_grid cell_grid;
+    double rcut;
+    int32_t twojmax;
+    mala_egrid egrid;
+    double T_kelvin;
+    double n_electrons;
+    double* dos_out;           /* host float64 [egrid.n]            */
+    double* density_out;       /* host float64 [N_points] or NULL   */
+} mala_request;
+
+mala_status mala_server_create(int32_t device, const void* weights_blob, size_t bytes,
+                               int32_t precision, size_t hbm_budget, int32_t max_inflight,
+                               mala_server** out);
+/* Host-only executor (a timer of ns_per_point per grid point per request)
+ * behind the same scheduler: exercises admission and ordering without a
+ * device.  Its "results" are the ticket number in dos_out/density_out.      */
+mala_status mala_server_create_mock(int32_t slots, size_t hbm_budget, double ns_per_point,
+                                    mala_server** out);
+mala_status mala_server_submit(mala_server* s, const mala_request* req, uint64_t* ticket);
+mala_status mala_server_poll(mala_server* s, uint64_t ticket, mala_result* result, double* times);
+mala_status mala_server_wait(mala_server* s, uint64_t ticket, double timeout_s,
+                             mala_result* result, double* times);
+/* stats[5] = queued, running, device bytes held by the slots, peak bytes
+ * held, budget.                                                             */
+mala_status mala_server_stats(mala_server* s, double* stats);
+const char* mala_server_last_error(void);
+mala_status mala_server_destroy(mala_server* s);
 
 /* ---------------------------------------------------------------- timing
  * Per-stage instrumentation (the method's cost breakdown by stage): while

@@ -18,6 +18,7 @@ import os
 import struct
 
 import numpy as np
+from scipy.spatial import cKDTree
 
 from .rng import SplitMix64
 
@@ -69,23 +70,45 @@ def jitter(pos, L, sigma, rng):
     return np.mod(p, L)
 
 
-def liquid_rsa(n_atoms, L, dmin, rng, max_tries=2_000_000):
-    """Random sequential packing with a periodic minimum-image distance >= dmin."""
+def liquid_rsa(n_atoms, L, dmin, rng, max_tries=2_000_000, batch=256):
+    """Random sequential packing with a periodic minimum-image distance >= dmin.
+
+    Candidates are uniform points drawn in order; each is accepted if it is at
+    least dmin from every atom accepted before it.  Candidates are drawn and
+    screened in batches (vectorised against the atoms placed before the batch,
+    then one by one against those accepted inside it), which gives the same
+    decisions as testing them one at a time.
+    """
     pos = np.empty((n_atoms, 3))
     k = 0
     tries = 0
+    d2 = dmin * dmin
     while k < n_atoms:
         if tries >= max_tries:
             raise RuntimeError("random packing did not converge")
-        tries += 1
-        c = rng.uniform(3) * L
+        m = min(batch, max_tries - tries)
+        cand = rng.uniform(3 * m).reshape(m, 3) * L
+        tries += m
         if k:
-            d = pos[:k] - c
-            d -= L * np.round(d / L)
-            if np.min(np.einsum("ij,ij->i", d, d)) < dmin * dmin:
-                continue
-        pos[k] = c
-        k += 1
+            # nearest placed atom (periodic) per candidate
+            box = np.broadcast_to(np.asarray(L, float), (3,))
+            tree = cKDTree(np.mod(pos[:k], box), boxsize=box)
+            dist, _ = tree.query(np.mod(cand, box), k=1)
+            ok = dist * dist >= d2
+        else:
+            ok = np.ones(m, bool)
+        start = k
+        for i in np.nonzero(ok)[0]:
+            c = cand[i]
+            if k > start:
+                e = pos[start:k] - c
+                e -= L * np.round(e / L)
+                if np.min(np.einsum("ij,ij->i", e, e)) < d2:
+                    continue
+            pos[k] = c
+            k += 1
+            if k == n_atoms:
+                break
     return pos
 
 

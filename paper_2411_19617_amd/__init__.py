@@ -47,6 +47,19 @@ class EGrid(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("de", ctypes.c_double), ("n", ctypes.c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("positions", ctypes.c_void_p), ("n_atoms", ctypes.c_int32), ("cell_grid", CellGrid),
+                ("rcut", ctypes.c_double), ("twojmax", ctypes.c_int32), ("egrid", EGrid),
+                ("T_kelvin", ctypes.c_double), ("n_electrons", ctypes.c_double),
+                ("dos_out", ctypes.c_void_p), ("density_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("e_fermi", ctypes.c_double), ("e_band", ctypes.c_double), ("n_found", ctypes.c_double),
+                ("n_target", ctypes.c_double), ("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("density_from_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 def lib():
     """Load libmala.so (raises if it is missing)."""
     global _lib
@@ -57,6 +70,7 @@ def lib():
         p, i32, i64, d, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
         L.mala_last_error.restype = ctypes.c_char_p
         L.mala_version.restype = ctypes.c_char_p
+        L.mala_server_last_error.restype = ctypes.c_char_p
         L.mala_n_descriptors.restype = i32
         L.mala_n_descriptors.argtypes = [i32]
         for name, args in [
@@ -73,6 +87,13 @@ def lib():
             ("mala_predict", [p, p, p, i32, ctypes.POINTER(CellGrid), d, i32, ctypes.POINTER(EGrid), d, d,
                               p, p, p, p]),
             ("mala_profile_enable", [p, i32]),
+            ("mala_server_create", [i32, p, sz, i32, sz, i32, ctypes.POINTER(p)]),
+            ("mala_server_create_mock", [i32, sz, d, ctypes.POINTER(p)]),
+            ("mala_server_submit", [p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+            ("mala_server_poll", [p, ctypes.c_uint64, ctypes.POINTER(Result), p]),
+            ("mala_server_wait", [p, ctypes.c_uint64, d, ctypes.POINTER(Result), p]),
+            ("mala_server_stats", [p, p]),
+            ("mala_server_destroy", [p]),
             ("mala_set_density_mode", [p, i32]),
             ("mala_profile_read", [p, p, p, p]),
         ]:
@@ -254,3 +275,91 @@ class Context:
                                   int(twojmax), ctypes.byref(eg), float(T), float(n_electrons), _ptr(dos),
                                   _ptr(dens if density else None), _ptr(res), _ptr(B_cache)))
         return dos, (dens if density else None), res
+
+
+class Server:
+    """Request loop of the library (mala_server_*): continuous admission of
+    snapshots into device slots under an HBM budget.  ``mock_ns_per_point``
+    selects the host-only executor (no GPU) that exercises the scheduler."""
+
+    def __init__(self, blob=None, precision=PREC_FP32, hbm_budget=64 << 30, max_inflight=4, device=0,
+                 mock_ns_per_point=None):
+        h = ctypes.c_void_p()
+        if mock_ns_per_point is not None:
+            st = lib().mala_server_create_mock(int(max_inflight), int(hbm_budget), float(mock_ns_per_point),
+                                               ctypes.byref(h))
+        else:
+            buf = ctypes.create_string_buffer(blob, len(blob))
+            st = lib().mala_server_create(int(device), buf, len(blob), int(precision), int(hbm_budget),
+                                          int(max_inflight), ctypes.byref(h))
+        if st != MALA_OK:
+            raise MalaError(st, lib().mala_last_error().decode())
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, positions, L, N, rcut, twojmax, egrid, T, n_electrons, density=True):
+        """Queue one snapshot; returns the ticket.  Output arrays are held until taken."""
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
+        dos = np.zeros(int(egrid[2]))
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        dens = np.zeros(ntot) if density else None
+        q = Request()
+        q.positions = pos.ctypes.data
+        q.n_atoms = pos.shape[0]
+        q.cell_grid = _cell_grid(L, N)
+        q.rcut = float(rcut)
+        q.twojmax = int(twojmax)
+        q.egrid = _egrid(egrid)
+        q.T_kelvin = float(T)
+        q.n_electrons = float(n_electrons)
+        q.dos_out = dos.ctypes.data
+        q.density_out = dens.ctypes.data if density else None
+        t = ctypes.c_uint64()
+        st = lib().mala_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t))
+        if st != MALA_OK:
+            raise MalaError(st, "submit rejected")
+        self._keep[t.value] = (pos, dos, dens)
+        return t.value
+
+    def _out(self, ticket, st, r, times):
+        if ticket not in self._keep:
+            raise MalaError(st, "unknown ticket %d" % ticket)
+        pos, dos, dens = self._keep.pop(ticket)
+        if st != MALA_OK:
+            raise MalaError(st, lib().mala_server_last_error().decode())
+        return {"e_fermi": r.e_fermi, "e_band": r.e_band, "n_found": r.n_found, "iterations": r.iterations,
+                "status": r.status, "density_from_window": r.density_from_window, "dos": dos, "density": dens,
+                "t_submit": times[0], "t_start": times[1], "t_done": times[2]}
+
+    def poll(self, ticket):
+        r = Result()
+        times = (ctypes.c_double * 3)()
+        st = lib().mala_server_poll(self.handle, ticket, ctypes.byref(r), times)
+        if st == MALA_E_BUSY:
+            return None
+        return self._out(ticket, st, r, times)
+
+    def wait(self, ticket, timeout=600.0):
+        r = Result()
+        times = (ctypes.c_double * 3)()
+        st = lib().mala_server_wait(self.handle, ticket, float(timeout), ctypes.byref(r), times)
+        if st == MALA_E_BUSY:
+            raise TimeoutError("ticket %d not done after %.1f s" % (ticket, timeout))
+        return self._out(ticket, st, r, times)
+
+    def stats(self):
+        s = (ctypes.c_double * 5)()
+        _check(lib().mala_server_stats(self.handle, s))
+        return {"queued": int(s[0]), "running": int(s[1]), "bytes_held": s[2], "peak_bytes": s[3],
+                "budget": s[4]}
+
+    def close(self):
+        if self.handle:
+            lib().mala_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -148,7 +148,7 @@ hipError_t staged(mala_ctx* c, int stage, int64_t pts, F&& fn) {
     return e;
 }
 
-constexpr int kEstStride = 17;          // subsample stride of the E_F estimate
+constexpr int kEstStride = 61;          // subsample stride of the E_F estimate
 
 __global__ void k_set_covered(WindowRec* w, int v) {
     if (threadIdx.x == 0) {
@@ -269,6 +269,33 @@ mala_status check_egrid(const mala_egrid* eg, double T, double ne) {
 }
 
 }  // namespace
+
+namespace mala {
+
+template <typename T>
+static size_t bytes_of(const DevBuf<T>& b) {
+    return b.cap * sizeof(T);
+}
+
+size_t ctx_device_bytes(mala_ctx* c) {
+    return bytes_of(c->pos) + bytes_of(c->cell_count) + bytes_of(c->cell_start) + bytes_of(c->cell_fill) +
+           bytes_of(c->atom_cell) + bytes_of(c->atoms_tmp) + bytes_of(c->atoms_sorted) + bytes_of(c->u) +
+           bytes_of(c->Bbuf) + bytes_of(c->partials) + bytes_of(c->est_partials) + bytes_of(c->fermi_w) +
+           bytes_of(c->window) + bytes_of(c->prefix);
+}
+
+void ctx_trim(mala_ctx* c) {
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    release(c->u);
+    release(c->Bbuf);
+    release(c->window);
+    release(c->prefix);
+    release(c->partials);
+    release(c->est_partials);
+}
+
+}  // namespace mala
 
 // ====================================================================== ABI
 extern "C" {

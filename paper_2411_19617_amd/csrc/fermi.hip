@@ -59,15 +59,13 @@ __device__ void gfun(double x, const double* coef, double& g0, double& g1, doubl
     }
 }
 
-// Fixed-shape tree sum over 256 threads.
+// Fixed-shape sum over the 256 threads: butterfly inside each wave, then the
+// four wave sums in order.
 __device__ double block_sum(double v, double* red) {
-    red[threadIdx.x] = v;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    const double r = red[0];
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return r;
 }
@@ -131,7 +129,15 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
     const int e = threadIdx.x;
     double d = 0.0;
     if (e < n_e) {
-        for (int w = 0; w < n_parts; ++w) d += partials[(size_t)w * kMlpMaxOut + e];
+        // eight independent running sums (loads in flight), combined in a fixed order
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int w = 0;
+        for (; w + 8 <= n_parts; w += 8) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += partials[(size_t)(w + q) * kMlpMaxOut + e];
+        }
+        for (; w < n_parts; ++w) acc[0] += partials[(size_t)w * kMlpMaxOut + e];
+        d = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         d *= dV;
         if (mode == 0) dos_out[e] = d;
     }

@@ -8,6 +8,8 @@
 #include <type_traits>
 #include <utility>
 
+struct mala_ctx;
+
 namespace mala {
 
 constexpr int kTile = 64;            // grid points per bispectrum tile (one per lane)
@@ -142,6 +144,10 @@ hipError_t launch_density_window(hipStream_t s, const double* prefix, const floa
 
 hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
                                     const double* weights, const void* result, double* density);
+
+// Device bytes held by a context's scratch, and releasing them (serving).
+size_t ctx_device_bytes(mala_ctx* c);
+void ctx_trim(mala_ctx* c);
 
 // Host-side tables.
 int build_cg_table(int twojmax, float* table, int* offsets, int cap);
