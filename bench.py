@@ -97,6 +97,45 @@ def cpu_baseline(snap, net, n_sample):
                       "E_F, E_band, density), %.1f s" % (n_sample, snap.name, dt)}
 
 
+TRAFFIC_FILES = {"paper_solid": "traffic_k_zb_al256_solid_90c_tj10.txt"}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2411_19617_amd/csrc/bispectrum.hip", "paper_2411_19617_amd/csrc/mala_internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_zb launch from the committed, calibrated rocprofv3 counters;
+    None if there are none for this workload or the kernel source changed since."""
+    name = TRAFFIC_FILES.get(workload)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def errors_vs_oracle(workload, snap, dos, r, dens):
+    """Whole-grid errors against the oracle's stored full-grid values (if any)."""
+    path = os.path.join(ROOT, "tests", "golden", "full_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    D = dos.cpu().numpy()
+    Dref = np.array(g["dos"])
+    return {"dos_max_rel": float(np.max(np.abs(D - Dref)) / np.max(np.abs(Dref))),
+            "e_fermi_ev": abs(r["e_fermi"] - g["e_fermi"]),
+            "e_band_mev_per_atom": abs(r["e_band"] - g["e_band"]) * 1000.0 / snap.n_atoms,
+            "density_integral_rel": abs(float(dens.sum().item()) * snap.dV - g["density_sum_dV"]) / g["density_sum_dV"],
+            "oracle": "tests/golden/full_%s.json (FP64 oracle, all %d points)" % (workload, g["n_points"])}
+
+
 def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5):
     """Poisson stream of the serving mix through the library's request loop.
 
@@ -221,13 +260,15 @@ def main():
                        "kind": "single snapshot, back-to-back"},
         "roofline": {"kernel": "k_zb (Z/B contraction)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": measured_traffic(a.workload),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "flops_per_point": fl["zb"], "points_per_launch": zb_pts / max(zb_n, 1),
                      "avg_launch_ms": zb_avg_ms},
         "stages": stages,
         "algorithmic_kflop_per_point": {"u": fl["u"] / 1e3, "zb": fl["zb"] / 1e3, "mlp": fl["mlp"] / 1e3,
                                         "mean_neighbours": fl["mean_neighbours"]},
         "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms},
+        "errors_vs_oracle": errors_vs_oracle(a.workload, snap, dos, mala.read_result(res), dens),
     }
     if a.serve_requests > 0:
         out["serving"] = serving_bench(mala, prec, a.serve_requests)

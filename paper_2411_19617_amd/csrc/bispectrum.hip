@@ -365,56 +365,100 @@ __device__ __forceinline__ float2 uload(const float2* __restrict__ su, int c, in
     }
 }
 
+// Number of (ma, ma1) row pairs of a triple: ma <= J/2, ma2 = ma - ma1 + D in [0, J2].
+__host__ __device__ constexpr int zb_pairs(int J1, int J2, int J) {
+    int n = 0;
+    const int D = (J1 + J2 - J) / 2;
+    for (int ma = 0; ma <= J / 2; ++ma)
+        for (int ma1 = 0; ma1 <= J1; ++ma1)
+            if (ma - ma1 + D >= 0 && ma - ma1 + D <= J2) ++n;
+    return n;
+}
+__host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, int ma1) {
+    int n = 0;
+    const int D = (J1 + J2 - J) / 2;
+    for (int a = 0; a <= J / 2; ++a)
+        for (int a1 = 0; a1 <= J1; ++a1)
+            if (a - a1 + D >= 0 && a - a1 + D <= J2) {
+                if (a == ma && a1 == ma1) return n;
+                ++n;
+            }
+    return -1;
+}
+
+// B(j1,j2,j) of the lane's point.  For each output column mb:
+//   T[ma][ma1] = sum_mb1 (C(mb1,mb) u1[ma1][mb1]) u2[ma-ma1+D][mb-mb1+D]
+// (the scaled u1 element is shared by every row ma), then
+//   Z[ma][mb] = sum_ma1 C(ma1,ma) T[ma][ma1],  B += w_ma Re(conj(u[ma][mb]) Z[ma][mb]).
 template <int J1, int J2, int J>
 __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int lane,
                                            const float* __restrict__ cg) {
     constexpr int D = (J1 + J2 - J) / 2;   // ma2 = ma - ma1 + D
     constexpr int HR = J / 2;              // half rows 0..HR
     constexpr int W = J + 1;               // cg row stride: cg[ma1*W + ma]
+    constexpr int NP = zb_pairs(J1, J2, J);
     float bsum = 0.f;
     for (int mb = 0; mb <= J; ++mb) {
-        float zr[HR + 1], zi[HR + 1];
-        static_for<0, HR + 1>([&](auto mc) {
-            zr[decltype(mc)::value] = 0.f;
-            zi[decltype(mc)::value] = 0.f;
-        });
-        const int lo = max(0, mb + D - J2), hi = min(J1, mb + D);
-        for (int mb1 = lo; mb1 <= hi; ++mb1) {
+        float tr[NP], ti[NP];
+        // one m1' column: the first one initialises T, the others accumulate
+        auto column = [&](int mb1, auto first) {
+            constexpr bool FIRST = decltype(first)::value;
             const int mb2 = mb + D - mb1;
             const float c2 = cg[mb1 * W + mb];
             float u2r[J2 + 1], u2i[J2 + 1];
             static_for<0, J2 + 1>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
-                const float2 v = uload<J2, r>(su, mb2, lane);
-                u2r[r] = v.x;
-                u2i[r] = v.y;
+                constexpr bool used = (r - D <= J1) && (r <= HR + D);
+                if constexpr (used) {
+                    const float2 v = uload<J2, r>(su, mb2, lane);
+                    u2r[r] = v.x;
+                    u2i[r] = v.y;
+                }
             });
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
-                // is row ma1 used by any half row ma?
                 constexpr bool used = (ma1 - D <= HR) && (ma1 - D + J2 >= 0);
                 if constexpr (used) {
                     const float2 v = uload<J1, ma1>(su, mb1, lane);
-                    const float vr = c2 * v.x, vi = c2 * v.y;
+                    const float wr = c2 * v.x, wi = c2 * v.y;
                     static_for<0, HR + 1>([&](auto mc) {
                         constexpr int ma = decltype(mc)::value;
                         constexpr int ma2 = ma - ma1 + D;
                         if constexpr (ma2 >= 0 && ma2 <= J2) {
-                            const float c1 = cg[ma1 * W + ma];
-                            const float pr = vr * u2r[ma2] - vi * u2i[ma2];
-                            const float pi = vr * u2i[ma2] + vi * u2r[ma2];
-                            zr[ma] += c1 * pr;
-                            zi[ma] += c1 * pi;
+                            constexpr int k = zb_pair_index(J1, J2, J, ma, ma1);
+                            if constexpr (FIRST) {
+                                tr[k] = fmaf(-wi, u2i[ma2], wr * u2r[ma2]);
+                                ti[k] = fmaf(wi, u2r[ma2], wr * u2i[ma2]);
+                            } else {
+                                tr[k] = fmaf(wr, u2r[ma2], tr[k]);
+                                tr[k] = fmaf(-wi, u2i[ma2], tr[k]);
+                                ti[k] = fmaf(wr, u2i[ma2], ti[k]);
+                                ti[k] = fmaf(wi, u2r[ma2], ti[k]);
+                            }
                         }
                     });
                 }
             });
-        }
+        };
+        const int lo = max(0, mb + D - J2), hi = min(J1, mb + D);   // never empty
+        column(lo, std::true_type{});
+        for (int mb1 = lo + 1; mb1 <= hi; ++mb1) column(mb1, std::false_type{});
         static_for<0, HR + 1>([&](auto mc) {
             constexpr int ma = decltype(mc)::value;
+            float zr = 0.f, zi = 0.f;
+            static_for<0, J1 + 1>([&](auto r1c) {
+                constexpr int ma1 = decltype(r1c)::value;
+                constexpr int ma2 = ma - ma1 + D;
+                if constexpr (ma2 >= 0 && ma2 <= J2) {
+                    constexpr int k = zb_pair_index(J1, J2, J, ma, ma1);
+                    const float c1 = cg[ma1 * W + ma];
+                    zr = fmaf(c1, tr[k], zr);
+                    zi = fmaf(c1, ti[k], zi);
+                }
+            });
             constexpr float w = (2 * ma < J) ? 2.f : 1.f;
             const float2 uj = su[(half_off(J) + ma * (J + 1) + mb) * kTile + lane];
-            bsum += w * (uj.x * zr[ma] + uj.y * zi[ma]);
+            bsum += w * (uj.x * zr + uj.y * zi);
         });
     }
     return bsum;
@@ -436,7 +480,7 @@ __device__ __forceinline__ float zb_dispatch(int t, const float2* __restrict__ s
 }
 
 template <int TJ>
-__global__ __launch_bounds__(1024) void k_zb(const float2* __restrict__ u, int64_t n_pts,
+__global__ __launch_bounds__(512) void k_zb(const float2* __restrict__ u, int64_t n_pts,
                                              float* __restrict__ B, const float* __restrict__ cg_table,
                                              const int* __restrict__ cg_off,
                                              const int* __restrict__ wave_triples, int stride) {
