@@ -493,13 +493,15 @@ mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32
     const bool bf = precision == MALA_PREC_BF16;
     auto ceil_div = [](int a, int b) { return (a + b - 1) / b; };
     const int KK = bf ? 32 : 4;
-    const int in_pad = KK * ceil_div(n_in, KK);
+    // fp32 batches 4 K-steps (16 units): input padded to a multiple of 16
+    const int in_pad = bf ? 32 * ceil_div(n_in, 32) : 16 * ceil_div(n_in, 16);
     const int h1t = bf ? 2 * ceil_div(h1, 32) : ceil_div(h1, 16);
     const int h2t = bf ? 2 * ceil_div(h2, 32) : ceil_div(h2, 16);
     const int ot = ceil_div(n_out, 16);
     const int KS1 = in_pad / KK, KS2 = h1t * 16 / KK, KS3 = h2t * 16 / KK;
-    // A operand of MFMA tile (mt, s): lane l holds row 16 mt + l%16 and
-    // k = KK s + (l/16) * (KK/4) + q, q < KK/4 (natural K order).
+    // A operand of MFMA tile (mt, s): lane l holds row 16 mt + l%16 and, for
+    // bf16, k = 32 s + 8 (l/16) + q, q < 8; for fp32 the K order that makes
+    // four consecutive K-steps contiguous per lane: k = 16 (s/4) + 4 (l/16) + s%4.
     auto pack = [&](const std::vector<double>& W, int fout, int fin, int mtiles, int ks, std::vector<float>& o) {
         const int per = KK / 4;
         o.assign((size_t)mtiles * ks * 64 * per, 0.f);
@@ -508,7 +510,8 @@ mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32
                 for (int lane = 0; lane < 64; ++lane)
                     for (int q = 0; q < per; ++q) {
                         const int row = 16 * mt + (lane & 15);
-                        const int k = KK * s + (lane >> 4) * per + q;
+                        const int k = bf ? 32 * s + 8 * (lane >> 4) + q
+                                         : 16 * (s / 4) + 4 * (lane >> 4) + (s % 4);
                         float v = 0.f;
                         if (row < fout && k < fin) v = (float)W[(size_t)row * fin + k];
                         o[(((size_t)mt * ks + s) * 64 + lane) * per + q] = v;

@@ -44,67 +44,114 @@ __device__ __forceinline__ f4 bias4(const float* b, int off) {
 template <int PREC>
 struct Prec;
 
+// FP32: MFMA 16x16x4.  K-step s of lane group g uses unit
+// 16*(s/4) + 4*g + s%4, so a batch of 4 K-steps reads 4 contiguous floats
+// per lane (one ds_read_b128); the weights are packed in the same order.
 template <>
 struct Prec<0> {
     using T = float;
-    using AT = float;
-    static constexpr int K = 4;
-    static constexpr int PF = 8;
+    static constexpr int K = 4;      // units per K-step
+    static constexpr int PF = 4;     // K-steps per batch
+    struct BatchA { float v[4]; };
+    struct BatchB { float4 v; };
     __host__ __device__ static int stride(int w) { return ((w + 63) / 64) * 64 + 4; }
-    __device__ static AT loadA(const void* A, size_t idx) { return static_cast<const float*>(A)[idx]; }
-    __device__ static f4 mma(AT a, const T* row, int k0, f4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, row[k0], c, 0, 0, 0);
+    __device__ static void loadA(BatchA& a, const void* A, size_t base, int q) {
+        const float* p = static_cast<const float*>(A) + base + (size_t)q * PF * 64;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a.v[i] = p[i * 64];
+    }
+    __device__ static void loadB(BatchB& b, const T* row, int q, int g) {
+        b.v = *reinterpret_cast<const float4*>(row + 16 * q + 4 * g);
+    }
+    __device__ static f4 mma_batch(const BatchA& a, const BatchB& b, f4 c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[0], b.v.x, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[1], b.v.y, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[2], b.v.z, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[3], b.v.w, c, 0, 0, 0);
+        return c;
     }
     __device__ static void store4(T* dst, f4 v) {
         *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
     }
     __device__ static T cvt(float x) { return x; }
-    __device__ static int kofs(int s, int g) { return 4 * s + g; }
 };
 
+// BF16: MFMA 16x16x32, K-step s of lane group g uses units 32 s + 8 g + 0..7.
 template <>
 struct Prec<1> {
     using T = __bf16;
-    using AT = uint4;
     static constexpr int K = 32;
-    static constexpr int PF = 4;
+    static constexpr int PF = 2;
+    struct BatchA { uint4 v[2]; };
+    struct BatchB { uint4 v[2]; };
     __host__ __device__ static int stride(int w) { return ((w + 127) / 128) * 128 + 8; }
-    __device__ static AT loadA(const void* A, size_t idx) { return static_cast<const uint4*>(A)[idx]; }
-    __device__ static f4 mma(AT av, const T* row, int k0, f4 c) {
+    __device__ static void loadA(BatchA& a, const void* A, size_t base, int q) {
+        const uint4* p = static_cast<const uint4*>(A) + base + (size_t)q * PF * 64;
+        a.v[0] = p[0];
+        a.v[1] = p[64];
+    }
+    __device__ static void loadB(BatchB& b, const T* row, int q, int g) {
+        b.v[0] = *reinterpret_cast<const uint4*>(row + 32 * (PF * q) + 8 * g);
+        b.v[1] = *reinterpret_cast<const uint4*>(row + 32 * (PF * q + 1) + 8 * g);
+    }
+    __device__ static f4 mma1(uint4 av, uint4 bv, f4 c) {
         bf8 a, b;
         __builtin_memcpy(&a, &av, 16);
-        const uint4 bv = *reinterpret_cast<const uint4*>(row + k0);
         __builtin_memcpy(&b, &bv, 16);
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static f4 mma_batch(const BatchA& a, const BatchB& b, f4 c) {
+        c = mma1(a.v[0], b.v[0], c);
+        return mma1(a.v[1], b.v[1], c);
+    }
+    __device__ static f4 mma_tail(const void* A, size_t base, int s, const T* row, int g, f4 c) {
+        const uint4 av = static_cast<const uint4*>(A)[base + (size_t)s * 64];
+        const uint4 bv = *reinterpret_cast<const uint4*>(row + 32 * s + 8 * g);
+        return mma1(av, bv, c);
     }
     __device__ static void store4(T* dst, f4 v) {
         bf4 h = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
         *reinterpret_cast<bf4*>(dst) = h;
     }
     __device__ static T cvt(float x) { return (__bf16)x; }
-    __device__ static int kofs(int s, int g) { return 32 * s + 8 * g; }
 };
 
-// acc[n] += sum over K-steps s < KS of A(s) * B_n(s), A streamed from global
-// through a prefetch ring, B_n read from LDS row rows[n].
+// acc[n] += sum over K-steps s < KS of A(s) B_n(s).  Batches of PF K-steps:
+// weights fetched two batches ahead, LDS operands one batch ahead, no
+// per-step branches.  FP32 K-step counts are multiples of PF; BF16 may
+// leave one tail step.
 template <int PREC, int NA>
 __device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const typename Prec<PREC>::T* const (&rows)[NA],
                                       int g, f4 (&acc)[NA]) {
     using P = Prec<PREC>;
-    typename P::AT ring[P::PF];
+    using BA = typename P::BatchA;
+    using BB = typename P::BatchB;
+    const int NQ = KS / P::PF;
+    BA a0, a1, a2;
+    BB b0[NA], b1[NA];
+    if (NQ > 0) {
+        P::loadA(a0, A, base, 0);
 #pragma unroll
-    for (int p = 0; p < P::PF; ++p)
-        if (p < KS) ring[p] = P::loadA(A, base + (size_t)p * 64);
-    for (int s0 = 0; s0 < KS; s0 += P::PF) {
+        for (int n = 0; n < NA; ++n) P::loadB(b0[n], rows[n], 0, g);
+    }
+    if (NQ > 1) P::loadA(a1, A, base, 1);
+    for (int q = 0; q < NQ; ++q) {
+        if (q + 2 < NQ) P::loadA(a2, A, base, q + 2);
+        if (q + 1 < NQ) {
 #pragma unroll
-        for (int p = 0; p < P::PF; ++p) {
-            const int s = s0 + p;
-            if (s < KS) {
-                const typename P::AT a = ring[p];
-                if (s + P::PF < KS) ring[p] = P::loadA(A, base + (size_t)(s + P::PF) * 64);
+            for (int n = 0; n < NA; ++n) P::loadB(b1[n], rows[n], q + 1, g);
+        }
 #pragma unroll
-                for (int n = 0; n < NA; ++n) acc[n] = P::mma(a, rows[n], P::kofs(s, g), acc[n]);
-            }
+        for (int n = 0; n < NA; ++n) acc[n] = P::mma_batch(a0, b0[n], acc[n]);
+        a0 = a1;
+        a1 = a2;
+#pragma unroll
+        for (int n = 0; n < NA; ++n) b0[n] = b1[n];
+    }
+    if constexpr (PREC == 1) {
+        for (int s = NQ * P::PF; s < KS; ++s) {
+#pragma unroll
+            for (int n = 0; n < NA; ++n) acc[n] = P::mma_tail(A, base, s, rows[n], g, acc[n]);
         }
     }
 }
