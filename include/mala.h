@@ -117,7 +117,7 @@ typedef struct {
     double e_band;        /* eV (total; divide by N_atoms for per-atom) */
     double n_found;       /* N(E_F) from the weights              */
     double n_target;      /* requested N_e                        */
-    int32_t iterations;   /* bisection steps                      */
+    int32_t iterations;   /* root-finder steps (Newton or bisection) */
     int32_t status;       /* MALA_OK or MALA_E_NO_ROOT            */
     int32_t density_from_window; /* mala_predict: 1 if the density came from
                                     the stored energy window, 0 otherwise */
@@ -237,7 +237,7 @@ mala_status mala_server_destroy(mala_server* s);
 #define MALA_STAGE_ZB 2           /* Z/B contraction (bispectrum)            */
 #define MALA_STAGE_MLP_LDOS 3     /* network, LDOS stored                    */
 #define MALA_STAGE_MLP_DOS 4      /* network, DOS reduced in the epilogue    */
-#define MALA_STAGE_FERMI 5        /* DOS sum, E_F bisection, E_band, weights */
+#define MALA_STAGE_FERMI 5        /* DOS sum, E_F root, E_band, weights */
 #define MALA_STAGE_MLP_DENSITY 6  /* network, density in the epilogue        */
 #define MALA_STAGE_INTEGRATE 7    /* stored-LDOS column sums and density     */
 #define MALA_STAGE_ESTIMATE 8     /* E_F estimate on a point subsample       */

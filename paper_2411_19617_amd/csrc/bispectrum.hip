@@ -4,11 +4,12 @@
 // Two kernels per tile of 64 consecutive grid points (one point per lane):
 //
 //  k_ui  -- neighbour gather and the expansion coefficients
-//           u^J = I + sum_k f_c(r_k) U^J(g_k).  U^J is built level by level
-//           from U^0 = f_c: row 0 of level J from row 0 of level J-1, and row
-//           ma >= 1 of level J from row ma-1 of level J-1 (both follow from
-//           writing the spin-J/2 irrep as the polynomial action of g on
-//           (xi, eta)).  The rows that share J-ma form independent chains;
+//           u^J = I + sum_k f_c(r_k) U^J(g_k).  U^J is the spin-J/2 irrep of
+//           g written as a polynomial action on (xi, eta); its unnormalised
+//           coefficients are built level by level from f_c: row 0 of level J
+//           from row 0 of level J-1, and row ma >= 1 of level J from row ma-1
+//           of level J-1, and are normalised once after the neighbour sum.
+//           The rows that share J-ma form independent chains;
 //           the chains are split over the waves of the block so that each
 //           wave keeps its share of u in registers over the whole neighbour
 //           loop.  Only rows ma <= J/2 are formed; the rest follow from
@@ -17,11 +18,15 @@
 //  k_zb  -- the tile's half-u (271 complex per point at twojmax 10, 139 KB
 //           for 64 points) is staged in LDS; every wave of the block owns a
 //           balanced subset of the (j1,j2,j) triples and contracts
-//           Z^j_{m m'} = sum C C u^{j1} u^{j2} column by column (a column of
-//           u^{j1} and one of u^{j2} in registers, the Z column in
-//           registers), then B = sum Re(conj(u^j) Z) over the half rows.
-//           Clebsch-Gordan values come from a per-triple table in global
-//           memory read with wave-uniform (scalar) loads.
+//           Z^j_{m m'} = sum C C u^{j1} u^{j2} one output column m' at a time
+//           (columns of u^{j1} and u^{j2} in registers, the row CG factor
+//           applied after the m1' sum), then B = sum Re(conj(u^j) Z) over the
+//           half rows.
+//           Each triple is contracted in whichever of its three
+//           orientations (which level is the conjugated output) costs
+//           least; Clebsch-Gordan values of that coupling come from a
+//           per-triple table in global memory read with wave-uniform
+//           (scalar) loads.
 #include "mala_internal.h"
 
 namespace mala {
@@ -72,7 +77,14 @@ __host__ __device__ constexpr int row_slot(int q, int k) {
     return n;
 }
 
-// Accumulate f_c * U(g) of one neighbour into the group's registers.
+// Accumulate f_c * c(g) of one neighbour into the group's registers, where
+// c^J[ma][mb] is the coefficient of xi^mb eta^(J-mb) in
+// (a xi - conj(b) eta)^ma (b xi + conj(a) eta)^(J-ma); U^J = N c^J with
+// N = sqrt(mb! (J-mb)! / (ma! (J-ma)!)) applied once at write-out.  The
+// coefficients obey two plain recursions (multiply the polynomial by one
+// more factor):
+//   row 0:   c^J[0][mb]  = b c^{J-1}[0][mb-1] + conj(a) c^{J-1}[0][mb]
+//   row k:   c^J[k][mb]  = a c^{J-1}[k-1][mb-1] - conj(b) c^{J-1}[k-1][mb]
 template <int TJ, int G, int NACC>
 __device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float bi, float fc,
                                              float (&accr)[NACC], float (&acci)[NACC]) {
@@ -83,21 +95,18 @@ __device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float
     if constexpr (in_group(TJ, G, 0)) accr[chain_slot(TJ, G, 0)] += fc;
     static_for<1, QMAX + 1>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
-        // row 0 of level J: b sqrt(mb/J) old[mb-1] + conj(a) sqrt((J-mb)/J) old[mb]
         static_for<0, J + 1>([&](auto ic) {
-            constexpr int mb = J - decltype(ic)::value;
+            constexpr int mb = J - decltype(ic)::value;   // in place, high mb first
             float nr = 0.f, ni = 0.f;
-            if constexpr (mb >= 1) {
-                constexpr float c = (float)ce_sqrt((double)mb / J);
+            if constexpr (mb >= 1) {                        // b * old[mb-1]
                 const float orr = r0r[mb - 1], oi = r0i[mb - 1];
-                nr = c * (br * orr - bi * oi);
-                ni = c * (br * oi + bi * orr);
+                nr = fmaf(br, orr, -bi * oi);
+                ni = fmaf(br, oi, bi * orr);
             }
-            if constexpr (mb <= J - 1) {
-                constexpr float c = (float)ce_sqrt((double)(J - mb) / J);
+            if constexpr (mb <= J - 1) {                    // conj(a) * old[mb]
                 const float orr = r0r[mb], oi = r0i[mb];
-                nr += c * (ar * orr + ai * oi);
-                ni += c * (ar * oi - ai * orr);
+                nr = fmaf(ar, orr, fmaf(ai, oi, nr));
+                ni = fmaf(ar, oi, fmaf(-ai, orr, ni));
             }
             r0r[mb] = nr;
             r0i[mb] = ni;
@@ -113,24 +122,21 @@ __device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float
                 accr[base + mb] += cr[mb];
                 acci[base + mb] += ci[mb];
             });
-            // rows k = 1..: level Jp = Q + k from the chain's previous row
             static_for<1, chain_rows(TJ, Q)>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 constexpr int Jp = Q + k;
                 static_for<0, Jp + 1>([&](auto ic) {
                     constexpr int mb = Jp - decltype(ic)::value;
                     float nr = 0.f, ni = 0.f;
-                    if constexpr (mb >= 1) {   // a sqrt(mb/k) old[mb-1]
-                        constexpr float c = (float)ce_sqrt((double)mb / k);
+                    if constexpr (mb >= 1) {                // a * old[mb-1]
                         const float orr = cr[mb - 1], oi = ci[mb - 1];
-                        nr = c * (ar * orr - ai * oi);
-                        ni = c * (ar * oi + ai * orr);
+                        nr = fmaf(ar, orr, -ai * oi);
+                        ni = fmaf(ar, oi, ai * orr);
                     }
-                    if constexpr (mb <= Jp - 1) {  // - conj(b) sqrt((Jp-mb)/k) old[mb]
-                        constexpr float c = (float)ce_sqrt((double)(Jp - mb) / k);
+                    if constexpr (mb <= Jp - 1) {           // - conj(b) * old[mb]
                         const float orr = cr[mb], oi = ci[mb];
-                        nr -= c * (br * orr + bi * oi);
-                        ni -= c * (br * oi - bi * orr);
+                        nr = fmaf(-br, orr, fmaf(-bi, oi, nr));
+                        ni = fmaf(-br, oi, fmaf(bi, orr, ni));
                     }
                     cr[mb] = nr;
                     ci[mb] = ni;
@@ -144,6 +150,12 @@ __device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float
             });
         }
     });
+}
+
+__host__ __device__ constexpr double ce_fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -316,7 +328,7 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_ui(BinState bins, int Nx,
             }
             ui_neighbour<TJ, G, NACC>(ar, ai, br, bi, fc, accr, acci);
         }
-        // self term (identity on the diagonal) and write-out
+        // normalisation, self term (identity on the diagonal, N = 1 there), write-out
         static_for<0, TJ + 1>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             if constexpr (in_group(TJ, G, q)) {
@@ -324,11 +336,13 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_ui(BinState bins, int Nx,
                     constexpr int k = decltype(kc)::value;
                     constexpr int J = q + k;
                     constexpr int rb = chain_slot(TJ, G, q) + row_slot(q, k);
-                    accr[rb + k] += 1.f;
                     static_for<0, J + 1>([&](auto mc) {
                         constexpr int mb = decltype(mc)::value;
+                        constexpr float nrm =
+                            (float)ce_sqrt(ce_fact(mb) * ce_fact(J - mb) / (ce_fact(k) * ce_fact(J - k)));
                         constexpr int e = half_off(J) + k * (J + 1) + mb;
-                        u_out[(tile * NH + e) * kTile + lane] = make_float2(accr[rb + mb], acci[rb + mb]);
+                        const float re = nrm * accr[rb + mb] + (mb == k ? 1.f : 0.f);
+                        u_out[(tile * NH + e) * kTile + lane] = make_float2(re, nrm * acci[rb + mb]);
                     });
                 });
             }
@@ -337,21 +351,6 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_ui(BinState bins, int Nx,
 }
 
 // ------------------------------------------------------------------ Z / B
-struct Triple {
-    int j1, j2, j;
-};
-__host__ __device__ constexpr Triple triple_of(int tj, int idx) {
-    int n = 0;
-    for (int j1 = 0; j1 <= tj; ++j1)
-        for (int j2 = 0; j2 <= j1; ++j2)
-            for (int j = j1 - j2; j <= j1 + j2 && j <= tj; j += 2)
-                if (j >= j1) {
-                    if (n == idx) return Triple{j1, j2, j};
-                    ++n;
-                }
-    return Triple{0, 0, 0};
-}
-
 // u element (J, row r [compile time], column c [runtime, uniform]) from the
 // half storage; rows past J/2 come from the conjugate symmetry.
 template <int J, int R>
@@ -390,6 +389,8 @@ __host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, i
 //   T[ma][ma1] = sum_mb1 (C(mb1,mb) u1[ma1][mb1]) u2[ma-ma1+D][mb-mb1+D]
 // (the scaled u1 element is shared by every row ma), then
 //   Z[ma][mb] = sum_ma1 C(ma1,ma) T[ma][ma1],  B += w_ma Re(conj(u[ma][mb]) Z[ma][mb]).
+// Z has the symmetry of u, so rows ma < J/2 count twice (w = 2) and the
+// middle row of an even J once.
 template <int J1, int J2, int J>
 __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int lane,
                                            const float* __restrict__ cg) {
@@ -471,7 +472,11 @@ __device__ __forceinline__ float zb_dispatch(int t, const float2* __restrict__ s
     if constexpr (T < n_triples(TJ)) {
         if (t == T) {
             constexpr Triple tr = triple_of(TJ, T);
-            return zb_triple<tr.j1, tr.j2, tr.j>(su, lane, cg_table + cg_off[T]);
+            constexpr ZbPerm p = zb_perm(TJ, T);
+            constexpr float scale = (float)(tr.j + 1) / (float)(p.c + 1);
+            const float v = zb_triple<p.a, p.b, p.c>(su, lane, cg_table + cg_off[T]);
+            if constexpr (p.c == tr.j) return v;
+            else return scale * v;
         }
         return zb_dispatch<TJ, T + 1>(t, su, lane, cg_table, cg_off);
     } else {

@@ -1,8 +1,8 @@
 // Energy-space observables in FP64 (Sec. 3.4): the DOS from its partial
 // sums (Eq. DOS.from.ldos), the Fermi level as the root of
-// N_e = int f D (Eq. NumberElectrons_from_DOS) found by bisection, the band
-// energy (Eq. band.energy) and the Fermi weights that turn an LDOS into the
-// density (Eq. density.from.ldos).
+// N_e = int f D (Eq. NumberElectrons_from_DOS), the band energy
+// (Eq. band.energy) and the Fermi weights that turn an LDOS into the density
+// (Eq. density.from.ldos).
 //
 // D is taken piecewise linear between the energy grid points, and the
 // integrals of f, f*e against each linear piece are exact: with
@@ -13,6 +13,11 @@
 // the form that only needs Li_s(-y) with 0 < y <= 1.  Li_s(-y) is summed as
 // its power series for y <= 1/2 and as the Taylor series in ln y about y = 1
 // (coefficients -eta(s-n)/n!, computed on the host) otherwise.
+//
+// The root is bracketed like the paper's TOMS748 solver: Newton steps on
+// N(mu) (dN/dmu = int D (-df/de) needs only f and the first antiderivative)
+// from the zero-temperature root of the piecewise-linear D, kept inside a
+// shrinking [lo, hi] and replaced by the midpoint whenever they leave it.
 #include <math.h>
 
 #include "mala_internal.h"
@@ -42,20 +47,23 @@ __device__ double li_neg(int s, double y, const double* __restrict__ coef) {
     return acc;
 }
 
-// G0, G1, G2 at x (see the file comment).
-__device__ void gfun(double x, const double* coef, double& g0, double& g1, double& g2) {
+// G0, G1 (and G2 if asked) at x (see the file comment), and f(x) = 1/(1+e^x).
+__device__ void gfun(double x, const double* coef, bool need_g2, double& g0, double& g1, double& g2,
+                     double& f) {
     if (x <= 0.0) {
         const double y = exp(x), lg = log1p(y);
-        const double l2 = li_neg(2, y, coef), l3 = li_neg(3, y, coef);
+        const double l2 = li_neg(2, y, coef);
         g0 = x - lg;
         g1 = 0.5 * x * x - x * lg - l2;
-        g2 = x * x * x / 3.0 - x * x * lg - 2.0 * x * l2 + 2.0 * l3;
+        g2 = need_g2 ? x * x * x / 3.0 - x * x * lg - 2.0 * x * l2 + 2.0 * li_neg(3, y, coef) : 0.0;
+        f = 1.0 / (1.0 + y);
     } else {
         const double y = exp(-x), lg = log1p(y);
-        const double l2 = li_neg(2, y, coef), l3 = li_neg(3, y, coef);
+        const double l2 = li_neg(2, y, coef);
         g0 = -lg;
         g1 = kPi * kPi / 6.0 - x * lg + l2;
-        g2 = -x * x * lg + 2.0 * x * l2 + 2.0 * l3;
+        g2 = need_g2 ? -x * x * lg + 2.0 * x * l2 + 2.0 * li_neg(3, y, coef) : 0.0;
+        f = y / (1.0 + y);
     }
 }
 
@@ -71,19 +79,22 @@ __device__ double block_sum(double v, double* red) {
 }
 
 struct FermiShared {
-    double D[256], red[256], g0[256], g1[256], g2[256];
+    double D[256], red[256], g0[256], g1[256], g2[256], f[256], cum[256];
+    double mu0;
+    int first;
 };
 
-// Antiderivatives at every grid point for Fermi level mu (one per thread).
+// Antiderivatives and f at every grid point for Fermi level mu (one per thread).
 __device__ void grid_g(FermiShared& sh, int n_e, double e0, double de, double mu, double kT, const double* coef,
                        bool need_g2) {
     const int e = threadIdx.x;
     if (e < n_e) {
-        double g0, g1, g2;
-        gfun((e0 + e * de - mu) / kT, coef, g0, g1, g2);
+        double g0, g1, g2, f;
+        gfun((e0 + e * de - mu) / kT, coef, need_g2, g0, g1, g2, f);
         sh.g0[e] = g0;
         sh.g1[e] = g1;
-        sh.g2[e] = need_g2 ? g2 : 0.0;
+        sh.g2[e] = g2;
+        sh.f[e] = f;
     }
     __syncthreads();
 }
@@ -104,17 +115,55 @@ __device__ void interval(const FermiShared& sh, int i, double e0, double de, dou
     vr = mu * I1 + K1 * kT;
 }
 
-__device__ double electrons(FermiShared& sh, int n_e, double e0, double de, double mu, double kT,
-                            const double* coef) {
+// N(mu) and dN/dmu.  On [a, b] with t = (e-a)/de, int (-df/de) = f(a) - f(b)
+// and int t (-df/de) = (kT/de)(G0(xb) - G0(xa)) - f(b).
+__device__ void electrons(FermiShared& sh, int n_e, double e0, double de, double mu, double kT,
+                          const double* coef, double& n, double& dn) {
     grid_g(sh, n_e, e0, de, mu, kT, coef, false);
     const int e = threadIdx.x;
-    double c = 0.0;
+    double c = 0.0, dc = 0.0;
     if (e < n_e - 1) {
         double wl, wr, vl, vr;
         interval(sh, e, e0, de, mu, kT, wl, wr, vl, vr);
         c = wl * sh.D[e] + wr * sh.D[e + 1];
+        const double P = sh.f[e] - sh.f[e + 1];
+        const double Q = kT / de * (sh.g0[e + 1] - sh.g0[e]) - sh.f[e + 1];
+        dc = (P - Q) * sh.D[e] + Q * sh.D[e + 1];
     }
-    return block_sum(c, sh.red);
+    n = block_sum(c, sh.red);
+    dn = block_sum(dc, sh.red);
+}
+
+// Zero-temperature root of int_{e0}^{mu} D = n_target for the piecewise-linear
+// D (a block scan of the trapezoids, then the quadratic on the crossing
+// interval); the midpoint of the grid if the count never crosses.
+__device__ double zero_t_root(FermiShared& sh, int n_e, double e0, double de, double n_target) {
+    const int e = threadIdx.x;
+    const double piece = e < n_e - 1 ? 0.5 * de * (sh.D[e] + sh.D[e + 1]) : 0.0;
+    sh.cum[e] = piece;
+    if (e == 0) sh.mu0 = e0 + 0.5 * (n_e - 1) * de;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {          // inclusive scan
+        const double v = e >= off ? sh.cum[e - off] : 0.0;
+        __syncthreads();
+        sh.cum[e] += v;
+        __syncthreads();
+    }
+    const double after = sh.cum[e], before = after - piece;
+    const bool cross = e < n_e - 1 && before <= n_target && n_target < after;
+    if (e == 0) sh.first = n_e;
+    __syncthreads();
+    if (cross) atomicMin(&sh.first, e);               // lowest crossing interval
+    __syncthreads();
+    if (e == sh.first) {
+        // de (D0 t + (D1 - D0) t^2 / 2) = n_target - before, t in [0, 1]
+        const double r = (n_target - before) / de, D0 = sh.D[e], k = sh.D[e + 1] - sh.D[e];
+        const double den = D0 + sqrt(fmax(D0 * D0 + 2.0 * k * r, 0.0));
+        const double t = den > 0.0 ? fmin(fmax(2.0 * r / den, 0.0), 1.0) : 0.5;
+        sh.mu0 = e0 + (e + t) * de;
+    }
+    __syncthreads();
+    return sh.mu0;
 }
 
 // mode 0: exact solve (DOS, result, weights; window coverage if win != NULL)
@@ -144,8 +193,9 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
     sh.D[e] = d;
     __syncthreads();
     const double elast = e0 + (n_e - 1) * de;
-    const double nlo = electrons(sh, n_e, e0, de, e0, kT, coef);
-    const double nhi = electrons(sh, n_e, e0, de, elast, kT, coef);
+    double nlo, nhi, dn;
+    electrons(sh, n_e, e0, de, e0, kT, coef, nlo, dn);
+    electrons(sh, n_e, e0, de, elast, kT, coef, nhi, dn);
     const bool ok = nlo <= n_target && n_target <= nhi;
     if (!ok) {
         if (e == 0) {
@@ -171,14 +221,28 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
     }
     const double tol = mode == 0 ? 1e-12 : 1e-6;
     double lo = e0, hi = elast;
+    double mu = zero_t_root(sh, n_e, e0, de, n_target);
     int it = 0;
-    while (hi - lo >= tol && it < 200) {
-        const double mid = 0.5 * (lo + hi);
-        if (electrons(sh, n_e, e0, de, mid, kT, coef) < n_target) lo = mid;
-        else hi = mid;
+    while (it < 200) {
+        double n;
+        electrons(sh, n_e, e0, de, mu, kT, coef, n, dn);
         ++it;
+        if (n == n_target) break;                       // mu is the root
+        if (n < n_target) lo = mu;
+        else hi = mu;
+        double nx = dn > 0.0 ? mu - (n - n_target) / dn : lo;
+        // a converged step is taken as it is (it may round onto mu, i.e. onto
+        // the end of the bracket just moved there); any other step that
+        // leaves the bracket becomes the midpoint
+        if (dn > 0.0 && fabs(nx - mu) <= 0.1 * tol) {
+            mu = nx;
+            break;
+        }
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        mu = nx;
+        if (hi - lo < tol) break;
     }
-    const double ef = 0.5 * (lo + hi);
+    const double ef = mu;
     const double reach = 40.0 * kT;
     if (mode == 1) {
         if (e == 0) {

@@ -16,7 +16,7 @@ constexpr int kTile = 64;            // grid points per bispectrum tile (one per
 constexpr int kMaxTwojmax = 10;
 constexpr int kMaxCand = 1024;       // candidate atom images per tile
 constexpr int kMaxNbr = 128;         // neighbours per grid point
-constexpr int kMlpBlocks = 1024;     // fixed block count of the network kernels (deterministic partials)
+constexpr int kMlpBlocks = 256;      // fixed block count of the network kernels (one per CU; deterministic partials)
 constexpr int kMaxZbStride = 64;     // per-wave triple list stride (count + indices)
 constexpr int kMlpMaxIn = 128;       // padded input width limit
 constexpr int kMlpMaxHidden = 512;   // hidden width limit
@@ -49,6 +49,63 @@ __host__ __device__ constexpr int n_triples(int tj) {
             for (int j = j1 - j2; j <= j1 + j2 && j <= tj; j += 2)
                 if (j >= j1) ++n;
     return n;
+}
+
+struct Triple {
+    int j1, j2, j;
+};
+__host__ __device__ constexpr Triple triple_of(int tj, int idx) {
+    int n = 0;
+    for (int j1 = 0; j1 <= tj; ++j1)
+        for (int j2 = 0; j2 <= j1; ++j2)
+            for (int j = j1 - j2; j <= j1 + j2 && j <= tj; j += 2)
+                if (j >= j1) {
+                    if (n == idx) return Triple{j1, j2, j};
+                    ++n;
+                }
+    return Triple{0, 0, 0};
+}
+
+// Operation count of the Z/B contraction with output index C and coupled
+// pair (A, B): per output column, every m1' column of u^A updates the
+// (row, row of u^A) pairs of T (4 FMA) after its loads, then the row CG
+// fold over the half rows.
+__host__ __device__ constexpr double zb_cost(int A, int B, int C) {
+    const int D = (A + B - C) / 2, HR = C / 2;
+    int terms = 0;
+    for (int ma = 0; ma <= HR; ++ma)
+        for (int ma1 = 0; ma1 <= A; ++ma1) {
+            const int ma2 = ma - ma1 + D;
+            if (ma2 >= 0 && ma2 <= B) ++terms;
+        }
+    double tot = 0.0;
+    for (int mb = 0; mb <= C; ++mb) {
+        const int lo = mb + D - B > 0 ? mb + D - B : 0, hi = A < mb + D ? A : mb + D;
+        tot += (hi - lo + 1) * (4.0 * terms + 2.0 * (A + 1) + (B + 1) + 2.0) + 2.0 * terms + 3.0 * (HR + 1);
+    }
+    return tot;
+}
+
+// The triple product is invariant under moving the conjugated level:
+// B(j1,j2,j) = (J+1)/(J1+1) I(j,j2 -> j1) = (J+1)/(J2+1) I(j,j1 -> j2), I
+// the same contraction with the named output level.  Each triple is
+// evaluated in the cheapest of the three orientations (first on ties).
+struct ZbPerm {
+    int a, b, c;          // coupled levels a >= b, output level c
+};
+__host__ __device__ constexpr ZbPerm zb_perm(int tj, int idx) {
+    const Triple t = triple_of(tj, idx);
+    ZbPerm best{t.j1, t.j2, t.j};
+    double cbest = zb_cost(t.j1, t.j2, t.j);
+    const ZbPerm alt[2] = {{t.j, t.j2, t.j1}, {t.j, t.j1, t.j2}};
+    for (int i = 0; i < 2; ++i) {
+        const double c = zb_cost(alt[i].a, alt[i].b, alt[i].c);
+        if (c < cbest) {
+            cbest = c;
+            best = alt[i];
+        }
+    }
+    return best;
 }
 
 // compile-time loop helper

@@ -7,9 +7,10 @@
 // Condon-Shortley phase <j1 j1, j2 (j-j1) | j j> > 0, and is lowered in turn.
 // This is a different route from the closed Racah sum.
 //
-// Table layout per descriptor triple (J1, J2, J) (doubled): a dense
-// (J1+1) x (J+1) block c[ma1*(J+1) + ma] = <j1 m1 j2 m2 | j m> with
-// ma1 = j1 + m1, ma = j + m, m2 = m - m1 (zero where m2 is out of range).
+// Table layout per descriptor triple, in its contraction orientation
+// (A, B -> C) (doubled): a dense (A+1) x (C+1) block
+// c[ma1*(C+1) + ma] = <a m1 b m2 | c m> with ma1 = a + m1, ma = c + m,
+// m2 = m - m1 (zero where m2 is out of range).
 #include <math.h>
 #include <string.h>
 
@@ -85,66 +86,45 @@ Coupling couple(int J1, int J2) {
 
 }  // namespace
 
-// Returns the number of floats written, or -1 if cap is too small.
+// Returns the number of floats written, or -1 if cap is too small.  Triple t
+// gets the block of its contraction orientation (A, B -> C) of zb_perm.
 int build_cg_table(int twojmax, float* table, int* offsets, int cap) {
-    int n = 0, t = 0;
+    int n = 0;
     std::vector<Coupling> cache((twojmax + 1) * (twojmax + 1));
     std::vector<bool> have(cache.size(), false);
-    for (int j1 = 0; j1 <= twojmax; ++j1)
-        for (int j2 = 0; j2 <= j1; ++j2)
-            for (int j = j1 - j2; j <= j1 + j2 && j <= twojmax; j += 2) {
-                if (j < j1) continue;
-                const int key = j1 * (twojmax + 1) + j2;
-                if (!have[key]) {
-                    cache[key] = couple(j1, j2);
-                    have[key] = true;
-                }
-                const Coupling& c = cache[key];
-                const int tidx = (j1 + j2 - j) / 2;
-                const int D = (j1 + j2 - j) / 2;
-                offsets[t++] = n;
-                const int sz = (j1 + 1) * (j + 1);
-                if (n + sz > cap) return -1;
-                for (int ma1 = 0; ma1 <= j1; ++ma1)
-                    for (int ma = 0; ma <= j; ++ma) {
-                        const int ma2 = ma - ma1 + D;
-                        double v = 0.0;
-                        if (ma2 >= 0 && ma2 <= j2) v = c.vec[tidx][ma][pidx(j2, ma1, ma2)];
-                        table[n + ma1 * (j + 1) + ma] = (float)v;
-                    }
-                n += sz;
-            }
-    return n;
-}
-
-// Estimated work of one triple in the column-blocked contraction.
-static double triple_cost(int J1, int J2, int J) {
-    const int D = (J1 + J2 - J) / 2, HR = J / 2;
-    double tot = 0.0;
-    for (int mb = 0; mb <= J; ++mb) {
-        for (int mb1 = std::max(0, mb + D - J2); mb1 <= std::min(J1, mb + D); ++mb1) {
-            int terms = 0;
-            for (int ma = 0; ma <= HR; ++ma)
-                for (int ma1 = 0; ma1 <= J1; ++ma1) {
-                    const int ma2 = ma - ma1 + D;
-                    if (ma2 >= 0 && ma2 <= J2) ++terms;
-                }
-            tot += 6.0 * terms + 2.0 * (J1 + 1) + (J2 + 1) + 4.0;
+    for (int t = 0; t < n_triples(twojmax); ++t) {
+        const ZbPerm p = zb_perm(twojmax, t);
+        const int A = p.a, B = p.b, C = p.c;
+        const int key = A * (twojmax + 1) + B;
+        if (!have[key]) {
+            cache[key] = couple(A, B);
+            have[key] = true;
         }
-        tot += 3.0 * (HR + 1);
+        const Coupling& c = cache[key];
+        const int D = (A + B - C) / 2;       // also the index of C in the coupling's list
+        offsets[t] = n;
+        const int sz = (A + 1) * (C + 1);
+        if (n + sz > cap) return -1;
+        for (int ma1 = 0; ma1 <= A; ++ma1)
+            for (int ma = 0; ma <= C; ++ma) {
+                const int ma2 = ma - ma1 + D;
+                double v = 0.0;
+                if (ma2 >= 0 && ma2 <= B) v = c.vec[D][ma][pidx(B, ma1, ma2)];
+                table[n + ma1 * (C + 1) + ma] = (float)v;
+            }
+        n += sz;
     }
-    return tot;
+    return n;
 }
 
 // Longest-processing-time assignment of triples to the waves of a block.
 // wave_triples[w*stride] = count, followed by the triple indices.
 void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride) {
     std::vector<std::pair<double, int>> jobs;
-    int t = 0;
-    for (int j1 = 0; j1 <= twojmax; ++j1)
-        for (int j2 = 0; j2 <= j1; ++j2)
-            for (int j = j1 - j2; j <= j1 + j2 && j <= twojmax; j += 2)
-                if (j >= j1) jobs.push_back({triple_cost(j1, j2, j), t++});
+    for (int t = 0; t < n_triples(twojmax); ++t) {
+        const ZbPerm p = zb_perm(twojmax, t);
+        jobs.push_back({zb_cost(p.a, p.b, p.c), t});
+    }
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
                          return a.first > b.first;

@@ -1,0 +1,110 @@
+"""GPU edge cases through the C ABI: every supported twojmax, a network shape
+other than the two workloads' (generic padded path), the no-root and
+mismatch paths of the fused call, and the neighbour-capacity flag."""
+import sys
+
+import numpy as np
+import pytest
+
+import mala_synth
+import oracle
+
+pytestmark = pytest.mark.gpu
+EG = mala_synth.EGRID
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_19617_amd as mala
+    mala.lib()
+    ctx = mala.Context(0)
+    yield mala, ctx, torch
+    ctx.close()
+
+
+def rel_rows(a, b):
+    return float(np.max(np.max(np.abs(a - b), axis=1) / np.maximum(np.max(np.abs(b), axis=1), 1e-300)))
+
+
+@pytest.mark.parametrize("tj", [2, 4, 6, 8, 10])
+def test_descriptors_every_twojmax(env, tj):
+    mala, ctx, torch = env
+    s = mala_synth.paper_liquid(grid=24)
+    s.twojmax = tj
+    pts = mala_synth.sample_points(s.n_points, 96, 100 + tj)
+    B = ctx.mala_descriptors(s.positions, s.L, s.N, s.rcut, tj).cpu().double().numpy()
+    ctx.check_device_errors()
+    assert B.shape[1] == mala.n_descriptors(tj)
+    err = rel_rows(B[pts], oracle.descriptors(s, pts))
+    log("twojmax", tj, "B rel err", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 3e-2)])
+def test_generic_network_shape(env, prec, tol):
+    mala, ctx, torch = env
+    net = mala_synth.make_net([55, 72, 96, 150], 7, 8, egrid=(-5.0, 0.1, 150))
+    s = mala_synth.small()
+    pts = mala_synth.sample_points(s.n_points, 200, 8)
+    Bref = oracle.descriptors(s, pts).astype(np.float32)
+    w = ctx.weights(mala_synth.net_to_blob(net), prec)
+    ld = ctx.mala_ldos_infer(w, torch.as_tensor(Bref, device="cuda"), 150).cpu().double().numpy()
+    err = rel_rows(ld, oracle.mlp(Bref.astype(np.float64), net))
+    log("generic shape prec", prec, "LDOS rel err", err)
+    assert err <= tol
+
+
+def test_predict_no_root_leaves_density(env):
+    mala, ctx, torch = env
+    s, net = mala_synth.small(), mala_synth.small_net()
+    w = ctx.weights(mala_synth.net_to_blob(net), 0)
+    dens = torch.full((s.n_points,), -7.0, dtype=torch.float64, device="cuda")
+    dos, d2, res = ctx.mala_predict(w, s.positions, s.L, s.N, s.rcut, s.twojmax, EG, s.T, 1e9, dens=dens)
+    r = mala.read_result(res)
+    assert r["status"] == mala.MALA_E_NO_ROOT and np.isnan(r["e_fermi"])
+    assert bool((dens == -7.0).all().item())
+
+
+def test_predict_argument_mismatch(env):
+    mala, ctx, torch = env
+    s, net = mala_synth.small(), mala_synth.small_net()
+    w = ctx.weights(mala_synth.net_to_blob(net), 0)
+    with pytest.raises(mala.MalaError) as e:       # 55-input net with twojmax 10 (91 components)
+        ctx.mala_predict(w, s.positions, s.L, s.N, s.rcut, 10, EG, s.T, s.n_electrons)
+    assert e.value.status == mala.MALA_E_INVALID_ARG
+    with pytest.raises(mala.MalaError) as e:       # 250 outputs vs 100-point energy grid
+        ctx.mala_predict(w, s.positions, s.L, s.N, s.rcut, 8, (-5.0, 0.1, 100), s.T, s.n_electrons)
+    assert e.value.status == mala.MALA_E_INVALID_ARG
+
+
+def test_empty_cell_predict(env):
+    mala, ctx, torch = env
+    net = mala_synth.small_net()
+    w = ctx.weights(mala_synth.net_to_blob(net), 0)
+    L, N = [10.0, 10.0, 10.0], [8, 8, 8]
+    dos, dens, res = ctx.mala_predict(w, np.zeros((0, 3)), L, N, 4.67, 8, EG, 298.0, 30.0)
+    r = mala.read_result(res)
+    assert r["status"] == 0
+    d = dens.cpu().numpy()
+    assert np.max(d) - np.min(d) <= 1e-12 * np.max(d)          # every point sees the same (empty) B
+    assert abs(d.sum() * 1000.0 / 512 - 30.0) <= 1e-9 * 30.0
+
+
+def test_neighbour_capacity_is_reported(env):
+    mala, ctx, torch = env
+    # 200 atoms packed within 1 A of the origin: more than 128 neighbours there
+    rng = mala_synth.SplitMix64(5)
+    pos = (rng.uniform(600).reshape(200, 3) - 0.5) * 1.0 + 5.0
+    B = ctx.mala_descriptors(pos, [10.0, 10.0, 10.0], [4, 4, 4], 4.67, 4)
+    with pytest.raises(mala.MalaError) as e:
+        ctx.check_device_errors()
+    assert e.value.status == mala.MALA_E_CAPACITY
+    ctx.check_device_errors()                                   # flag cleared

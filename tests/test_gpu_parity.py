@@ -242,7 +242,7 @@ def _check_full(ctx, mala, torch, snap, net, gold, prec, tol_eb_mev, tol_dos, to
     assert r["status"] == 0
     assert err_dos <= tol_dos and err_ef <= tol_ef and err_eb <= tol_eb_mev
     assert abs(n.sum() * snap.dV - r["n_found"]) <= 1e-9 * r["n_found"]
-    assert abs(r["n_found"] - snap.n_electrons) <= 1e-6 * snap.n_electrons
+    assert abs(r["n_found"] - snap.n_electrons) <= 1e-10 * snap.n_electrons
     return n, r
 
 
