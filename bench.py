@@ -121,6 +121,132 @@ def measured_traffic(workload):
     return float(kv["traffic_bytes_per_launch"])
 
 
+TRAFFIC_CMDS = """# commands (repository root = $REPO on the GPU box, after cd /tmp && export TMPDIR=/tmp):
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_cfetch -o run -- python $REPO/bench.py --copy-calibration
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_cwrite -o run -- python $REPO/bench.py --copy-calibration
+#   python bench.py --traffic-summary gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/pmc_cfetch gpurun_out/pmc_cwrite
+"""
+COPY_GIB = 1
+
+
+def copy_calibration():
+    """Three plain device-to-device copies of 1 GiB: the reference for scaling
+    FETCH_SIZE / WRITE_SIZE (KiB per dispatch) to bytes."""
+    import torch
+    a = torch.ones(COPY_GIB << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x %d GiB" % COPY_GIB, flush=True)
+
+
+def _pmc_rows(d, counter, kernel_prefix):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    out = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and r["Kernel_Name"].startswith(kernel_prefix):
+                out.append((int(r["Dispatch_Id"]), int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return sorted(out)
+
+
+def traffic_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload="paper_solid"):
+    """Write the calibrated HBM traffic of k_zb<10> into profiles/ from four
+    rocprofv3 --pmc runs (kernel FETCH_SIZE, WRITE_SIZE; copy FETCH_SIZE, WRITE_SIZE)."""
+    copy_kib = float(COPY_GIB << 20)
+    cf = [v for _, _, v in _pmc_rows(cfetch_dir, "FETCH_SIZE", "__amd_rocclr_copyBuffer") if v > 0.5 * copy_kib / 4]
+    cw = [v for _, _, v in _pmc_rows(cwrite_dir, "WRITE_SIZE", "__amd_rocclr_copyBuffer") if v > 0.5 * copy_kib / 4]
+    fs, ws = copy_kib / float(np.mean(cf)), copy_kib / float(np.mean(cw))
+    kz = "void mala::k_zb<10>"
+    fr, wr = _pmc_rows(fetch_dir, "FETCH_SIZE", kz), _pmc_rows(write_dir, "WRITE_SIZE", kz)
+    pts = [g // 512 * 64 for _, g, _ in fr]
+    fb = [v * 1024.0 * fs for _, _, v in fr]
+    wb = [v * 1024.0 * ws for _, _, v in wr]
+    snap = WORKLOADS[workload][0]()
+    tj = snap.twojmax
+    n_half = sum((J // 2 + 1) * (J + 1) for J in range(tj + 1))
+    n_b = (tj + 2) * (tj + 3) * (tj + 4) // 24
+    alg = n_half * 8 + n_b * 4
+    per_launch = float(np.mean(fb) + np.mean(wb))
+    per_point = (sum(fb) + sum(wb)) / float(sum(pts))
+    name = TRAFFIC_FILES[workload]
+    with open(os.path.join(ROOT, "profiles", name), "w") as f:
+        f.write("# HBM traffic of k_zb<10> (Z/B contraction), %s\n" % snap.name)
+        f.write(TRAFFIC_CMDS)
+        f.write("# calibration: the same two counters on a plain %d GiB device-to-device copy (torch copy_ ->\n"
+                "# __amd_rocclr_copyBuffer), %d copies: FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB per copy of %.0f KiB\n"
+                % (COPY_GIB, len(cf), np.mean(cf), np.mean(cw), copy_kib))
+        f.write("# k_zb dispatches (points, tiles x 64): %s\n" % pts)
+        f.write("# FETCH_SIZE KiB per dispatch: %s\n" % [round(v) for _, _, v in fr])
+        f.write("# WRITE_SIZE KiB per dispatch: %s\n" % [round(v) for _, _, v in wr])
+        f.write("# algorithmic bytes per point: read u %d x 8 = %d, write B %d x 4 = %d -> %d\n"
+                % (n_half, n_half * 8, n_b, n_b * 4, alg))
+        f.write("kernel_source_sha256_16=%s\n" % kernel_source_hash())
+        f.write("fetch_scale=%.6f\nwrite_scale=%.6f\n" % (fs, ws))
+        f.write("points_per_launch=%.1f\n" % float(np.mean(pts)))
+        f.write("fetch_bytes_per_launch=%.0f\nwrite_bytes_per_launch=%.0f\n" % (np.mean(fb), np.mean(wb)))
+        f.write("traffic_bytes_per_launch=%.0f\n" % per_launch)
+        f.write("traffic_bytes_per_point=%.1f\n" % per_point)
+    print("wrote profiles/%s: %.1f B/point (algorithmic %d)" % (name, per_point, alg))
+
+
+def _short_kernel_name(n):
+    n = n.replace("(anonymous namespace)", "(anon)")
+    if n.startswith("void "):
+        n = n[5:]
+    depth, out = 0, []
+    for ch in n:                       # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0 and out and out[-1] != ":":
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out)
+
+
+def stats_summary(prof_dir, bench_json, out_name, command):
+    """Markdown kernel table from a rocprofv3 --kernel-trace --stats run plus the
+    bench line of the same build (for the live HIP-event launch time)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(prof_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit("no kernel_stats.csv under %s" % prof_dir)
+    rows = list(csv.DictReader(open(f[0])))
+    b = json.loads(open(bench_json).read().strip().split("\n")[-1])
+    cfg, rf = b["config"], b["roofline"]
+    lines = ["# rocprofv3 kernel stats: %s, %s network" % (cfg["workload"], cfg["network_precision"]), "",
+             "Command (repository root = $REPO on the GPU box):", "", "```",
+             "cd /tmp && export TMPDIR=/tmp && " + command, "```", "",
+             "| kernel | calls | avg ms | min ms | max ms | total ms | share |", "|---|---|---|---|---|---|---|"]
+    zb = None
+    for r in rows:
+        name = _short_kernel_name(r["Name"])
+        lines.append("| `%s` | %s | %.4f | %.4f | %.4f | %.3f | %.1f%% |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6, float(r["MaxNs"]) / 1e6,
+            float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+        if name.startswith("mala::k_zb<"):
+            zb = float(r["AverageNs"]) / 1e6
+    lines += ["", "Dominant kernel `k_zb`: rocprof average %.4f ms per launch; bench.py (same build, "
+              "HIP events on the library stream) %.4f ms per launch over %.0f points: achieved %.1f %s = "
+              "%.3f of the %.1f %s peak (%.1f kflop/point)."
+              % (zb or float("nan"), rf["avg_launch_ms"], rf["points_per_launch"], rf["achieved"], rf["unit"],
+                 rf["frac"], rf["peak"], rf["unit"], rf["flops_per_point"] / 1e3), "",
+              "Per-stage times of the bench step (ms): " + ", ".join(
+                  "%s %.3f" % (k, v["ms_per_step"]) for k, v in b["stages"].items()), ""]
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
+        fo.write("\n".join(lines))
+    print("wrote profiles/%s" % out_name)
+
+
 def errors_vs_oracle(workload, snap, dos, r, dens):
     """Whole-grid errors against the oracle's stored full-grid values (if any)."""
     path = os.path.join(ROOT, "tests", "golden", "full_%s.json" % workload)
@@ -190,7 +316,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--serve-requests", type=int, default=48, help="0 disables the serving stream")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain device copies that calibrate the HBM byte counters")
+    ap.add_argument("--traffic-summary", nargs=4, metavar="DIR",
+                    help="write the calibrated k_zb traffic profile from four rocprofv3 --pmc output "
+                         "directories (kernel FETCH_SIZE, WRITE_SIZE; copy FETCH_SIZE, WRITE_SIZE); no GPU")
+    ap.add_argument("--stats-summary", nargs=4, metavar=("PROF_DIR", "BENCH_LOG", "OUT_NAME", "COMMAND"),
+                    help="write a profiles/ markdown table from a rocprofv3 --kernel-trace --stats run; no GPU")
     a = ap.parse_args()
+    if a.stats_summary:
+        stats_summary(*a.stats_summary)
+        return
+    if a.traffic_summary:
+        traffic_summary(*a.traffic_summary)
+        return
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU: the path shards by grid slabs with one 2 KB DOS all-reduce, "
               "but multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
