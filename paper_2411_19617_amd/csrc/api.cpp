@@ -169,7 +169,7 @@ mala_status ensure_tables(mala_ctx* c, int tj) {
     std::vector<int> off(n_triples(tj));
     int n = build_cg_table(tj, tab.data(), off.data(), (int)tab.size());
     if (n < 0) return fail(MALA_E_UNSUPPORTED, "Clebsch-Gordan table too large");
-    t.zb_waves = 8;
+    t.zb_waves = 12;      // three waves per SIMD share the LDS tile
     std::vector<int> waves(t.zb_waves * kMaxZbStride, 0);
     plan_zb_waves(tj, t.zb_waves, waves.data(), kMaxZbStride);
     HIP_TRY(hipMalloc(&t.cg, sizeof(float) * (n > 0 ? n : 1)));

@@ -6,13 +6,14 @@
 //  k_ui  -- neighbour gather and the expansion coefficients
 //           u^J = I + sum_k f_c(r_k) U^J(g_k).  U^J is the spin-J/2 irrep of
 //           g written as a polynomial action on (xi, eta); its unnormalised
-//           coefficients are built level by level from f_c: row 0 of level J
-//           from row 0 of level J-1, and row ma >= 1 of level J from row ma-1
-//           of level J-1, and are normalised once after the neighbour sum.
-//           The rows that share J-ma form independent chains;
-//           the chains are split over the waves of the block so that each
-//           wave keeps its share of u in registers over the whole neighbour
-//           loop.  Only rows ma <= J/2 are formed; the rest follow from
+//           coefficients are products of powers of a, b and their conjugates.
+//           The rows that share J-ma form independent chains: the first row
+//           of a chain comes from powers of b and f_c conj(a), each later row
+//           from the previous one (one more factor), and everything is
+//           normalised once after the neighbour sum.  The chains are split
+//           over the waves of the block so that each wave keeps its share of
+//           u in registers over the whole neighbour loop.  Only rows
+//           ma <= J/2 are formed; the rest follow from
 //           u_{J-ma,J-mb} = (-1)^(ma-mb) conj(u_{ma,mb}).
 //
 //  k_zb  -- the tile's half-u (271 complex per point at twojmax 10, 139 KB
@@ -24,9 +25,10 @@
 //           half rows.
 //           Each triple is contracted in whichever of its three
 //           orientations (which level is the conjugated output) costs
-//           least; Clebsch-Gordan values of that coupling come from a
-//           per-triple table in global memory read with wave-uniform
-//           (scalar) loads.
+//           least, and when its two coupled levels are equal only one of
+//           each exchanged pair of rows is formed.  Clebsch-Gordan values of
+//           the coupling come from a per-triple table in global memory read
+//           with wave-uniform (scalar) loads.
 #include "mala_internal.h"
 
 namespace mala {
@@ -46,11 +48,17 @@ __host__ __device__ constexpr int chain_len(int tj, int q) {
     for (int k = 0; k < chain_rows(tj, q); ++k) n += q + k + 1;
     return n;
 }
-__host__ __device__ constexpr int n_groups(int tj) { return tj >= 8 ? 2 : 1; }
+// Chains are split over four waves at twojmax 8 and 10 (operation counts
+// balanced to within 4%, at most 75 complex accumulators per wave, and
+// power tables small enough that every wave keeps its share in VGPRs with
+// two waves per SIMD); one wave below that.
+__host__ __device__ constexpr int n_groups(int tj) { return tj >= 8 ? 4 : 1; }
 __host__ __device__ constexpr bool in_group(int tj, int g, int q) {
-    if (tj == 10) return g == 0 ? (q == 0 || q == 1 || q == 5 || q == 6 || q == 7)
-                                : (q == 2 || q == 3 || q == 4 || q == 8 || q == 9 || q == 10);
-    if (tj == 8) return g == 0 ? (q <= 4) : (q >= 5);
+    if (tj == 10) return g == 0 ? (q == 0 || q == 5 || q == 10)
+                       : g == 1 ? (q == 1 || q == 2 || q == 3 || q == 4)
+                       : g == 2 ? (q == 6 || q == 9)
+                                : (q == 7 || q == 8);
+    if (tj == 8) return g == 0 ? (q <= 3) : g == 1 ? (q == 4) : g == 2 ? (q == 5 || q == 8) : (q == 6 || q == 7);
     return g == 0;
 }
 __host__ __device__ constexpr int group_size(int tj, int g) {
@@ -77,76 +85,117 @@ __host__ __device__ constexpr int row_slot(int q, int k) {
     return n;
 }
 
+__host__ __device__ constexpr double ce_binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
 // Accumulate f_c * c(g) of one neighbour into the group's registers, where
 // c^J[ma][mb] is the coefficient of xi^mb eta^(J-mb) in
 // (a xi - conj(b) eta)^ma (b xi + conj(a) eta)^(J-ma); U^J = N c^J with
-// N = sqrt(mb! (J-mb)! / (ma! (J-ma)!)) applied once at write-out.  The
-// coefficients obey two plain recursions (multiply the polynomial by one
-// more factor):
-//   row 0:   c^J[0][mb]  = b c^{J-1}[0][mb-1] + conj(a) c^{J-1}[0][mb]
+// N = sqrt(mb! (J-mb)! / (ma! (J-ma)!)) applied once at write-out.
+// Row 0 of level q is binom(q, mb) b^mb conj(a)^(q-mb) (from powers of b
+// and f_c conj(a) shared by the group's chains); the later rows of a chain
+// follow from multiplying by one more factor:
 //   row k:   c^J[k][mb]  = a c^{J-1}[k-1][mb-1] - conj(b) c^{J-1}[k-1][mb]
+// and the chain's last row is summed into the accumulators directly.
 template <int TJ, int G, int NACC>
 __device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float bi, float fc,
                                              float (&accr)[NACC], float (&acci)[NACC]) {
     constexpr int QMAX = group_qmax(TJ, G);
-    float r0r[TJ + 1], r0i[TJ + 1];
-    r0r[0] = fc;
-    r0i[0] = 0.f;
-    if constexpr (in_group(TJ, G, 0)) accr[chain_slot(TJ, G, 0)] += fc;
-    static_for<1, QMAX + 1>([&](auto Jc) {
-        constexpr int J = decltype(Jc)::value;
-        static_for<0, J + 1>([&](auto ic) {
-            constexpr int mb = J - decltype(ic)::value;   // in place, high mb first
-            float nr = 0.f, ni = 0.f;
-            if constexpr (mb >= 1) {                        // b * old[mb-1]
-                const float orr = r0r[mb - 1], oi = r0i[mb - 1];
-                nr = fmaf(br, orr, -bi * oi);
-                ni = fmaf(br, oi, bi * orr);
-            }
-            if constexpr (mb <= J - 1) {                    // conj(a) * old[mb]
-                const float orr = r0r[mb], oi = r0i[mb];
-                nr = fmaf(ar, orr, fmaf(ai, oi, nr));
-                ni = fmaf(ar, oi, fmaf(-ai, orr, ni));
-            }
-            r0r[mb] = nr;
-            r0i[mb] = ni;
-        });
-        if constexpr (in_group(TJ, G, J)) {
-            constexpr int Q = J;
+    float pbr[QMAX + 1], pbi[QMAX + 1], par[QMAX + 1], pai[QMAX + 1];   // b^k, fc conj(a)^k
+    par[0] = fc;
+    pai[0] = 0.f;
+    static_for<1, QMAX + 1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (k == 1) {
+            pbr[1] = br;
+            pbi[1] = bi;
+            par[1] = fc * ar;
+            pai[1] = -fc * ai;
+        } else {
+            pbr[k] = fmaf(pbr[k - 1], br, -pbi[k - 1] * bi);
+            pbi[k] = fmaf(pbr[k - 1], bi, pbi[k - 1] * br);
+            par[k] = fmaf(par[k - 1], ar, pai[k - 1] * ai);
+            pai[k] = fmaf(pai[k - 1], ar, -par[k - 1] * ai);
+        }
+    });
+    static_for<0, TJ + 1>([&](auto qc) {
+        constexpr int Q = decltype(qc)::value;
+        if constexpr (in_group(TJ, G, Q)) {
             constexpr int base = chain_slot(TJ, G, Q);
+            constexpr int NR = chain_rows(TJ, Q);
             float cr[TJ + 1], ci[TJ + 1];
             static_for<0, Q + 1>([&](auto mc) {
                 constexpr int mb = decltype(mc)::value;
-                cr[mb] = r0r[mb];
-                ci[mb] = r0i[mb];
-                accr[base + mb] += cr[mb];
-                acci[base + mb] += ci[mb];
+                constexpr float bin = (float)ce_binom(Q, mb);
+                float xr, xi;
+                if constexpr (mb == 0) {
+                    xr = par[Q];
+                    xi = pai[Q];
+                } else if constexpr (mb == Q) {
+                    xr = fc * pbr[Q];
+                    xi = fc * pbi[Q];
+                } else {
+                    xr = fmaf(pbr[mb], par[Q - mb], -pbi[mb] * pai[Q - mb]);
+                    xi = fmaf(pbr[mb], pai[Q - mb], pbi[mb] * par[Q - mb]);
+                }
+                if constexpr (bin != 1.f) {
+                    xr *= bin;
+                    xi *= bin;
+                }
+                cr[mb] = xr;
+                ci[mb] = xi;
+                accr[base + mb] += xr;
+                if constexpr (Q > 0) acci[base + mb] += xi;     // level 0 is the real f_c
             });
-            static_for<1, chain_rows(TJ, Q)>([&](auto kc) {
+            static_for<1, NR>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 constexpr int Jp = Q + k;
-                static_for<0, Jp + 1>([&](auto ic) {
-                    constexpr int mb = Jp - decltype(ic)::value;
-                    float nr = 0.f, ni = 0.f;
-                    if constexpr (mb >= 1) {                // a * old[mb-1]
-                        const float orr = cr[mb - 1], oi = ci[mb - 1];
-                        nr = fmaf(ar, orr, -ai * oi);
-                        ni = fmaf(ar, oi, ai * orr);
-                    }
-                    if constexpr (mb <= Jp - 1) {           // - conj(b) * old[mb]
-                        const float orr = cr[mb], oi = ci[mb];
-                        nr = fmaf(-br, orr, fmaf(-bi, oi, nr));
-                        ni = fmaf(-br, oi, fmaf(bi, orr, ni));
-                    }
-                    cr[mb] = nr;
-                    ci[mb] = ni;
-                });
                 constexpr int rb = base + row_slot(Q, k);
-                static_for<0, Jp + 1>([&](auto mc) {
-                    constexpr int mb = decltype(mc)::value;
-                    accr[rb + mb] += cr[mb];
-                    acci[rb + mb] += ci[mb];
-                });
+                if constexpr (k == NR - 1) {
+                    static_for<0, Jp + 1>([&](auto mc) {
+                        constexpr int mb = decltype(mc)::value;
+                        float sr = accr[rb + mb], si = acci[rb + mb];
+                        if constexpr (mb >= 1) {                // a * old[mb-1]
+                            sr = fmaf(ar, cr[mb - 1], sr);
+                            sr = fmaf(-ai, ci[mb - 1], sr);
+                            si = fmaf(ar, ci[mb - 1], si);
+                            si = fmaf(ai, cr[mb - 1], si);
+                        }
+                        if constexpr (mb <= Jp - 1) {           // - conj(b) * old[mb]
+                            sr = fmaf(-br, cr[mb], sr);
+                            sr = fmaf(-bi, ci[mb], sr);
+                            si = fmaf(-br, ci[mb], si);
+                            si = fmaf(bi, cr[mb], si);
+                        }
+                        accr[rb + mb] = sr;
+                        acci[rb + mb] = si;
+                    });
+                } else {
+                    static_for<0, Jp + 1>([&](auto ic) {
+                        constexpr int mb = Jp - decltype(ic)::value;   // in place, high mb first
+                        float nr = 0.f, ni = 0.f;
+                        if constexpr (mb >= 1) {                // a * old[mb-1]
+                            const float orr = cr[mb - 1], oi = ci[mb - 1];
+                            nr = fmaf(ar, orr, -ai * oi);
+                            ni = fmaf(ar, oi, ai * orr);
+                        }
+                        if constexpr (mb <= Jp - 1) {           // - conj(b) * old[mb]
+                            const float orr = cr[mb], oi = ci[mb];
+                            nr = fmaf(-br, orr, fmaf(-bi, oi, nr));
+                            ni = fmaf(-br, oi, fmaf(bi, orr, ni));
+                        }
+                        cr[mb] = nr;
+                        ci[mb] = ni;
+                    });
+                    static_for<0, Jp + 1>([&](auto mc) {
+                        constexpr int mb = decltype(mc)::value;
+                        accr[rb + mb] += cr[mb];
+                        acci[rb + mb] += ci[mb];
+                    });
+                }
             });
         }
     });
@@ -192,7 +241,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total)
 }
 
 template <int TJ>
-__global__ __launch_bounds__(64 * n_groups(TJ)) void k_ui(BinState bins, int Nx, int Ny, int Nz,
+__global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int Nx, int Ny, int Nz,
                                                           double rcut, int64_t pt_begin, int64_t n_pts,
                                                           float2* __restrict__ u_out,
                                                           int* __restrict__ err) {
@@ -364,25 +413,36 @@ __device__ __forceinline__ float2 uload(const float2* __restrict__ su, int c, in
     }
 }
 
-// Number of (ma, ma1) row pairs of a triple: ma <= J/2, ma2 = ma - ma1 + D in [0, J2].
+// Number of (ma, ma1) row pairs of a triple (rows ma <= J/2), their index,
+// and which rows of u^{J1} and u^{J2} they use.
 __host__ __device__ constexpr int zb_pairs(int J1, int J2, int J) {
     int n = 0;
-    const int D = (J1 + J2 - J) / 2;
     for (int ma = 0; ma <= J / 2; ++ma)
         for (int ma1 = 0; ma1 <= J1; ++ma1)
-            if (ma - ma1 + D >= 0 && ma - ma1 + D <= J2) ++n;
+            if (zb_pair_ok(J1, J2, J, ma, ma1)) ++n;
     return n;
 }
 __host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, int ma1) {
     int n = 0;
-    const int D = (J1 + J2 - J) / 2;
     for (int a = 0; a <= J / 2; ++a)
         for (int a1 = 0; a1 <= J1; ++a1)
-            if (a - a1 + D >= 0 && a - a1 + D <= J2) {
+            if (zb_pair_ok(J1, J2, J, a, a1)) {
                 if (a == ma && a1 == ma1) return n;
                 ++n;
             }
     return -1;
+}
+__host__ __device__ constexpr bool zb_row1_used(int J1, int J2, int J, int ma1) {
+    for (int ma = 0; ma <= J / 2; ++ma)
+        if (zb_pair_ok(J1, J2, J, ma, ma1)) return true;
+    return false;
+}
+__host__ __device__ constexpr bool zb_row2_used(int J1, int J2, int J, int r) {
+    const int D = (J1 + J2 - J) / 2;
+    for (int ma = 0; ma <= J / 2; ++ma)
+        for (int ma1 = 0; ma1 <= J1; ++ma1)
+            if (zb_pair_ok(J1, J2, J, ma, ma1) && ma - ma1 + D == r) return true;
+    return false;
 }
 
 // B(j1,j2,j) of the lane's point.  For each output column mb:
@@ -390,7 +450,8 @@ __host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, i
 // (the scaled u1 element is shared by every row ma), then
 //   Z[ma][mb] = sum_ma1 C(ma1,ma) T[ma][ma1],  B += w_ma Re(conj(u[ma][mb]) Z[ma][mb]).
 // Z has the symmetry of u, so rows ma < J/2 count twice (w = 2) and the
-// middle row of an even J once.
+// middle row of an even J once.  For J1 == J2 only the pairs of zb_pair_ok
+// are formed; the others equal their exchanged partner (zb_pair_doubled).
 template <int J1, int J2, int J>
 __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int lane,
                                            const float* __restrict__ cg) {
@@ -399,6 +460,7 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
     constexpr int W = J + 1;               // cg row stride: cg[ma1*W + ma]
     constexpr int NP = zb_pairs(J1, J2, J);
     float bsum = 0.f;
+#pragma clang loop unroll(disable)
     for (int mb = 0; mb <= J; ++mb) {
         float tr[NP], ti[NP];
         // one m1' column: the first one initialises T, the others accumulate
@@ -409,8 +471,7 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
             float u2r[J2 + 1], u2i[J2 + 1];
             static_for<0, J2 + 1>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
-                constexpr bool used = (r - D <= J1) && (r <= HR + D);
-                if constexpr (used) {
+                if constexpr (zb_row2_used(J1, J2, J, r)) {
                     const float2 v = uload<J2, r>(su, mb2, lane);
                     u2r[r] = v.x;
                     u2i[r] = v.y;
@@ -418,14 +479,13 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
             });
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
-                constexpr bool used = (ma1 - D <= HR) && (ma1 - D + J2 >= 0);
-                if constexpr (used) {
+                if constexpr (zb_row1_used(J1, J2, J, ma1)) {
                     const float2 v = uload<J1, ma1>(su, mb1, lane);
                     const float wr = c2 * v.x, wi = c2 * v.y;
                     static_for<0, HR + 1>([&](auto mc) {
                         constexpr int ma = decltype(mc)::value;
                         constexpr int ma2 = ma - ma1 + D;
-                        if constexpr (ma2 >= 0 && ma2 <= J2) {
+                        if constexpr (zb_pair_ok(J1, J2, J, ma, ma1)) {
                             constexpr int k = zb_pair_index(J1, J2, J, ma, ma1);
                             if constexpr (FIRST) {
                                 tr[k] = fmaf(-wi, u2i[ma2], wr * u2r[ma2]);
@@ -443,20 +503,31 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
         };
         const int lo = max(0, mb + D - J2), hi = min(J1, mb + D);   // never empty
         column(lo, std::true_type{});
+        // runtime loops stay rolled: unrolling them spills (the whole triple
+        // list is inlined into one kernel) and doubles the code size
+#pragma clang loop unroll(disable)
         for (int mb1 = lo + 1; mb1 <= hi; ++mb1) column(mb1, std::false_type{});
         static_for<0, HR + 1>([&](auto mc) {
             constexpr int ma = decltype(mc)::value;
-            float zr = 0.f, zi = 0.f;
+            float zr = 0.f, zi = 0.f, zr2 = 0.f, zi2 = 0.f;
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
-                constexpr int ma2 = ma - ma1 + D;
-                if constexpr (ma2 >= 0 && ma2 <= J2) {
+                if constexpr (zb_pair_ok(J1, J2, J, ma, ma1)) {
                     constexpr int k = zb_pair_index(J1, J2, J, ma, ma1);
                     const float c1 = cg[ma1 * W + ma];
-                    zr = fmaf(c1, tr[k], zr);
-                    zi = fmaf(c1, ti[k], zi);
+                    if constexpr (zb_pair_doubled(J1, J2, J, ma, ma1)) {
+                        zr2 = fmaf(c1, tr[k], zr2);
+                        zi2 = fmaf(c1, ti[k], zi2);
+                    } else {
+                        zr = fmaf(c1, tr[k], zr);
+                        zi = fmaf(c1, ti[k], zi);
+                    }
                 }
             });
+            if constexpr (J1 == J2) {
+                zr = fmaf(2.f, zr2, zr);
+                zi = fmaf(2.f, zi2, zi);
+            }
             constexpr float w = (2 * ma < J) ? 2.f : 1.f;
             const float2 uj = su[(half_off(J) + ma * (J + 1) + mb) * kTile + lane];
             bsum += w * (uj.x * zr + uj.y * zi);
@@ -485,7 +556,7 @@ __device__ __forceinline__ float zb_dispatch(int t, const float2* __restrict__ s
 }
 
 template <int TJ>
-__global__ __launch_bounds__(512) void k_zb(const float2* __restrict__ u, int64_t n_pts,
+__global__ __launch_bounds__(768) void k_zb(const float2* __restrict__ u, int64_t n_pts,
                                              float* __restrict__ B, const float* __restrict__ cg_table,
                                              const int* __restrict__ cg_off,
                                              const int* __restrict__ wave_triples, int stride) {

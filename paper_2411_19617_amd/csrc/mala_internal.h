@@ -66,18 +66,29 @@ __host__ __device__ constexpr Triple triple_of(int tj, int idx) {
     return Triple{0, 0, 0};
 }
 
+// Pairs (row ma of the output level, row ma1 of level A) of the Z/B
+// contraction with coupled levels (A, B) and output C: the row of level B is
+// ma2 = ma - ma1 + (A+B-C)/2.  When A == B, exchanging the two coupled
+// factors maps pair (ma, ma1) to (ma, ma2) and multiplies both its T sum and
+// its row Clebsch-Gordan factor by the same sign (-1)^((A+B-C)/2), so only
+// ma1 <= ma2 is formed and ma1 < ma2 counts twice.
+__host__ __device__ constexpr bool zb_pair_ok(int A, int B, int C, int ma, int ma1) {
+    const int ma2 = ma - ma1 + (A + B - C) / 2;
+    return ma2 >= 0 && ma2 <= B && (A != B || ma1 <= ma2);
+}
+__host__ __device__ constexpr bool zb_pair_doubled(int A, int B, int C, int ma, int ma1) {
+    return A == B && zb_pair_ok(A, B, C, ma, ma1) && ma1 < ma - ma1 + (A + B - C) / 2;
+}
+
 // Operation count of the Z/B contraction with output index C and coupled
-// pair (A, B): per output column, every m1' column of u^A updates the
-// (row, row of u^A) pairs of T (4 FMA) after its loads, then the row CG
-// fold over the half rows.
+// pair (A, B): per output column, every m1' column of u^A updates the pairs
+// of T (4 FMA) after its loads, then the row CG fold over the half rows.
 __host__ __device__ constexpr double zb_cost(int A, int B, int C) {
     const int D = (A + B - C) / 2, HR = C / 2;
     int terms = 0;
     for (int ma = 0; ma <= HR; ++ma)
-        for (int ma1 = 0; ma1 <= A; ++ma1) {
-            const int ma2 = ma - ma1 + D;
-            if (ma2 >= 0 && ma2 <= B) ++terms;
-        }
+        for (int ma1 = 0; ma1 <= A; ++ma1)
+            if (zb_pair_ok(A, B, C, ma, ma1)) ++terms;
     double tot = 0.0;
     for (int mb = 0; mb <= C; ++mb) {
         const int lo = mb + D - B > 0 ? mb + D - B : 0, hi = A < mb + D ? A : mb + D;

@@ -52,6 +52,7 @@ struct Prec<0> {
     using T = float;
     static constexpr int K = 4;      // units per K-step
     static constexpr int PF = 4;     // K-steps per batch
+    static constexpr int DA = 2;     // weight batches fetched ahead
     struct BatchA { float v[4]; };
     struct BatchB { float4 v; };
     __host__ __device__ static int stride(int w) { return ((w + 63) / 64) * 64 + 4; }
@@ -63,12 +64,10 @@ struct Prec<0> {
     __device__ static void loadB(BatchB& b, const T* row, int q, int g) {
         b.v = *reinterpret_cast<const float4*>(row + 16 * q + 4 * g);
     }
-    __device__ static f4 mma_batch(const BatchA& a, const BatchB& b, f4 c) {
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[0], b.v.x, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[1], b.v.y, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[2], b.v.z, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[3], b.v.w, c, 0, 0, 0);
-        return c;
+    template <int S>
+    __device__ static f4 mma_step(const BatchA& a, const BatchB& b, f4 c) {
+        const float bv = S == 0 ? b.v.x : S == 1 ? b.v.y : S == 2 ? b.v.z : b.v.w;
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[S], bv, c, 0, 0, 0);
     }
     __device__ static void store4(T* dst, f4 v) {
         *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
@@ -77,37 +76,29 @@ struct Prec<0> {
 };
 
 // BF16: MFMA 16x16x32, K-step s of lane group g uses units 32 s + 8 g + 0..7.
+// One K-step per batch (a 16x16x32 MFMA is short, so the weights are fetched
+// five batches ahead instead of holding larger batches).
 template <>
 struct Prec<1> {
     using T = __bf16;
     static constexpr int K = 32;
-    static constexpr int PF = 2;
-    struct BatchA { uint4 v[2]; };
-    struct BatchB { uint4 v[2]; };
+    static constexpr int PF = 1;
+    static constexpr int DA = 5;
+    struct BatchA { uint4 v; };
+    struct BatchB { uint4 v; };
     __host__ __device__ static int stride(int w) { return ((w + 127) / 128) * 128 + 8; }
     __device__ static void loadA(BatchA& a, const void* A, size_t base, int q) {
-        const uint4* p = static_cast<const uint4*>(A) + base + (size_t)q * PF * 64;
-        a.v[0] = p[0];
-        a.v[1] = p[64];
+        a.v = static_cast<const uint4*>(A)[base + (size_t)q * 64];
     }
     __device__ static void loadB(BatchB& b, const T* row, int q, int g) {
-        b.v[0] = *reinterpret_cast<const uint4*>(row + 32 * (PF * q) + 8 * g);
-        b.v[1] = *reinterpret_cast<const uint4*>(row + 32 * (PF * q + 1) + 8 * g);
+        b.v = *reinterpret_cast<const uint4*>(row + 32 * q + 8 * g);
     }
-    __device__ static f4 mma1(uint4 av, uint4 bv, f4 c) {
-        bf8 a, b;
-        __builtin_memcpy(&a, &av, 16);
-        __builtin_memcpy(&b, &bv, 16);
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    }
-    __device__ static f4 mma_batch(const BatchA& a, const BatchB& b, f4 c) {
-        c = mma1(a.v[0], b.v[0], c);
-        return mma1(a.v[1], b.v[1], c);
-    }
-    __device__ static f4 mma_tail(const void* A, size_t base, int s, const T* row, int g, f4 c) {
-        const uint4 av = static_cast<const uint4*>(A)[base + (size_t)s * 64];
-        const uint4 bv = *reinterpret_cast<const uint4*>(row + 32 * s + 8 * g);
-        return mma1(av, bv, c);
+    template <int S>
+    __device__ static f4 mma_step(const BatchA& a, const BatchB& b, f4 c) {
+        bf8 x, y;
+        __builtin_memcpy(&x, &a.v, 16);
+        __builtin_memcpy(&y, &b.v, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
     }
     __device__ static void store4(T* dst, f4 v) {
         bf4 h = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
@@ -116,44 +107,57 @@ struct Prec<1> {
     __device__ static T cvt(float x) { return (__bf16)x; }
 };
 
-// acc[n] += sum over K-steps s < KS of A(s) B_n(s).  Batches of PF K-steps:
-// weights fetched two batches ahead, LDS operands one batch ahead, no
-// per-step branches.  FP32 K-step counts are multiples of PF; BF16 may
-// leave one tail step.
+// acc[n] += sum over K-steps s < KS of A(s) B_n(s), in batches of PF K-steps
+// (KS is a multiple of PF).  Weights (from L2) are fetched DA batches ahead
+// into a ring of DA+1 register sets, LDS operands one batch ahead into a
+// ring of two; the loop is unrolled by a multiple of both ring sizes so the
+// sets rotate by name: no register copies and no wait on a load issued in
+// the same batch.  Within a batch the MFMAs go K-step by K-step over the NA
+// independent accumulators.
 template <int PREC, int NA>
 __device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const typename Prec<PREC>::T* const (&rows)[NA],
                                       int g, f4 (&acc)[NA]) {
     using P = Prec<PREC>;
     using BA = typename P::BatchA;
     using BB = typename P::BatchB;
+    constexpr int RA = P::DA + 1;
+    constexpr int U = RA % 2 == 0 ? RA : 2 * RA;
     const int NQ = KS / P::PF;
-    BA a0, a1, a2;
-    BB b0[NA], b1[NA];
-    if (NQ > 0) {
-        P::loadA(a0, A, base, 0);
+    BA a[RA];
+    BB b[2][NA];
+    auto fetchB = [&](int q, BB (&bd)[NA]) {
 #pragma unroll
-        for (int n = 0; n < NA; ++n) P::loadB(b0[n], rows[n], 0, g);
-    }
-    if (NQ > 1) P::loadA(a1, A, base, 1);
-    for (int q = 0; q < NQ; ++q) {
-        if (q + 2 < NQ) P::loadA(a2, A, base, q + 2);
-        if (q + 1 < NQ) {
+        for (int n = 0; n < NA; ++n) P::loadB(bd[n], rows[n], q, g);
+    };
+    auto mma = [&](const BA& as, const BB (&bs)[NA]) {
+        static_for<0, P::PF>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
 #pragma unroll
-            for (int n = 0; n < NA; ++n) P::loadB(b1[n], rows[n], q + 1, g);
-        }
-#pragma unroll
-        for (int n = 0; n < NA; ++n) acc[n] = P::mma_batch(a0, b0[n], acc[n]);
-        a0 = a1;
-        a1 = a2;
-#pragma unroll
-        for (int n = 0; n < NA; ++n) b0[n] = b1[n];
-    }
-    if constexpr (PREC == 1) {
-        for (int s = NQ * P::PF; s < KS; ++s) {
-#pragma unroll
-            for (int n = 0; n < NA; ++n) acc[n] = P::mma_tail(A, base, s, rows[n], g, acc[n]);
-        }
-    }
+            for (int n = 0; n < NA; ++n) acc[n] = P::template mma_step<S>(as, bs[n], acc[n]);
+        });
+    };
+    // batch q + u (u < U) lives in a[u % RA] and b[u % 2].  Prefetches past
+    // the last batch re-read the last batch (unused): every load is
+    // unconditional, so the waits count exactly the loads still needed.
+    auto step = [&](int q, auto uc) {
+        constexpr int u = decltype(uc)::value;
+        const int qa = q + u + P::DA < NQ ? q + u + P::DA : NQ - 1;
+        const int qb = q + u + 1 < NQ ? q + u + 1 : NQ - 1;
+        P::loadA(a[(u + P::DA) % RA], A, base, qa);
+        fetchB(qb, b[(u + 1) % 2]);
+        mma(a[u % RA], b[u % 2]);
+    };
+    if (NQ <= 0) return;
+    static_for<0, P::DA>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        P::loadA(a[i], A, base, i < NQ ? i : NQ - 1);
+    });
+    fetchB(0, b[0]);
+    int q = 0;
+    for (; q + U <= NQ; q += U) static_for<0, U>([&](auto uc) { step(q, uc); });
+    static_for<0, U>([&](auto uc) {
+        if (q + decltype(uc)::value < NQ) step(q, uc);
+    });
 }
 
 // One dense layer on the waves of the block: out[p][16 mt + u] = act(W x + b).
@@ -200,7 +204,6 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
     __shared__ double s_dos[kMlpMaxOut];
     __shared__ double s_part[kWaves][NP];
     __shared__ double s_w[kMlpMaxOut];
-    __shared__ double s_c;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = lane & 15, g = lane >> 4;
@@ -218,18 +221,13 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
     T* H2 = X0;
 
     if constexpr (MODE == kModeDensity || MODE == kModeDosWindow) {
-        // weights of the per-point energy sum: density -> w_e*s_e (+ sum w_e c_e),
+        // weights of the per-point energy sum: density -> Fermi weights w_e,
         // window prefix -> trapezoid weight de (de/2 at e = 0) below lo
         for (int e = threadIdx.x; e < kMlpMaxOut; e += blockDim.x) {
             double we = 0.0;
             if (MODE == kModeDensity) we = e < a.n_out ? o.fermi_w[e] : 0.0;
             else we = (e < lo) ? (e == 0 ? 0.5 * o.de : o.de) : 0.0;
             s_w[e] = we;
-        }
-        if (threadIdx.x == 0 && MODE == kModeDensity) {
-            double c = 0.0;
-            for (int e = 0; e < a.n_out; ++e) c += o.fermi_w[e] * (double)a.out_shift[e];
-            s_c = c;
         }
     }
     if constexpr (MODE == kModeDos || MODE == kModeDosWindow)
@@ -293,6 +291,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
             for (int r = 0; r < 4; ++r) {
                 const int e = 16 * ot + 4 * g + r;
                 const bool ev = e < a.n_out;
+                // every mode forms the same float LDOS value d = s y + c (affine map
+                // in FP64, rounded once), so that the stored LDOS, the DOS, the
+                // window, its prefix and a recomputed density all use identical numbers
                 const double sc = ev ? (double)a.out_scale[e] : 0.0, sh = ev ? (double)a.out_shift[e] : 0.0;
                 double dsum = 0.0;
 #pragma unroll
@@ -301,16 +302,17 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
                     const bool pv = (16 * n + j) < rows;
                     float yv = acc3[i][n][r];
                     if (a.out_act) yv = leaky(yv, a.slope);
+                    const float df = (float)(sc * (double)yv + sh);
                     if constexpr (MODE == kModeLdos) {
-                        if (pv && ev) o.ldos[p * a.n_out + e] = a.out_scale[e] * yv + a.out_shift[e];
+                        if (pv && ev) o.ldos[p * a.n_out + e] = df;
                     } else if constexpr (MODE == kModeDensity) {
-                        if (ev) part[n] += s_w[e] * (sc * (double)yv);
+                        if (ev) part[n] += s_w[e] * (double)df;
                     } else {
-                        const double d = (pv && ev) ? sc * (double)yv + sh : 0.0;
+                        const double d = (pv && ev) ? (double)df : 0.0;
                         dsum += d;
                         if constexpr (MODE == kModeDosWindow) {
                             part[n] += s_w[e] * d;
-                            if (pv && e >= lo && e < lo + W) o.window[p * W + (e - lo)] = (float)d;
+                            if (pv && e >= lo && e < lo + W) o.window[p * W + (e - lo)] = df;
                         }
                     }
                 }
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
                 double v = 0.0;
                 for (int w = 0; w < kWaves; ++w) v += s_part[w][threadIdx.x];
                 const int64_t q = p0 + threadIdx.x;
-                if constexpr (MODE == kModeDensity) o.density[q] = v + s_c;
+                if constexpr (MODE == kModeDensity) o.density[q] = v;
                 else o.prefix[q] = v;
             }
         }
