@@ -468,6 +468,7 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
             constexpr bool FIRST = decltype(first)::value;
             const int mb2 = mb + D - mb1;
             const float c2 = cg[mb1 * W + mb];
+            const float c2p = (mb1 & 1) ? -c2 : c2;          // c2 (-1)^mb1 (wave-uniform)
             float u2r[J2 + 1], u2i[J2 + 1];
             static_for<0, J2 + 1>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
@@ -480,8 +481,19 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
                 if constexpr (zb_row1_used(J1, J2, J, ma1)) {
-                    const float2 v = uload<J1, ma1>(su, mb1, lane);
-                    const float wr = c2 * v.x, wi = c2 * v.y;
+                    // scaled u1 element; a mirrored row is (-1)^(ma1-mb1) conj of
+                    // the stored one, its sign folded into the scalar factor
+                    float wr, wi;
+                    if constexpr (2 * ma1 <= J1) {
+                        const float2 v = su[(half_off(J1) + ma1 * (J1 + 1) + mb1) * kTile + lane];
+                        wr = c2 * v.x;
+                        wi = c2 * v.y;
+                    } else {
+                        const float2 v = su[(half_off(J1) + (J1 - ma1) * (J1 + 1) + (J1 - mb1)) * kTile + lane];
+                        const float f = (ma1 & 1) ? -c2p : c2p;
+                        wr = f * v.x;
+                        wi = -f * v.y;
+                    }
                     static_for<0, HR + 1>([&](auto mc) {
                         constexpr int ma = decltype(mc)::value;
                         constexpr int ma2 = ma - ma1 + D;
