@@ -448,24 +448,44 @@ __host__ __device__ constexpr bool zb_row2_used(int J1, int J2, int J, int r) {
 // B(j1,j2,j) of the lane's point.  For each output column mb:
 //   T[ma][ma1] = sum_mb1 (C(mb1,mb) u1[ma1][mb1]) u2[ma-ma1+D][mb-mb1+D]
 // (the scaled u1 element is shared by every row ma), then
-//   Z[ma][mb] = sum_ma1 C(ma1,ma) T[ma][ma1],  B += w_ma Re(conj(u[ma][mb]) Z[ma][mb]).
-// Z has the symmetry of u, so rows ma < J/2 count twice (w = 2) and the
-// middle row of an even J once.  For J1 == J2 only the pairs of zb_pair_ok
-// are formed; the others equal their exchanged partner (zb_pair_doubled).
+//   Z[ma][mb] = sum_ma1 C(ma1,ma) T[ma][ma1],  B += w Re(conj(u[ma][mb]) Z[ma][mb]).
+// Z has the symmetry of u, so rows ma < J/2 count twice (w = 2); the middle
+// row of an even J is its own mirror image with columns mb and J-mb paired,
+// so it is formed for mb <= J/2 only (w = 2, 1 at mb = J/2): its pairs come
+// last in each column body behind one wave-uniform branch.  For J1 == J2
+// only the pairs of zb_pair_ok are formed; the others equal their exchanged
+// partner (zb_pair_doubled).
 template <int J1, int J2, int J>
 __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int lane,
                                            const float* __restrict__ cg) {
     constexpr int D = (J1 + J2 - J) / 2;   // ma2 = ma - ma1 + D
     constexpr int HR = J / 2;              // half rows 0..HR
+    constexpr bool MID = (J % 2 == 0);     // row HR is the middle row
+    constexpr int HN = MID ? HR - 1 : HR;  // last row formed for every column
     constexpr int W = J + 1;               // cg row stride: cg[ma1*W + ma]
     constexpr int NP = zb_pairs(J1, J2, J);
     float bsum = 0.f;
 #pragma clang loop unroll(disable)
     for (int mb = 0; mb <= J; ++mb) {
         float tr[NP], ti[NP];
+        const bool mid_on = mb <= HR;      // wave-uniform
+        auto pair_fma = [&](auto mac, auto ma1c, float wr, float wi, const float (&u2r)[J2 + 1],
+                            const float (&u2i)[J2 + 1], auto first) {
+            constexpr int ma = decltype(mac)::value, ma1 = decltype(ma1c)::value;
+            constexpr int ma2 = ma - ma1 + D;
+            constexpr int k = zb_pair_index(J1, J2, J, ma, ma1);
+            if constexpr (decltype(first)::value) {
+                tr[k] = fmaf(-wi, u2i[ma2], wr * u2r[ma2]);
+                ti[k] = fmaf(wi, u2r[ma2], wr * u2i[ma2]);
+            } else {
+                tr[k] = fmaf(wr, u2r[ma2], tr[k]);
+                tr[k] = fmaf(-wi, u2i[ma2], tr[k]);
+                ti[k] = fmaf(wr, u2i[ma2], ti[k]);
+                ti[k] = fmaf(wi, u2r[ma2], ti[k]);
+            }
+        };
         // one m1' column: the first one initialises T, the others accumulate
         auto column = [&](int mb1, auto first) {
-            constexpr bool FIRST = decltype(first)::value;
             const int mb2 = mb + D - mb1;
             const float c2 = cg[mb1 * W + mb];
             const float c2p = (mb1 & 1) ? -c2 : c2;          // c2 (-1)^mb1 (wave-uniform)
@@ -478,40 +498,37 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
                     u2i[r] = v.y;
                 }
             });
+            float wrs[J1 + 1], wis[J1 + 1];
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
                 if constexpr (zb_row1_used(J1, J2, J, ma1)) {
                     // scaled u1 element; a mirrored row is (-1)^(ma1-mb1) conj of
                     // the stored one, its sign folded into the scalar factor
-                    float wr, wi;
                     if constexpr (2 * ma1 <= J1) {
                         const float2 v = su[(half_off(J1) + ma1 * (J1 + 1) + mb1) * kTile + lane];
-                        wr = c2 * v.x;
-                        wi = c2 * v.y;
+                        wrs[ma1] = c2 * v.x;
+                        wis[ma1] = c2 * v.y;
                     } else {
                         const float2 v = su[(half_off(J1) + (J1 - ma1) * (J1 + 1) + (J1 - mb1)) * kTile + lane];
                         const float f = (ma1 & 1) ? -c2p : c2p;
-                        wr = f * v.x;
-                        wi = -f * v.y;
+                        wrs[ma1] = f * v.x;
+                        wis[ma1] = -f * v.y;
                     }
-                    static_for<0, HR + 1>([&](auto mc) {
-                        constexpr int ma = decltype(mc)::value;
-                        constexpr int ma2 = ma - ma1 + D;
-                        if constexpr (zb_pair_ok(J1, J2, J, ma, ma1)) {
-                            constexpr int k = zb_pair_index(J1, J2, J, ma, ma1);
-                            if constexpr (FIRST) {
-                                tr[k] = fmaf(-wi, u2i[ma2], wr * u2r[ma2]);
-                                ti[k] = fmaf(wi, u2r[ma2], wr * u2i[ma2]);
-                            } else {
-                                tr[k] = fmaf(wr, u2r[ma2], tr[k]);
-                                tr[k] = fmaf(-wi, u2i[ma2], tr[k]);
-                                ti[k] = fmaf(wr, u2i[ma2], ti[k]);
-                                ti[k] = fmaf(wi, u2r[ma2], ti[k]);
-                            }
-                        }
+                    static_for<0, HN + 1>([&](auto mc) {
+                        if constexpr (zb_pair_ok(J1, J2, J, decltype(mc)::value, ma1))
+                            pair_fma(mc, r1c, wrs[ma1], wis[ma1], u2r, u2i, first);
                     });
                 }
             });
+            if constexpr (MID) {
+                if (mid_on) {
+                    static_for<0, J1 + 1>([&](auto r1c) {
+                        constexpr int ma1 = decltype(r1c)::value;
+                        if constexpr (zb_pair_ok(J1, J2, J, HR, ma1))
+                            pair_fma(std::integral_constant<int, HR>{}, r1c, wrs[ma1], wis[ma1], u2r, u2i, first);
+                    });
+                }
+            }
         };
         const int lo = max(0, mb + D - J2), hi = min(J1, mb + D);   // never empty
         column(lo, std::true_type{});
@@ -521,6 +538,8 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
         for (int mb1 = lo + 1; mb1 <= hi; ++mb1) column(mb1, std::false_type{});
         static_for<0, HR + 1>([&](auto mc) {
             constexpr int ma = decltype(mc)::value;
+            constexpr bool MIDROW = MID && ma == HR;
+            if (MIDROW && !mid_on) return;
             float zr = 0.f, zi = 0.f, zr2 = 0.f, zi2 = 0.f;
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
@@ -540,7 +559,7 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
                 zr = fmaf(2.f, zr2, zr);
                 zi = fmaf(2.f, zi2, zi);
             }
-            constexpr float w = (2 * ma < J) ? 2.f : 1.f;
+            const float w = MIDROW ? (mb < HR ? 2.f : 1.f) : 2.f;
             const float2 uj = su[(half_off(J) + ma * (J + 1) + mb) * kTile + lane];
             bsum += w * (uj.x * zr + uj.y * zi);
         });

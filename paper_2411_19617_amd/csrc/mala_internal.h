@@ -82,17 +82,22 @@ __host__ __device__ constexpr bool zb_pair_doubled(int A, int B, int C, int ma, 
 
 // Operation count of the Z/B contraction with output index C and coupled
 // pair (A, B): per output column, every m1' column of u^A updates the pairs
-// of T (4 FMA) after its loads, then the row CG fold over the half rows.
+// of T (4 FMA) after its loads, then the row CG fold over the half rows; the
+// middle row of an even C is formed for the columns mb <= C/2 only.
 __host__ __device__ constexpr double zb_cost(int A, int B, int C) {
     const int D = (A + B - C) / 2, HR = C / 2;
-    int terms = 0;
+    int terms = 0, mid = 0;
     for (int ma = 0; ma <= HR; ++ma)
         for (int ma1 = 0; ma1 <= A; ++ma1)
-            if (zb_pair_ok(A, B, C, ma, ma1)) ++terms;
+            if (zb_pair_ok(A, B, C, ma, ma1)) {
+                if (C % 2 == 0 && ma == HR) ++mid;
+                else ++terms;
+            }
     double tot = 0.0;
     for (int mb = 0; mb <= C; ++mb) {
         const int lo = mb + D - B > 0 ? mb + D - B : 0, hi = A < mb + D ? A : mb + D;
-        tot += (hi - lo + 1) * (4.0 * terms + 2.0 * (A + 1) + (B + 1) + 2.0) + 2.0 * terms + 3.0 * (HR + 1);
+        const int t = terms + (mb <= HR ? mid : 0);
+        tot += (hi - lo + 1) * (4.0 * t + 2.0 * (A + 1) + (B + 1) + 2.0) + 2.0 * t + 3.0 * (HR + 1);
     }
     return tot;
 }
