@@ -25,8 +25,10 @@ import mala_synth  # noqa: E402
 
 METRIC = "grid points/s (bispectrum+MLP+LDOS reduce); p50/p99 snapshot latency"
 PEAK_FP32_VALU_TFLOPS = 157.3     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense matrix peaks
 WORKLOADS = {
     "paper_solid": (mala_synth.paper_solid, mala_synth.paper_net),
+    "paper_solid_200": (lambda: mala_synth.paper_solid(grid=200), mala_synth.paper_net),
     "paper_liquid": (mala_synth.paper_liquid, mala_synth.paper_net),
     "small": (mala_synth.small, mala_synth.small_net),
     "slab": (mala_synth.slab, mala_synth.paper_net),
@@ -258,16 +260,19 @@ def errors_vs_oracle(workload, snap, dos, r, dens):
     return {"dos_max_rel": float(np.max(np.abs(D - Dref)) / np.max(np.abs(Dref))),
             "e_fermi_ev": abs(r["e_fermi"] - g["e_fermi"]),
             "e_band_mev_per_atom": abs(r["e_band"] - g["e_band"]) * 1000.0 / snap.n_atoms,
+            "minus_ts_mev_per_atom": (abs(r["e_entropy"] - g["minus_ts"]) * 1000.0 / snap.n_atoms
+                                      if "minus_ts" in g else None),
             "density_integral_rel": abs(float(dens.sum().item()) * snap.dV - g["density_sum_dV"]) / g["density_sum_dV"],
             "oracle": "tests/golden/full_%s.json (FP64 oracle, all %d points)" % (workload, g["n_points"])}
 
 
-def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5):
-    """Poisson stream of the serving mix through the library's request loop.
+def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5, loads=(0.5, 0.7, 0.9)):
+    """Poisson streams of the serving mix through the library's request loop.
 
     The saturation request rate of the mix is measured first (all requests
-    submitted at once); the stream then arrives at 0.7 x that rate.
-    Latency = completion - arrival (server clock).
+    submitted at once); streams then arrive at 0.5, 0.7 and 0.9 x that rate.
+    Latency = completion - arrival (server clock).  The top-level latency
+    fields are those of the 0.7 x stream.
     """
     rng = mala_synth.SplitMix64(seed)
     reqs = [mala_synth.serving_request(rng) for _ in range(n_requests)]
@@ -283,26 +288,34 @@ def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5):
     outs = [sv.wait(t, 600) for t in [submit(r) for r in reqs]]
     sat = time.perf_counter() - t0
     sat_rate = n_requests / sat
-    lam = 0.7 * sat_rate
-    gaps = -np.log(1.0 - rng.uniform(n_requests)) / lam
-    arrivals = np.cumsum(gaps)
-    tickets = []
-    t0 = time.perf_counter()
-    for r, ta in zip(reqs, arrivals):
-        while time.perf_counter() - t0 < ta:
-            time.sleep(0.0002)
-        tickets.append(submit(r))
-    outs = [sv.wait(t, 600) for t in tickets]
-    span = time.perf_counter() - t0
-    sv.close()
-    lat = np.array([o["t_done"] - o["t_submit"] for o in outs]) * 1000.0
     pts = sum(r.n_points for r in reqs)
-    bad = sum(1 for o in outs if o["status"] != 0)
+    streams = []
+    for load in loads:
+        lam = load * sat_rate
+        gaps = -np.log(1.0 - rng.uniform(n_requests)) / lam
+        arrivals = np.cumsum(gaps)
+        tickets = []
+        t0 = time.perf_counter()
+        for r, ta in zip(reqs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(0.0002)
+            tickets.append(submit(r))
+        outs = [sv.wait(t, 600) for t in tickets]
+        span = time.perf_counter() - t0
+        lat = np.array([o["t_done"] - o["t_submit"] for o in outs]) * 1000.0
+        streams.append({"load": load, "arrival_rate_req_per_s": lam,
+                        "p50_latency_ms": float(np.percentile(lat, 50)),
+                        "p99_latency_ms": float(np.percentile(lat, 99)),
+                        "stream_points_per_s": pts / span,
+                        "failed": sum(1 for o in outs if o["status"] != 0)})
+    sv.close()
+    main_stream = min(streams, key=lambda st: abs(st["load"] - 0.7))
     return {"requests": n_requests, "slots": slots, "hbm_budget_gb": budget_gb,
             "points_total": pts, "saturation_req_per_s": sat_rate,
-            "saturation_points_per_s": pts / sat, "arrival_rate_req_per_s": lam,
-            "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
-            "stream_points_per_s": pts / span, "failed": bad,
+            "saturation_points_per_s": pts / sat, "arrival_rate_req_per_s": main_stream["arrival_rate_req_per_s"],
+            "p50_latency_ms": main_stream["p50_latency_ms"], "p99_latency_ms": main_stream["p99_latency_ms"],
+            "stream_points_per_s": main_stream["stream_points_per_s"],
+            "failed": sum(st["failed"] for st in streams), "streams": streams,
             "mix": "fcc n^3*4 (n=2..8) or liquid N~U[32,2048], 298-933 K, ~2800 points/atom, seed %d" % seed}
 
 
@@ -389,6 +402,12 @@ def main():
     achieved = zb_flops_per_launch / (zb_avg_ms * 1e-3) / 1e12
     stages = {k: {"ms_per_step": v[0] / a.steps, "launches_per_step": v[1] / a.steps}
               for k, v in prof.items() if v[1]}
+    # per-stage algorithmic rate against the peak of the unit that bounds it
+    for k, fk, peak in (("ui", "u", PEAK_FP32_VALU_TFLOPS), ("zb", "zb", PEAK_FP32_VALU_TFLOPS),
+                        ("mlp_dos", "mlp", PEAK_MFMA_TFLOPS[a.precision])):
+        if k in stages and prof[k][0] > 0:
+            tf = fl[fk] * prof[k][2] / (prof[k][0] * 1e-3) / 1e12
+            stages[k].update({"tflops": tf, "peak_tflops": peak, "frac": tf / peak})
     out = {
         "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1000.0 * elapsed / a.steps, "higher_is_better": True,
@@ -409,7 +428,8 @@ def main():
         "stages": stages,
         "algorithmic_kflop_per_point": {"u": fl["u"] / 1e3, "zb": fl["zb"] / 1e3, "mlp": fl["mlp"] / 1e3,
                                         "mean_neighbours": fl["mean_neighbours"]},
-        "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms},
+        "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms,
+                   "minus_ts_mev_per_atom": 1000 * r["e_entropy"] / snap.n_atoms, "entropy_kb": r["entropy"]},
         "errors_vs_oracle": errors_vs_oracle(a.workload, snap, dos, mala.read_result(res), dens),
     }
     if a.serve_requests > 0:

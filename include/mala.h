@@ -122,6 +122,10 @@ typedef struct {
     int32_t density_from_window; /* mala_predict: 1 if the density came from
                                     the stored energy window, 0 otherwise */
     int32_t reserved;
+    double entropy;       /* S_s / k_B (Eq. electronicentropyDOS):
+                             int -[f ln f + (1-f) ln(1-f)] D de       */
+    double e_entropy;     /* -tau S_s in eV, the entropy term of the
+                             free energy (Eq. KSfreeenergy)           */
 } mala_result;
 
 /* ---------------------------------------------------------------- compute */
@@ -141,19 +145,20 @@ mala_status mala_descriptors(mala_ctx* ctx, const double* positions, int32_t n_a
 mala_status mala_ldos_infer(mala_ctx* ctx, const mala_weights* w, const float* B,
                             int64_t n_pts, float* ldos_out);
 
-/* Observables from a stored LDOS (Sec. 3.4).
+/* Observables from a stored LDOS (Sec. 3.4): DOS, Fermi level, band
+ * energy, electronic entropy (Eq. electronicentropyDOS) and density.
  *  ldos: device float32 [n_pts][eg->n]; dV = cell volume / N_points;
  *  T_kelvin > 0; n_electrons > 0.
  *  dos_out: device float64 [eg->n]; density_out: device float64 [n_pts] or
  *  NULL; result: device mala_result.  If N_e has no root, result->status is
- *  MALA_E_NO_ROOT, E_F/E_b are NaN and the density is not written.          */
+ *  MALA_E_NO_ROOT, E_F/E_b/entropy are NaN and the density is not written. */
 mala_status mala_integrate(mala_ctx* ctx, const float* ldos, int64_t n_pts, double dV,
                            const mala_egrid* eg, double T_kelvin, double n_electrons,
                            double* dos_out, double* density_out, mala_result* result);
 
 /* Whole path, fused: descriptors of every grid point (cached as B in
  * device memory), network with the DOS reduced in the epilogue (the full
- * LDOS is never stored), Fermi level, band energy and density.
+ * LDOS is never stored), Fermi level, band energy, entropy and density.
  * The density needs E_F, which needs every point.  In the default mode a
  * network pass over every 61st point first estimates E_F; the main pass then
  * keeps per point only the FP64 sum of the fully occupied part below the

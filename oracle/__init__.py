@@ -63,6 +63,9 @@ def lib():
         L.oracle_li_neg.restype = d
         L.oracle_li_neg.argtypes = [i, d]
         L.oracle_fermi_weights.argtypes = [d, d, i, d, d, p, p]
+        L.oracle_entropy_weights.argtypes = [d, d, i, d, d, p]
+        L.oracle_entropy.restype = d
+        L.oracle_entropy.argtypes = [p, d, d, i, d, d, p]
         L.oracle_fermi.restype = i
         L.oracle_fermi.argtypes = [p, d, d, i, d, d, d, p, p]
         L.oracle_density.argtypes = [p, i64, i, p, p]
@@ -210,6 +213,23 @@ def fermi_weights(egrid, mu, T):
     return w, v
 
 
+def entropy_weights(egrid, mu, T):
+    """u with S_s / k_B = u.D for piecewise-linear D (Eq. electronicentropyDOS)."""
+    e0, de, n = egrid
+    u = np.zeros(n)
+    lib().oracle_entropy_weights(float(e0), float(de), int(n), float(mu), KB_EV * float(T), _ptr(u))
+    return u
+
+
+def entropy(dos_, egrid, mu, T):
+    """(S_s / k_B, -tau S_s in eV) at Fermi level mu (Eqs. electronicentropyDOS, KSfreeenergy)."""
+    e0, de, n = egrid
+    d = _f64(dos_)
+    mts = ctypes.c_double()
+    s = lib().oracle_entropy(_ptr(d), float(e0), float(de), int(n), float(T), float(mu), ctypes.byref(mts))
+    return s, mts.value
+
+
 class NoRoot(Exception):
     pass
 
@@ -238,11 +258,12 @@ def density(ldos, w):
 
 def predict(snap, net, egrid, points=None, nthreads=0):
     """Whole path on the listed points (all points by default): B, LDOS, DOS, E_F,
-    E_band and density.  DOS/E_F/E_band are only meaningful over all points."""
+    E_band, the entropy term and density.  DOS/E_F/E_band are only meaningful over all points."""
     B = descriptors(snap, points, nthreads)
     ld = mlp(B, net, nthreads)
     D = dos(ld, snap.dV)
     fr = fermi(D, egrid, snap.T, snap.n_electrons)
+    s_kb, mts = entropy(D, egrid, fr["e_fermi"], snap.T)
     return {"B": B, "ldos": ld, "dos": D, "e_fermi": fr["e_fermi"], "e_band": fr["e_band"],
             "n_found": fr["n_found"], "iters": fr["iters"], "weights": fr["weights"],
-            "density": density(ld, fr["weights"])}
+            "entropy": s_kb, "minus_ts": mts, "density": density(ld, fr["weights"])}

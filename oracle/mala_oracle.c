@@ -464,6 +464,68 @@ void oracle_fermi_weights(double e0, double de, int n, double mu, double kT,
     }
 }
 
+/* Electronic entropy (Eq. electronicentropyDOS): with x = beta (e - mu) and
+ * f = 1/(1+e^x), the integrand -[f ln f + (1-f) ln(1-f)] equals
+ * s(x) = ln(1+e^x) - x (1 - f), whose antiderivatives are
+ *   S0(x) = int s dx   = -2 Li2(-e^x) - x ln(1+e^x),
+ *   S1(x) = int x s dx = -x^2 ln(1+e^x) - 3x Li2(-e^x) + 3 Li3(-e^x)
+ * (differentiate with d/dx Li_s(-e^x) = Li_{s-1}(-e^x)); for x > 0 they are
+ * rewritten with the inversion formulas for Li2, Li3 so only Li_s(-e^-x) is
+ * needed.  There S0 = pi^2/3 + 2 Li2(-e^-x) - x ln(1+e^-x): the constant is
+ * left out here and added by the caller to the one interval that crosses
+ * x = 0, so that differences far in the tail are not lost to rounding.     */
+static void s01(double x, double *s0, double *s1)
+{
+    if (x <= 0.0) {
+        double y = exp(x), Lg = log1p(y);
+        double l2 = oracle_li_neg(2, y), l3 = oracle_li_neg(3, y);
+        *s0 = -2.0 * l2 - x * Lg;
+        *s1 = -x * x * Lg - 3.0 * x * l2 + 3.0 * l3;
+    } else {
+        double y = exp(-x), Lg = log1p(y);
+        double l2 = oracle_li_neg(2, y), l3 = oracle_li_neg(3, y);
+        *s0 = 2.0 * l2 - x * Lg;
+        *s1 = -x * x * Lg + 3.0 * x * l2 + 3.0 * l3;
+    }
+}
+
+/* Entropy weights of a piecewise-linear DOS on the uniform grid:
+ *   S_s / k_B = int s(beta (e - mu)) D(e) de = sum_i u_i D_i,
+ * exact for D linear between grid points and zero outside.  kT in eV.     */
+void oracle_entropy_weights(double e0, double de, int n, double mu, double kT, double *u)
+{
+    double beta = 1.0 / kT;
+    for (int i = 0; i < n; i++) u[i] = 0.0;
+    for (int i = 0; i + 1 < n; i++) {
+        double xa = beta * (e0 + i * de - mu), xb = beta * (e0 + (i + 1) * de - mu);
+        double a0, a1, b0, b1;
+        s01(xa, &a0, &a1);
+        s01(xb, &b0, &b1);
+        double d0 = b0 - a0;
+        if (xa <= 0.0 && xb > 0.0) d0 += OR_PI * OR_PI / 3.0;   /* S0's jump of constant */
+        double D = xb - xa;
+        double J0 = d0 / beta;                                 /* int s de       */
+        double J1 = ((b1 - a1) - xa * d0) / (beta * D);        /* int s t de     */
+        u[i] += J0 - J1;
+        u[i + 1] += J1;
+    }
+}
+
+/* S_s / k_B at Fermi level mu for the DOS on the grid, and the free-energy
+ * term -tau S_s = -k_B T (S_s / k_B) in eV (Eq. KSfreeenergy).             */
+double oracle_entropy(const double *dos, double e0, double de, int n, double T_K, double mu,
+                      double *minus_ts)
+{
+    double kT = OR_KB_EV * T_K;
+    double *u = malloc(sizeof(double) * n);
+    oracle_entropy_weights(e0, de, n, mu, kT, u);
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += u[i] * dos[i];
+    free(u);
+    if (minus_ts) *minus_ts = -kT * s;
+    return s;
+}
+
 static double count_electrons(const double *dos, double e0, double de, int n, double mu,
                               double kT, double *w, double *v)
 {

@@ -24,7 +24,7 @@ MALA_E_BUSY = -6
 MALA_E_CAPACITY = -7
 PREC_FP32 = 0
 PREC_BF16 = 1
-RESULT_BYTES = 48
+RESULT_BYTES = 64
 STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
           "density_window"]
 DENSITY_WINDOW = 0
@@ -57,7 +57,8 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("e_fermi", ctypes.c_double), ("e_band", ctypes.c_double), ("n_found", ctypes.c_double),
                 ("n_target", ctypes.c_double), ("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("density_from_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("density_from_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("entropy", ctypes.c_double), ("e_entropy", ctypes.c_double)]
 
 
 def lib():
@@ -142,13 +143,14 @@ def _positions(pos):
 
 
 def read_result(res):
-    """Decode a device mala_result (uint8 tensor of 48 bytes); synchronises."""
+    """Decode a device mala_result (uint8 tensor of 64 bytes); synchronises."""
     raw = res.cpu().numpy().tobytes()
     d = np.frombuffer(raw[:32], dtype="<f8")
     i = np.frombuffer(raw[32:44], dtype="<i4")
+    s = np.frombuffer(raw[48:64], dtype="<f8")
     return {"e_fermi": float(d[0]), "e_band": float(d[1]), "n_found": float(d[2]),
             "n_target": float(d[3]), "iterations": int(i[0]), "status": int(i[1]),
-            "density_from_window": int(i[2])}
+            "density_from_window": int(i[2]), "entropy": float(s[0]), "e_entropy": float(s[1])}
 
 
 class Weights:
@@ -328,6 +330,7 @@ class Server:
         if st != MALA_OK:
             raise MalaError(st, lib().mala_server_last_error().decode())
         return {"e_fermi": r.e_fermi, "e_band": r.e_band, "n_found": r.n_found, "iterations": r.iterations,
+                "entropy": r.entropy, "e_entropy": r.e_entropy,
                 "status": r.status, "density_from_window": r.density_from_window, "dos": dos, "density": dens,
                 "t_submit": times[0], "t_start": times[1], "t_done": times[2]}
 

@@ -9,10 +9,18 @@
 #include <string>
 #include <vector>
 
+#include <stddef.h>
+
 #include "mala.h"
 #include "mala_internal.h"
 
 using namespace mala;
+
+// the kernels write mala_result through their own record type
+static_assert(sizeof(mala_result) == sizeof(ResultRec), "result record layout");
+static_assert(offsetof(mala_result, status) == offsetof(ResultRec, status), "result record layout");
+static_assert(offsetof(mala_result, entropy) == offsetof(ResultRec, entropy), "result record layout");
+static_assert(offsetof(mala_result, e_entropy) == offsetof(ResultRec, e_entropy), "result record layout");
 
 namespace {
 

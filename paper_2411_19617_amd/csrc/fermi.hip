@@ -1,8 +1,9 @@
 // Energy-space observables in FP64 (Sec. 3.4): the DOS from its partial
 // sums (Eq. DOS.from.ldos), the Fermi level as the root of
 // N_e = int f D (Eq. NumberElectrons_from_DOS), the band energy
-// (Eq. band.energy) and the Fermi weights that turn an LDOS into the density
-// (Eq. density.from.ldos).
+// (Eq. band.energy), the electronic entropy and its free-energy term
+// (Eqs. electronicentropyDOS, KSfreeenergy) and the Fermi weights that turn
+// an LDOS into the density (Eq. density.from.ldos).
 //
 // D is taken piecewise linear between the energy grid points, and the
 // integrals of f, f*e against each linear piece are exact: with
@@ -47,24 +48,40 @@ __device__ double li_neg(int s, double y, const double* __restrict__ coef) {
     return acc;
 }
 
-// G0, G1 (and G2 if asked) at x (see the file comment), and f(x) = 1/(1+e^x).
-__device__ void gfun(double x, const double* coef, bool need_g2, double& g0, double& g1, double& g2,
-                     double& f) {
+// G0, G1 (and, for the final pass, G2 and the entropy antiderivatives S0,
+// S1) at x (see the file comment), and f(x) = 1/(1+e^x).  The entropy
+// kernel -[f ln f + (1-f) ln(1-f)] = ln(1+e^x) - x (1-f) has
+//   S0 = -2 Li2(-e^x) - x ln(1+e^x),  S1 = -x^2 ln(1+e^x) - 3x Li2(-e^x) + 3 Li3(-e^x);
+// for x > 0 they are written through Li_s(-e^-x), with S0's constant pi^2/3
+// left to the one interval that crosses x = 0.
+__device__ void gfun(double x, const double* coef, bool final, double& g0, double& g1, double& g2, double& f,
+                     double& s0, double& s1) {
     if (x <= 0.0) {
         const double y = exp(x), lg = log1p(y);
         const double l2 = li_neg(2, y, coef);
         g0 = x - lg;
         g1 = 0.5 * x * x - x * lg - l2;
-        g2 = need_g2 ? x * x * x / 3.0 - x * x * lg - 2.0 * x * l2 + 2.0 * li_neg(3, y, coef) : 0.0;
         f = 1.0 / (1.0 + y);
+        if (final) {
+            const double l3 = li_neg(3, y, coef);
+            g2 = x * x * x / 3.0 - x * x * lg - 2.0 * x * l2 + 2.0 * l3;
+            s0 = -2.0 * l2 - x * lg;
+            s1 = -x * x * lg - 3.0 * x * l2 + 3.0 * l3;
+        }
     } else {
         const double y = exp(-x), lg = log1p(y);
         const double l2 = li_neg(2, y, coef);
         g0 = -lg;
         g1 = kPi * kPi / 6.0 - x * lg + l2;
-        g2 = need_g2 ? -x * x * lg + 2.0 * x * l2 + 2.0 * li_neg(3, y, coef) : 0.0;
         f = y / (1.0 + y);
+        if (final) {
+            const double l3 = li_neg(3, y, coef);
+            g2 = -x * x * lg + 2.0 * x * l2 + 2.0 * l3;
+            s0 = 2.0 * l2 - x * lg;
+            s1 = -x * x * lg + 3.0 * x * l2 + 3.0 * l3;
+        }
     }
+    if (!final) g2 = s0 = s1 = 0.0;
 }
 
 // Fixed-shape sum over the 256 threads: butterfly inside each wave, then the
@@ -79,22 +96,24 @@ __device__ double block_sum(double v, double* red) {
 }
 
 struct FermiShared {
-    double D[256], red[256], g0[256], g1[256], g2[256], f[256], cum[256];
+    double D[256], red[256], g0[256], g1[256], g2[256], f[256], cum[256], s0[256], s1[256];
     double mu0;
     int first;
 };
 
 // Antiderivatives and f at every grid point for Fermi level mu (one per thread).
 __device__ void grid_g(FermiShared& sh, int n_e, double e0, double de, double mu, double kT, const double* coef,
-                       bool need_g2) {
+                       bool final) {
     const int e = threadIdx.x;
     if (e < n_e) {
-        double g0, g1, g2, f;
-        gfun((e0 + e * de - mu) / kT, coef, need_g2, g0, g1, g2, f);
+        double g0, g1, g2, f, s0, s1;
+        gfun((e0 + e * de - mu) / kT, coef, final, g0, g1, g2, f, s0, s1);
         sh.g0[e] = g0;
         sh.g1[e] = g1;
         sh.g2[e] = g2;
         sh.f[e] = f;
+        sh.s0[e] = s0;
+        sh.s1[e] = s1;
     }
     __syncthreads();
 }
@@ -203,6 +222,8 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
                 res->e_fermi = NAN;
                 res->e_band = NAN;
                 res->n_found = NAN;
+                res->entropy = NAN;
+                res->e_entropy = NAN;
                 res->n_target = n_target;
                 res->iterations = 0;
                 res->status = -4;
@@ -258,8 +279,18 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
         return;
     }
     grid_g(sh, n_e, e0, de, ef, kT, coef, true);
-    double wl = 0, wr = 0, vl = 0, vr = 0;
-    if (e < n_e - 1) interval(sh, e, e0, de, ef, kT, wl, wr, vl, vr);
+    double wl = 0, wr = 0, vl = 0, vr = 0, sc = 0;
+    if (e < n_e - 1) {
+        interval(sh, e, e0, de, ef, kT, wl, wr, vl, vr);
+        // entropy (Eq. electronicentropyDOS) on the same hat pieces: int s,
+        // int s t over the interval, t = (x - xa)/D
+        const double xa = (e0 + e * de - ef) / kT, xb = (e0 + (e + 1) * de - ef) / kT, D = de / kT;
+        double d0 = sh.s0[e + 1] - sh.s0[e];
+        if (xa <= 0.0 && xb > 0.0) d0 += kPi * kPi / 3.0;
+        const double J0 = d0 * kT, J1 = (sh.s1[e + 1] - sh.s1[e] - xa * d0) * kT / D;
+        sc = (J0 - J1) * sh.D[e] + J1 * sh.D[e + 1];
+    }
+    const double s_kb = block_sum(sc, sh.red);
     __syncthreads();
     // reuse the g arrays for the per-interval pieces
     sh.g0[e] = wr;
@@ -277,6 +308,8 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
         res->e_fermi = ef;
         res->e_band = eb;
         res->n_found = nf;
+        res->entropy = s_kb;
+        res->e_entropy = -kT * s_kb;
         res->n_target = n_target;
         res->iterations = it;
         res->status = 0;

@@ -178,6 +178,7 @@ constexpr size_t kMlpLdsBudget = 155000;   // dynamic LDS of one network block
 struct ResultRec {
     double e_fermi, e_band, n_found, n_target;
     int32_t iterations, status, density_from_window, reserved;
+    double entropy, e_entropy;        // S_s / k_B, -tau S_s (eV)
 };
 
 // Energy window of the stored LDOS (device scratch).

@@ -8,8 +8,11 @@
 // every weight operand fetched from L2 feeds NT MFMAs; the tiles left over
 // after the full rounds are split as (M-tile, point-tile) items so the waves
 // stay balanced.  Weights stream through a small register ring (prefetch).
-// Activations live in LDS as [point][unit] rows with a stride of 4 (mod 64)
-// dwords (conflict-free B-operand reads and result writes).  Layer 2 is
+// Activations live in LDS as [point][unit] rows with a stride of 8 (mod 64)
+// dwords: on gfx950 that makes the 128-bit B-operand reads (row = point,
+// column = 4 units per lane group) and the result writes conflict-free,
+// where a stride of 4, 12, 16 or 36 (mod 64) costs 4 extra cycles per read
+// (measured with the SQ_LDS_BANK_CONFLICT counter).  Layer 2 is
 // produced eight M-tiles at a time and consumed by layer 3 at once.
 //
 // Epilogues:
@@ -55,7 +58,7 @@ struct Prec<0> {
     static constexpr int DA = 2;     // weight batches fetched ahead
     struct BatchA { float v[4]; };
     struct BatchB { float4 v; };
-    __host__ __device__ static int stride(int w) { return ((w + 63) / 64) * 64 + 4; }
+    __host__ __device__ static int stride(int w) { return ((w + 63) / 64) * 64 + 8; }
     __device__ static void loadA(BatchA& a, const void* A, size_t base, int q) {
         const float* p = static_cast<const float*>(A) + base + (size_t)q * PF * 64;
 #pragma unroll
@@ -86,7 +89,7 @@ struct Prec<1> {
     static constexpr int DA = 5;
     struct BatchA { uint4 v; };
     struct BatchB { uint4 v; };
-    __host__ __device__ static int stride(int w) { return ((w + 127) / 128) * 128 + 8; }
+    __host__ __device__ static int stride(int w) { return ((w + 127) / 128) * 128 + 16; }
     __device__ static void loadA(BatchA& a, const void* A, size_t base, int q) {
         a.v = static_cast<const uint4*>(A)[base + (size_t)q * 64];
     }

@@ -8,6 +8,10 @@ the tests directly, because the oracle finishes those in seconds.
 
 Usage (from the repository root):
     python -m tests.golden.make_golden paper_solid paper_liquid small [--threads N]
+    python -m tests.golden.make_golden --derived paper_solid paper_liquid small
+
+--derived recomputes only the quantities that follow from the stored oracle
+DOS and Fermi level (the electronic entropy), without the descriptor pass.
 """
 import argparse
 import hashlib
@@ -50,12 +54,14 @@ def run(case, threads):
     D = oracle.dos(ld, snap.dV)
     fr = oracle.fermi(D, mala_synth.EGRID, snap.T, snap.n_electrons)
     dens = oracle.density(ld, fr["weights"])
+    s_kb, minus_ts = oracle.entropy(D, mala_synth.EGRID, fr["e_fermi"], snap.T)
     out = {
         "case": case, "snapshot": snap.name, "fingerprint": fingerprint(snap, net),
         "n_points": snap.n_points, "n_atoms": snap.n_atoms, "dV": snap.dV,
         "T": snap.T, "n_electrons": snap.n_electrons, "egrid": list(mala_synth.EGRID),
         "dos": [float(x) for x in D], "e_fermi": fr["e_fermi"], "e_band": fr["e_band"],
         "n_found": fr["n_found"], "iters": fr["iters"],
+        "entropy_kb": s_kb, "minus_ts": minus_ts,
         "density_sum_dV": float(dens.sum() * snap.dV),
         "density_min": float(dens.min()), "density_max": float(dens.max()),
         "oracle_seconds": time.time() - t0, "descriptor_seconds": t1 - t0, "threads": threads,
@@ -66,13 +72,28 @@ def run(case, threads):
     print(case, "E_F", fr["e_fermi"], "E_b", fr["e_band"], "%.0fs" % (time.time() - t0), flush=True)
 
 
+def derived(case):
+    """Entropy from the stored oracle DOS and Fermi level (Eq. electronicentropyDOS)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_%s.json" % case)
+    g = json.load(open(path))
+    s_kb, minus_ts = oracle.entropy(np.array(g["dos"]), tuple(g["egrid"]), g["e_fermi"], g["T"])
+    g["entropy_kb"], g["minus_ts"] = s_kb, minus_ts
+    with open(path, "w") as f:
+        json.dump(g, f, indent=1)
+    print(case, "S/k_B", s_kb, "-TS", minus_ts, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cases", nargs="+", choices=sorted(CASES))
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--derived", action="store_true")
     a = ap.parse_args()
     for c in a.cases:
-        run(c, a.threads)
+        if a.derived:
+            derived(c)
+        else:
+            run(c, a.threads)
 
 
 if __name__ == "__main__":

@@ -61,3 +61,11 @@ def test_null_arguments_are_rejected_without_a_device(lib):
 def test_version_string(lib):
     lib.mala_version.restype = ctypes.c_char_p
     assert lib.mala_version().startswith(b"mala-gfx950")
+
+
+def test_result_record_layout():
+    # mala_result as the Python binding decodes it: 4 doubles, 4 int32, 2 doubles
+    import paper_2411_19617_amd as mala
+    assert mala.RESULT_BYTES == 64
+    assert ctypes.sizeof(mala.Result) == 64
+    assert mala.Result.entropy.offset == 48 and mala.Result.e_entropy.offset == 56

@@ -192,6 +192,10 @@ def test_integrate_matches_oracle_on_identical_ldos(ctx, torch):
         assert abs(r["e_band"] - ref["e_band"]) <= 1e-9 * abs(ref["e_band"])
         assert abs(r["n_found"] - ne) <= 1e-9 * ne
         assert np.max(np.abs(dens.cpu().numpy() - dens_ref)) <= 1e-12 * np.max(dens_ref)
+        # entropy (Eq. electronicentropyDOS) of the same DOS at the oracle's E_F
+        s_ref, mts_ref = oracle.entropy(D, EG, ref["e_fermi"], T)
+        assert abs(r["entropy"] - s_ref) <= 1e-9 * s_ref
+        assert abs(r["e_entropy"] - mts_ref) <= 1e-9 * abs(mts_ref)
 
 
 def test_integrate_no_root(ctx, mala, torch):
@@ -199,6 +203,7 @@ def test_integrate_no_root(ctx, mala, torch):
     dos, dens, res = ctx.mala_integrate(ld, 0.1, EG, 298.0, 1e9)
     r = mala.read_result(res)
     assert r["status"] == mala.MALA_E_NO_ROOT and np.isnan(r["e_fermi"])
+    assert np.isnan(r["entropy"]) and np.isnan(r["e_entropy"])
 
 
 def test_invalid_arguments(ctx, mala, torch):
@@ -236,11 +241,13 @@ def _check_full(ctx, mala, torch, snap, net, gold, prec, tol_eb_mev, tol_dos, to
     err_dos = np.max(np.abs(D - Dref)) / np.max(np.abs(Dref))
     err_ef = abs(r["e_fermi"] - gold["e_fermi"])
     err_eb = abs(r["e_band"] - gold["e_band"]) / snap.n_atoms * 1000.0
+    err_ts = abs(r["e_entropy"] - gold["minus_ts"]) / snap.n_atoms * 1000.0
     n = dens.cpu().numpy()
-    log(snap.name, "prec", prec, "dos", err_dos, "E_F", err_ef, "E_b meV/atom", err_eb, "iters",
-        r["iterations"])
+    log(snap.name, "prec", prec, "dos", err_dos, "E_F", err_ef, "E_b meV/atom", err_eb, "-TS meV/atom", err_ts,
+        "iters", r["iterations"])
     assert r["status"] == 0
-    assert err_dos <= tol_dos and err_ef <= tol_ef and err_eb <= tol_eb_mev
+    assert err_dos <= tol_dos and err_ef <= tol_ef and err_eb <= tol_eb_mev and err_ts <= tol_eb_mev
+    assert abs(r["e_entropy"] + 8.617333262e-5 * snap.T * r["entropy"]) <= 1e-12 * abs(r["e_entropy"])
     assert abs(n.sum() * snap.dV - r["n_found"]) <= 1e-9 * r["n_found"]
     assert abs(r["n_found"] - snap.n_electrons) <= 1e-10 * snap.n_electrons
     return n, r

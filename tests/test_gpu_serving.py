@@ -55,6 +55,7 @@ def test_alone_equals_in_mix(mala):
     assert alone["status"] == 0 and m["status"] == 0
     assert np.array_equal(alone["dos"], m["dos"])
     assert alone["e_fermi"] == m["e_fermi"] and alone["e_band"] == m["e_band"]
+    assert alone["entropy"] == m["entropy"]
     assert np.array_equal(alone["density"], m["density"])
     # requests overlapped: some started before an earlier one finished
     overlaps = sum(1 for a, b in zip(mixed, mixed[1:]) if b["t_start"] < a["t_done"])

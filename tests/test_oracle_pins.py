@@ -458,3 +458,58 @@ def test_density_integrates_to_electron_count():
     r = oracle.fermi(D, eg, 298.0, ne)
     n = oracle.density(ld, r["weights"])
     assert abs(n.sum() * dV - ne) < 1e-9 * ne
+
+
+# ---------------------------------------------------------------- entropy
+# Eq. electronicentropyDOS: S_s / k_B = int -[f ln f + (1-f) ln(1-f)] D de.
+
+def _entropy_integrand(E, mu, kT):
+    x = (E - mu) / kT
+    if abs(x) > 700:
+        return 0.0
+    f = 1.0 / (1.0 + np.exp(x))
+    r = 0.0
+    if f > 0.0:
+        r -= f * np.log(f)
+    if f < 1.0:
+        r -= (1.0 - f) * np.log1p(-f)
+    return r
+
+
+@pytest.mark.parametrize("T,mu", [(298.0, 0.93), (933.0, 1.234), (3000.0, 2.0), (298.0, -1.97)])
+def test_entropy_weights_match_quadrature(T, mu):
+    # the paper's integrand integrated numerically against a random piecewise-linear D
+    from scipy.integrate import quad
+    kT = oracle.KB_EV * T
+    rng = np.random.default_rng(7)
+    eg = (-2.0, 0.1, 60)
+    e = eg[0] + eg[1] * np.arange(eg[2])
+    D = rng.uniform(0.0, 2.0, eg[2])
+    q = 0.0
+    for i in range(eg[2] - 1):
+        a, b = e[i], e[i + 1]
+        lin = lambda E, i=i, a=a: D[i] + (D[i + 1] - D[i]) * (E - a) / eg[1]
+        q += quad(lambda E: _entropy_integrand(E, mu, kT) * lin(E), a, b, epsabs=1e-14, epsrel=1e-13,
+                  limit=200, points=[mu] if a < mu < b else None)[0]
+    S, mts = oracle.entropy(D, eg, mu, T)
+    assert abs(S - q) <= 1e-12 * abs(q)
+    assert abs(mts + kT * S) <= 1e-15 * abs(mts)
+
+
+def test_entropy_closed_forms():
+    # int s(x) dx = pi^2/3 and s is even: a constant D gives D kT pi^2/3 and a
+    # linear D gives kT pi^2/3 D(mu) (the odd part integrates to zero), when the
+    # grid reaches far past mu on both sides; at T -> 0 the entropy vanishes.
+    eg = (-10.0, 0.05, 401)
+    e = eg[0] + eg[1] * np.arange(eg[2])
+    mu, T = 0.0123, 933.0
+    kT = oracle.KB_EV * T
+    S, _ = oracle.entropy(np.full(eg[2], 2.5), eg, mu, T)
+    assert abs(S - 2.5 * kT * np.pi ** 2 / 3.0) <= 1e-13 * S
+    D = 1.7 + 0.3 * (e - mu)
+    S, _ = oracle.entropy(D, eg, mu, T)
+    assert abs(S - 1.7 * kT * np.pi ** 2 / 3.0) <= 1e-12 * S
+    S, _ = oracle.entropy(np.full(eg[2], 2.5), eg, mu, 1e-3)
+    assert 0.0 <= S <= 2.5 * oracle.KB_EV * 1e-3 * np.pi ** 2 / 3.0 * (1 + 1e-9)
+    u = oracle.entropy_weights(eg, mu, T)
+    assert np.all(u >= 0.0)
