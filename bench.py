@@ -266,6 +266,25 @@ def errors_vs_oracle(workload, snap, dos, r, dens):
             "oracle": "tests/golden/full_%s.json (FP64 oracle, all %d points)" % (workload, g["n_points"])}
 
 
+def gaussian_bench(ctx, snap, torch, reps=5):
+    """Gaussian descriptors of the whole grid (sigma = grid spacing, cutoff 8
+    sigma), outside the metric's step: time per grid and the write rate (the
+    kernel writes 4 B per point; its neighbour sums are short)."""
+    sigma = float(np.max(snap.L / snap.N))
+    G = torch.empty(snap.n_points, dtype=torch.float32, device="cuda")
+    ctx.mala_gaussian_descriptors(snap.positions, snap.L, snap.N, sigma, 8 * sigma, out=G)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_gaussian_descriptors(snap.positions, snap.L, snap.N, sigma, 8 * sigma, out=G)
+    ms = ctx.profile_read()["gauss"][0] / reps
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    return {"sigma": sigma, "cutoff": 8 * sigma, "ms_per_grid": ms,
+            "points_per_s": snap.n_points / (ms * 1e-3),
+            "write_GB_s": 4.0 * snap.n_points / (ms * 1e-3) / 1e9,
+            "sum_G_dV_over_atoms": float(G.double().sum().item()) * snap.dV / snap.n_atoms}
+
+
 def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5, loads=(0.5, 0.7, 0.9)):
     """Poisson streams of the serving mix through the library's request loop.
 
@@ -432,6 +451,7 @@ def main():
                    "minus_ts_mev_per_atom": 1000 * r["e_entropy"] / snap.n_atoms, "entropy_kb": r["entropy"]},
         "errors_vs_oracle": errors_vs_oracle(a.workload, snap, dos, mala.read_result(res), dens),
     }
+    out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
     if a.serve_requests > 0:
         out["serving"] = serving_bench(mala, prec, a.serve_requests)
         out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]

@@ -139,6 +139,20 @@ mala_status mala_descriptors(mala_ctx* ctx, const double* positions, int32_t n_a
                              const mala_cell_grid* cg, double rcut, int32_t twojmax,
                              int64_t pt_begin, int64_t pt_end, float* B_out);
 
+/* Gaussian descriptors of grid points [pt_begin, pt_end): the Gaussian
+ * representation of the ionic positions behind the structure factor
+ * (Eq. structurefactor_gaussian), a Gaussian of width sigma normalised to
+ * unit integral on every atom and periodic image within the cutoff:
+ *   G(r) = (2 pi sigma^2)^(-3/2) sum_{|r-R| < cutoff} exp(-|r-R|^2 / (2 sigma^2)).
+ *  positions: host float64 [n_atoms][3]; cg as for mala_descriptors;
+ *  sigma > 0 and cutoff > 0 in Angstrom (cutoff = 8 sigma leaves e^-32 of
+ *  each Gaussian out); G_out: device float32 [pt_end - pt_begin].
+ * Empty ranges are a no-op.  More than 1024 atom images near one 64-point
+ * tile is reported by mala_check_device_errors (MALA_E_CAPACITY).          */
+mala_status mala_gaussian_descriptors(mala_ctx* ctx, const double* positions, int32_t n_atoms,
+                                      const mala_cell_grid* cg, double sigma, double cutoff,
+                                      int64_t pt_begin, int64_t pt_end, float* G_out);
+
 /* LDOS of n_pts points through the network (Eq. ffnn) and the output
  * transform.  B: device float32 [n_pts][w0]; ldos_out: device float32
  * [n_pts][wL].                                                                */
@@ -247,7 +261,8 @@ mala_status mala_server_destroy(mala_server* s);
 #define MALA_STAGE_INTEGRATE 7    /* stored-LDOS column sums and density     */
 #define MALA_STAGE_ESTIMATE 8     /* E_F estimate on a point subsample       */
 #define MALA_STAGE_DENSITY_WINDOW 9 /* density from the stored energy window */
-#define MALA_N_STAGES 10
+#define MALA_STAGE_GAUSS 10       /* Gaussian descriptors                    */
+#define MALA_N_STAGES 11
 mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
 mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
 

@@ -64,6 +64,7 @@ def lib():
         L.oracle_li_neg.argtypes = [i, d]
         L.oracle_fermi_weights.argtypes = [d, d, i, d, d, p, p]
         L.oracle_entropy_weights.argtypes = [d, d, i, d, d, p]
+        L.oracle_gaussian.argtypes = [p, i, p, p, d, d, p, i64, p, i]
         L.oracle_entropy.restype = d
         L.oracle_entropy.argtypes = [p, d, d, i, d, d, p]
         L.oracle_fermi.restype = i
@@ -174,6 +175,21 @@ def descriptors(snap, points=None, nthreads=0, return_meta=False):
     if return_meta:
         return B, {"max_neighbours": worst, "max_imag": mi.value}
     return B
+
+
+def gaussian(snap, sigma, cutoff, points=None, nthreads=0):
+    """Gaussian descriptors G(r) (normalised Gaussians on every atom image within
+    the cutoff) at flat grid indices `points` (default: all)."""
+    if points is None:
+        points = np.arange(snap.n_points, dtype=np.int64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    pos = _f64(snap.positions)
+    L = _f64(snap.L)
+    N = np.ascontiguousarray(snap.N, dtype=np.int32)
+    out = np.zeros(pts.shape[0])
+    lib().oracle_gaussian(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N), float(sigma), float(cutoff),
+                          _ptr(pts), pts.shape[0], _ptr(out), int(nthreads))
+    return out
 
 
 def mlp(B, net, nthreads=0):

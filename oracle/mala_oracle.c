@@ -293,6 +293,39 @@ int oracle_neighbours(const double *pos, int n_atoms, const double *L, const int
     return cnt;
 }
 
+/* Gaussian descriptors: the Gaussian representation of the ionic positions
+ * that gives the structure factor (Eq. structurefactor_gaussian), a
+ * normalised Gaussian of width sigma on every atom and periodic image:
+ *   G(r) = sum_{atoms, images, |r-R| < cutoff} (2 pi sigma^2)^(-3/2) exp(-|r-R|^2 / (2 sigma^2)),
+ * at the listed flat grid points.                                          */
+void oracle_gaussian(const double *pos, int n_atoms, const double *L, const int *N, double sigma,
+                     double cutoff, const int64_t *pts, int64_t n_pts, double *out, int nthreads)
+{
+    const double norm = pow(2.0 * OR_PI * sigma * sigma, -1.5);
+    int nmax[3];
+    for (int d = 0; d < 3; d++) nmax[d] = (int)ceil(cutoff / L[d]) + 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t q = 0; q < n_pts; q++) {
+        double r[3];
+        grid_point(N, L, pts[q], r);
+        double sum = 0.0;
+        for (int a = 0; a < n_atoms; a++)
+            for (int nx = -nmax[0]; nx <= nmax[0]; nx++)
+                for (int ny = -nmax[1]; ny <= nmax[1]; ny++)
+                    for (int nz = -nmax[2]; nz <= nmax[2]; nz++) {
+                        double dx = pos[3 * a] + nx * L[0] - r[0];
+                        double dy = pos[3 * a + 1] + ny * L[1] - r[1];
+                        double dz = pos[3 * a + 2] + nz * L[2] - r[2];
+                        double d2 = dx * dx + dy * dy + dz * dz;
+                        if (d2 < cutoff * cutoff) sum += exp(-d2 / (2.0 * sigma * sigma));
+                    }
+        out[q] = norm * sum;
+    }
+}
+
 /* B at the listed flat grid points; B_out is [n_pts][n_triples].
  * Returns the largest neighbour count seen (or -1 if max_nbr overflowed). */
 int oracle_descriptors(const double *pos, int n_atoms, const double *L, const int *N,

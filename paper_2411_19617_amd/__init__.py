@@ -26,7 +26,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 RESULT_BYTES = 64
 STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
-          "density_window"]
+          "density_window", "gauss"]
 DENSITY_WINDOW = 0
 DENSITY_RECOMPUTE = 1
 
@@ -83,6 +83,7 @@ def lib():
             ("mala_weights_load", [p, p, sz, i32, ctypes.POINTER(p)]),
             ("mala_weights_free", [p]),
             ("mala_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p]),
+            ("mala_gaussian_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, d, i64, i64, p]),
             ("mala_ldos_infer", [p, p, p, i64, p]),
             ("mala_integrate", [p, p, i64, d, ctypes.POINTER(EGrid), d, d, p, p, p]),
             ("mala_predict", [p, p, p, i32, ctypes.POINTER(CellGrid), d, i32, ctypes.POINTER(EGrid), d, d,
@@ -236,6 +237,19 @@ class Context:
         cg = _cell_grid(L, N)
         _check(lib().mala_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(twojmax),
                                       int(pt_begin), int(pt_end), _ptr(out)))
+        return out
+
+    def mala_gaussian_descriptors(self, positions, L, N, sigma, cutoff, pt_begin=0, pt_end=None, out=None):
+        import torch
+        self._sync_stream()
+        pos, pp, n_at = _positions(positions)
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        pt_end = ntot if pt_end is None else int(pt_end)
+        if out is None:
+            out = torch.empty(max(pt_end - pt_begin, 0), dtype=torch.float32, device=self.torch_device)
+        cg = _cell_grid(L, N)
+        _check(lib().mala_gaussian_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(sigma), float(cutoff),
+                                               int(pt_begin), int(pt_end), _ptr(out)))
         return out
 
     def mala_ldos_infer(self, weights, B, n_out, out=None):

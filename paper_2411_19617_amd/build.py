@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmala.so")
-SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "mlp.hip", "fermi.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "gauss.hip", "mlp.hip", "fermi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
@@ -29,7 +29,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
 def _stale(path, obj):
     if not os.path.exists(obj):
         return True
-    deps = [path, os.path.join(CSRC, "mala_internal.h"), os.path.join(ROOT, "include", "mala.h")]
+    deps = [path, os.path.join(ROOT, "include", "mala.h")]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
     return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
 
 

@@ -227,9 +227,8 @@ mala_status upload_positions(mala_ctx* c, const double* positions, int32_t n_ato
     return MALA_OK;
 }
 
-mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut,
-                            int32_t twojmax, int64_t pt_begin, int64_t pt_end, float* B_out) {
-    BinState bs{};
+// Cell list of the uploaded atoms for neighbour searches within rcut.
+mala_status bin_atoms(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut, BinState* bs) {
     int nc_est = 1;
     for (int d = 0; d < 3; ++d) {
         int nc = (int)floor(cg->L[d] / (0.5 * rcut));
@@ -245,8 +244,16 @@ mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* 
     HIP_TRY(ensure(c->atoms_sorted, na));
     HIP_TRY(staged(c, MALA_STAGE_BIN, 0, [&] {
         return launch_bin(c->stream, c->pos.p, n_atoms, cg->L, rcut, c->cell_count.p, c->cell_start.p,
-                          c->cell_fill.p, c->atoms_tmp.p, c->atom_cell.p, c->atoms_sorted.p, &bs);
+                          c->cell_fill.p, c->atoms_tmp.p, c->atom_cell.p, c->atoms_sorted.p, bs);
     }));
+    return MALA_OK;
+}
+
+mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut,
+                            int32_t twojmax, int64_t pt_begin, int64_t pt_end, float* B_out) {
+    BinState bs{};
+    mala_status st = bin_atoms(c, n_atoms, cg, rcut, &bs);
+    if (st) return st;
     const int nB = n_triples(twojmax);
     const int64_t total = pt_end - pt_begin;
     const int64_t chunk = total < kChunk ? total : kChunk;
@@ -610,6 +617,27 @@ mala_status mala_descriptors(mala_ctx* c, const double* positions, int32_t n_ato
     if ((st = ensure_tables(c, twojmax))) return st;
     if ((st = upload_positions(c, positions, n_atoms))) return st;
     return run_descriptors(c, n_atoms, cg, rcut, twojmax, pt_begin, pt_end, B_out);
+}
+
+mala_status mala_gaussian_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms,
+                                      const mala_cell_grid* cg, double sigma, double cutoff, int64_t pt_begin,
+                                      int64_t pt_end, float* G_out) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    if (!(sigma > 0.0) || !isfinite(sigma)) return fail(MALA_E_INVALID_ARG, "sigma not positive");
+    mala_status st = check_geometry(positions, n_atoms, cg, cutoff, 2);
+    if (st) return st;
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    if (pt_begin < 0 || pt_end < pt_begin || pt_end > ntot) return fail(MALA_E_INVALID_ARG, "bad point range");
+    if (pt_end == pt_begin) return MALA_OK;
+    if (!G_out) return fail(MALA_E_INVALID_ARG, "G_out is NULL");
+    DeviceGuard g(c->device);
+    if ((st = upload_positions(c, positions, n_atoms))) return st;
+    BinState bs{};
+    if ((st = bin_atoms(c, n_atoms, cg, cutoff, &bs))) return st;
+    HIP_TRY(staged(c, MALA_STAGE_GAUSS, pt_end - pt_begin, [&] {
+        return launch_gauss(c->stream, bs, cg->N, sigma, cutoff, pt_begin, pt_end - pt_begin, G_out, c->err);
+    }));
+    return MALA_OK;
 }
 
 mala_status mala_ldos_infer(mala_ctx* c, const mala_weights* w, const float* B, int64_t n_pts, float* ldos_out) {

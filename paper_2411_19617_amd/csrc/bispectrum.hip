@@ -29,7 +29,7 @@
 //           each exchanged pair of rows is formed.  Clebsch-Gordan values of
 //           the coupling come from a per-triple table in global memory read
 //           with wave-uniform (scalar) loads.
-#include "mala_internal.h"
+#include "tile_gather.h"
 
 namespace mala {
 
@@ -207,39 +207,6 @@ __host__ __device__ constexpr double ce_fact(int n) {
     return f;
 }
 
-__device__ __forceinline__ int wave_max_int(int v) {
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_min_d(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_max_d(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Block-wide exclusive scan of one int per thread (blockDim <= 1024).
-__device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) tmp[wave] = x;
-    __syncthreads();
-    int wbase = 0, tot = 0;
-    for (int w = 0; w < nw; ++w) {
-        if (w < wave) wbase += tmp[w];
-        tot += tmp[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return wbase + x - v;
-}
-
 template <int TJ>
 __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int Nx, int Ny, int Nz,
                                                           double rcut, int64_t pt_begin, int64_t n_pts,
@@ -251,7 +218,6 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
     __shared__ unsigned short nbr[kMaxNbr][kTile];
     __shared__ int nnbr[kTile];
     __shared__ int scan_tmp[16];
-    __shared__ int s_ncand;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t tile = blockIdx.x;
@@ -266,65 +232,12 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
     const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
                  oz = (double)qk * bins.L[2] / Nz;
     // bounding box of the tile's points
-    const double lox = wave_min_d(rx), hix = wave_max_d(rx);
-    const double loy = wave_min_d(ry), hiy = wave_max_d(ry);
-    const double loz = wave_min_d(rz), hiz = wave_max_d(rz);
-    const double rc2 = rcut * rcut;
+    const double lo[3] = {wave_min_d(rx), wave_min_d(ry), wave_min_d(rz)};
+    const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
+    const double org[3] = {ox, oy, oz};
 
-    // ---- candidate atom images: cells overlapping the box grown by rcut,
-    //      visited in a fixed order, compacted with a block scan.
-    int c_lo[3], c_n[3];
-    {
-        const double lo[3] = {lox - rcut, loy - rcut, loz - rcut};
-        const double hi[3] = {hix + rcut, hiy + rcut, hiz + rcut};
-        for (int d = 0; d < 3; ++d) {
-            c_lo[d] = (int)floor(lo[d] / bins.cs[d]);
-            c_n[d] = (int)floor(hi[d] / bins.cs[d]) - c_lo[d] + 1;
-        }
-    }
-    const int ncells = c_n[0] * c_n[1] * c_n[2];
-    int base = 0;
-    for (int c0 = 0; c0 < ncells; c0 += blockDim.x) {
-        const int c = c0 + threadIdx.x;
-        int cnt = 0, b = 0, e = 0;
-        double sx = 0, sy = 0, sz = 0;
-        if (c < ncells) {
-            const int cz = c % c_n[2], cy = (c / c_n[2]) % c_n[1], cx = c / (c_n[2] * c_n[1]);
-            const int gx = c_lo[0] + cx, gy = c_lo[1] + cy, gz = c_lo[2] + cz;
-            const int wx = ((gx % bins.nc[0]) + bins.nc[0]) % bins.nc[0];
-            const int wy = ((gy % bins.nc[1]) + bins.nc[1]) % bins.nc[1];
-            const int wz = ((gz % bins.nc[2]) + bins.nc[2]) % bins.nc[2];
-            sx = (double)((gx - wx) / bins.nc[0]) * bins.L[0];
-            sy = (double)((gy - wy) / bins.nc[1]) * bins.L[1];
-            sz = (double)((gz - wz) / bins.nc[2]) * bins.L[2];
-            const int cell = (wx * bins.nc[1] + wy) * bins.nc[2] + wz;
-            b = bins.cell_start[cell];
-            e = bins.cell_start[cell + 1];
-            for (int a = b; a < e; ++a) {
-                const double4 at = bins.atoms[a];
-                const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
-                const double dx = fmax(0.0, fmax(lox - X, X - hix));
-                const double dy = fmax(0.0, fmax(loy - Y, Y - hiy));
-                const double dz = fmax(0.0, fmax(loz - Z, Z - hiz));
-                cnt += (dx * dx + dy * dy + dz * dz < rc2);
-            }
-        }
-        int total;
-        int off = base + block_exclusive_scan(cnt, scan_tmp, &total);
-        for (int a = b; a < e; ++a) {
-            const double4 at = bins.atoms[a];
-            const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
-            const double dx = fmax(0.0, fmax(lox - X, X - hix));
-            const double dy = fmax(0.0, fmax(loy - Y, Y - hiy));
-            const double dz = fmax(0.0, fmax(loz - Z, Z - hiz));
-            if (dx * dx + dy * dy + dz * dz < rc2) {
-                if (off < kMaxCand)
-                    cand[off] = make_float4((float)(X - ox), (float)(Y - oy), (float)(Z - oz), 0.f);
-                ++off;
-            }
-        }
-        base += total;
-    }
+    // ---- candidate atom images within rcut of the box, in a fixed order
+    const int base = gather_candidates(bins, lo, hi, org, rcut, cand, kMaxCand, scan_tmp);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     __syncthreads();

@@ -152,6 +152,8 @@ hipError_t launch_ui(hipStream_t s, int twojmax, const BinState& bins, const int
                      int64_t pt_begin, int64_t n_pts, float2* u_scratch, int* err_flag);
 hipError_t launch_zb(hipStream_t s, int twojmax, int64_t n_pts, const float2* u_scratch, float* B_out,
                      const float* cg_table, const int* cg_offsets, const int* wave_triples, int zb_waves);
+hipError_t launch_gauss(hipStream_t s, const BinState& bins, const int N[3], double sigma, double cutoff,
+                        int64_t pt_begin, int64_t n_pts, float* out, int* err_flag);
 
 struct MlpArgs {
     int precision;               // 0 fp32, 1 bf16

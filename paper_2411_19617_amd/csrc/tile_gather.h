@@ -1,0 +1,105 @@
+// Device helpers shared by the kernels that visit, for a tile of grid
+// points, every atom image within a cutoff (the neighbour sums of
+// Eq. ionicdensity and the Gaussian descriptors): wave reductions, a block
+// scan, and the candidate gather over the cell list.
+#pragma once
+
+#include "mala_internal.h"
+
+namespace mala {
+
+__device__ __forceinline__ int wave_max_int(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim <= 1024).
+__device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) tmp[wave] = x;
+    __syncthreads();
+    int wbase = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) wbase += tmp[w];
+        tot += tmp[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + x - v;
+}
+
+// Candidate atom images of a tile whose bounding box is [lo, hi]: every image
+// in the cells overlapping the box grown by rcut that lies within rcut of the
+// box, in a fixed order (cells in index order, atoms in cell order), stored
+// relative to the origin o as float4 in cand[0 .. cap).  Called by the whole
+// block; returns the total count, which exceeds cap when the list overflowed
+// (only the first cap are stored).  scan_tmp holds blockDim/64 ints.
+__device__ __forceinline__ int gather_candidates(const BinState& bins, const double lo[3], const double hi[3],
+                                                 const double o[3], double rcut, float4* cand, int cap,
+                                                 int* scan_tmp) {
+    const double rc2 = rcut * rcut;
+    int c_lo[3], c_n[3];
+    for (int d = 0; d < 3; ++d) {
+        c_lo[d] = (int)floor((lo[d] - rcut) / bins.cs[d]);
+        c_n[d] = (int)floor((hi[d] + rcut) / bins.cs[d]) - c_lo[d] + 1;
+    }
+    const int ncells = c_n[0] * c_n[1] * c_n[2];
+    int base = 0;
+    for (int c0 = 0; c0 < ncells; c0 += blockDim.x) {
+        const int c = c0 + threadIdx.x;
+        int cnt = 0, b = 0, e = 0;
+        double sx = 0, sy = 0, sz = 0;
+        if (c < ncells) {
+            const int cz = c % c_n[2], cy = (c / c_n[2]) % c_n[1], cx = c / (c_n[2] * c_n[1]);
+            const int gx = c_lo[0] + cx, gy = c_lo[1] + cy, gz = c_lo[2] + cz;
+            const int wx = ((gx % bins.nc[0]) + bins.nc[0]) % bins.nc[0];
+            const int wy = ((gy % bins.nc[1]) + bins.nc[1]) % bins.nc[1];
+            const int wz = ((gz % bins.nc[2]) + bins.nc[2]) % bins.nc[2];
+            sx = (double)((gx - wx) / bins.nc[0]) * bins.L[0];
+            sy = (double)((gy - wy) / bins.nc[1]) * bins.L[1];
+            sz = (double)((gz - wz) / bins.nc[2]) * bins.L[2];
+            const int cell = (wx * bins.nc[1] + wy) * bins.nc[2] + wz;
+            b = bins.cell_start[cell];
+            e = bins.cell_start[cell + 1];
+            for (int a = b; a < e; ++a) {
+                const double4 at = bins.atoms[a];
+                const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
+                const double dx = fmax(0.0, fmax(lo[0] - X, X - hi[0]));
+                const double dy = fmax(0.0, fmax(lo[1] - Y, Y - hi[1]));
+                const double dz = fmax(0.0, fmax(lo[2] - Z, Z - hi[2]));
+                cnt += (dx * dx + dy * dy + dz * dz < rc2);
+            }
+        }
+        int total;
+        int off = base + block_exclusive_scan(cnt, scan_tmp, &total);
+        for (int a = b; a < e; ++a) {
+            const double4 at = bins.atoms[a];
+            const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
+            const double dx = fmax(0.0, fmax(lo[0] - X, X - hi[0]));
+            const double dy = fmax(0.0, fmax(lo[1] - Y, Y - hi[1]));
+            const double dz = fmax(0.0, fmax(lo[2] - Z, Z - hi[2]));
+            if (dx * dx + dy * dy + dz * dz < rc2) {
+                if (off < cap)
+                    cand[off] = make_float4((float)(X - o[0]), (float)(Y - o[1]), (float)(Z - o[2]), 0.f);
+                ++off;
+            }
+        }
+        base += total;
+    }
+    return base;
+}
+
+}  // namespace mala

@@ -10,6 +10,7 @@ import os
 import numpy as np
 import pytest
 
+import mala_synth
 import oracle
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -513,3 +514,53 @@ def test_entropy_closed_forms():
     assert 0.0 <= S <= 2.5 * oracle.KB_EV * 1e-3 * np.pi ** 2 / 3.0 * (1 + 1e-9)
     u = oracle.entropy_weights(eg, mu, T)
     assert np.all(u >= 0.0)
+
+
+# ---------------------------------------------------------------- Gaussian descriptors
+# Normalised Gaussians on every atom image (the representation behind
+# Eq. structurefactor_gaussian).
+
+def _aliasing_bound(sigma, h):
+    # Poisson summation: sum_p G(p) dV - N_atoms = N_atoms x (sum over nonzero
+    # reciprocal grid vectors of the Gaussian's Fourier transform x phases), so
+    # |error| / N_atoms <= sum_{m != 0} exp(-2 pi^2 sigma^2 sum_d (m_d / h_d)^2)
+    m = np.arange(-4, 5)
+    tot = 0.0
+    for a in m:
+        for b in m:
+            for c in m:
+                if a == b == c == 0:
+                    continue
+                tot += np.exp(-2 * np.pi ** 2 * sigma ** 2 * ((a / h[0]) ** 2 + (b / h[1]) ** 2 + (c / h[2]) ** 2))
+    return tot
+
+
+@pytest.mark.parametrize("fac", [0.7, 1.0, 1.5])
+def test_gaussian_integrates_to_atom_count(fac):
+    snap = mala_synth.small()
+    h = snap.L / snap.N
+    sigma = fac * float(np.max(h))
+    G = oracle.gaussian(snap, sigma, 8.0 * sigma)
+    err = abs(G.sum() * snap.dV / snap.n_atoms - 1.0)
+    assert err <= 1.01 * _aliasing_bound(sigma, h) + 1e-13
+    if fac == 0.7:
+        assert err > 1e-7                     # the bound is not vacuous here
+
+
+def test_gaussian_single_atom_closed_form_and_translation():
+    # one atom on a grid point of a large cell: G there is the peak value;
+    # moving the atom by whole grid steps moves the field by the same steps
+    L, N = np.array([12.0, 12.0, 12.0]), np.array([24, 24, 24])
+    sigma = 0.6
+    pos = np.array([[6.0, 6.0, 6.0]])
+    snap = mala_synth.Snapshot("one", pos, L, N, 4.67, 8, 298.0, 3.0)
+    p0 = (12 * 24 + 12) * 24 + 12
+    G = oracle.gaussian(snap, sigma, 5.0)
+    assert abs(G[p0] - (2 * np.pi * sigma ** 2) ** -1.5) <= 1e-15 * G[p0]
+    snap2 = mala_synth.Snapshot("one", pos + np.array([0.5, 1.0, 1.5]), L, N, 4.67, 8, 298.0, 3.0)
+    G2 = oracle.gaussian(snap2, sigma, 5.0).reshape(24, 24, 24)
+    G1 = np.roll(G.reshape(24, 24, 24), (1, 2, 3), axis=(0, 1, 2))
+    assert np.max(np.abs(G2 - G1)) <= 1e-14 * np.max(G)
+    # a point 1 A from the atom along x sees exp(-1/(2 sigma^2)) of the peak
+    p1 = (14 * 24 + 12) * 24 + 12
+    assert abs(G[p1] / G[p0] - np.exp(-1.0 / (2 * sigma ** 2))) <= 1e-14
