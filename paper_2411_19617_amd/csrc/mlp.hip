@@ -243,15 +243,43 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
     const int KS1 = a.in_pad / P::K, KS2 = a.h1_tiles * 16 / P::K, KS3 = a.h2_tiles * 16 / P::K;
     const int n_in = a.n_in;
 
+    // DOS column sums: every lane keeps the FP64 sums of its 8 energies over
+    // all of its points and iterations; the 16 point lanes are combined once
+    // at the end (fixed order)
+    double dacc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    // input staging: thread t owns column k_t of the [NP][in_pad] tile and
+    // rows r_t, r_t + R, ... (R = blockDim / in_pad >= 4 rows per pass, as
+    // in_pad <= 128). All of its loads are issued before any is used; a row
+    // past the tile's last valid point re-reads that point (always in bounds)
+    // and is stored as zero, and a pad column re-reads column n_in - 1.
+    constexpr int SPT = NP / 4;
+    const int R = (kWaves * 64) / a.in_pad;
+    const int k_t = threadIdx.x % a.in_pad, r_t = threadIdx.x / a.in_pad;
+    const bool col_in = k_t < n_in;
+    const int k_c = col_in ? k_t : n_in - 1;
+    const float mu_t = a.in_mean[k_c], rs_t = a.in_rstd[k_c];
+    const int rsn = row_stride * n_in;                 // floats per tile row; NP * rsn * 4 < 2^31 (host check)
+
     for (int64_t it = it_begin; it < it_end; ++it) {
         const int64_t p0 = it * NP;
         const int rows = (int)((n_pts - p0) < NP ? (n_pts - p0) : NP);
-        for (int e = threadIdx.x; e < NP * a.in_pad; e += blockDim.x) {
-            const int pj = e / a.in_pad, k = e - pj * a.in_pad;
-            float v = 0.f;
-            if (pj < rows && k < n_in)
-                v = (B[(p0 + pj) * row_stride * n_in + k] - a.in_mean[k]) * a.in_rstd[k];
-            X0[pj * xs + k] = P::cvt(v);
+        if (r_t < R) {
+            // the empty asm makes the row index loop-variant, so the per-row
+            // offsets are formed next to their loads and not held across the loop
+            int row0 = r_t;
+            asm volatile("" : "+v"(row0));
+            const char* Bt = reinterpret_cast<const char*>(B + p0 * row_stride * n_in);
+            float v[SPT];
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int row = min(row0 + q * R, rows - 1);
+                v[q] = *reinterpret_cast<const float*>(Bt + (unsigned)((row * rsn + k_c) * 4));
+            }
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int pj = row0 + q * R;
+                if (pj < NP) X0[pj * xs + k_t] = P::cvt((col_in && pj < rows) ? (v[q] - mu_t) * rs_t : 0.f);
+            }
         }
         __syncthreads();
         layer<PREC, NT>(a.W1, a.b1, a.h1_tiles, 0, KS1, X0, xs, H1, hs, a.slope, wave, lane);
@@ -319,13 +347,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
                         }
                     }
                 }
-                if constexpr (MODE == kModeDos || MODE == kModeDosWindow) {
-                    dsum += __shfl_xor(dsum, 1, 16);
-                    dsum += __shfl_xor(dsum, 2, 16);
-                    dsum += __shfl_xor(dsum, 4, 16);
-                    dsum += __shfl_xor(dsum, 8, 16);
-                    if (j == 0 && ev) s_dos[e] += dsum;
-                }
+                if constexpr (MODE == kModeDos || MODE == kModeDosWindow) dacc[i][r] += dsum;
             }
         }
         if constexpr (MODE == kModeDensity || MODE == kModeDosWindow) {
@@ -348,6 +370,21 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
         __syncthreads();
     }
     if constexpr (MODE == kModeDos || MODE == kModeDosWindow) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int ot = wave + kWaves * i;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = dacc[i][r];
+                v += __shfl_xor(v, 1, 16);
+                v += __shfl_xor(v, 2, 16);
+                v += __shfl_xor(v, 4, 16);
+                v += __shfl_xor(v, 8, 16);
+                const int e = 16 * ot + 4 * g + r;
+                if (j == 0 && ot < a.out_tiles && e < a.n_out) s_dos[e] = v;
+            }
+        }
+        __syncthreads();
         for (int e = threadIdx.x; e < kMlpMaxOut; e += blockDim.x)
             o.partials[(size_t)blockIdx.x * kMlpMaxOut + e] = s_dos[e];
     }
@@ -377,6 +414,7 @@ static hipError_t launch_pmn(hipStream_t s, const MlpArgs& a, const float* B, in
 template <int PREC, int MODE>
 static hipError_t launch_pm(hipStream_t s, const MlpArgs& a, const float* B, int64_t n_pts, int row_stride,
                             int n_blocks, const MlpOut& o) {
+    if ((int64_t)row_stride * a.n_in * 4 * 64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     if (lds_bytes<PREC, 4>(a) <= kMlpLdsBudget) return launch_pmn<PREC, MODE, 4>(s, a, B, n_pts, row_stride, n_blocks, o);
     return launch_pmn<PREC, MODE, 2>(s, a, B, n_pts, row_stride, n_blocks, o);
 }
