@@ -313,17 +313,9 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
 }
 
 // ------------------------------------------------------------------ Z / B
-// u element (J, row r [compile time], column c [runtime, uniform]) from the
-// half storage; rows past J/2 come from the conjugate symmetry.
-template <int J, int R>
-__device__ __forceinline__ float2 uload(const float2* __restrict__ su, int c, int lane) {
-    if constexpr (2 * R <= J) {
-        return su[(half_off(J) + R * (J + 1) + c) * kTile + lane];
-    } else {
-        const float2 v = su[(half_off(J) + (J - R) * (J + 1) + (J - c)) * kTile + lane];
-        const float sg = ((R - c) & 1) ? -1.f : 1.f;
-        return make_float2(sg * v.x, -sg * v.y);
-    }
+// x * (-1)^k for wave-uniform x and k, as a sign-bit flip on the scalar unit
+__device__ __forceinline__ float flip_odd(float x, int k) {
+    return __int_as_float(__float_as_int(x) ^ (int)((unsigned)(k & 1) << 31));
 }
 
 // Number of (ma, ma1) row pairs of a triple (rows ma <= J/2), their index,
@@ -345,22 +337,10 @@ __host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, i
             }
     return -1;
 }
-__host__ __device__ constexpr bool zb_row1_used(int J1, int J2, int J, int ma1) {
-    for (int ma = 0; ma <= J / 2; ++ma)
-        if (zb_pair_ok(J1, J2, J, ma, ma1)) return true;
-    return false;
-}
-__host__ __device__ constexpr bool zb_row2_used(int J1, int J2, int J, int r) {
-    const int D = (J1 + J2 - J) / 2;
-    for (int ma = 0; ma <= J / 2; ++ma)
-        for (int ma1 = 0; ma1 <= J1; ++ma1)
-            if (zb_pair_ok(J1, J2, J, ma, ma1) && ma - ma1 + D == r) return true;
-    return false;
-}
-
 // B(j1,j2,j) of the lane's point.  For each output column mb:
-//   T[ma][ma1] = sum_mb1 (C(mb1,mb) u1[ma1][mb1]) u2[ma-ma1+D][mb-mb1+D]
-// (the scaled u1 element is shared by every row ma), then
+//   T[ma][ma1] = sum_mb1 C(mb1,mb) u1[ma1][mb1] u2[ma-ma1+D][mb-mb1+D]
+// (the CG factor scales the column of whichever level has fewer rows to
+// scale, zb_scale2, and is shared by every row ma), then
 //   Z[ma][mb] = sum_ma1 C(ma1,ma) T[ma][ma1],  B += w Re(conj(u[ma][mb]) Z[ma][mb]).
 // Z has the symmetry of u, so rows ma < J/2 count twice (w = 2); the middle
 // row of an even J is its own mirror image with columns mb and J-mb paired,
@@ -368,6 +348,11 @@ __host__ __device__ constexpr bool zb_row2_used(int J1, int J2, int J, int r) {
 // last in each column body behind one wave-uniform branch.  For J1 == J2
 // only the pairs of zb_pair_ok are formed; the others equal their exchanged
 // partner (zb_pair_doubled).
+// A row past J/2 of a level is (-1)^(row - column) times the conjugate of
+// the stored row J - row at column J - column.  The level offsets in the u
+// tile are kept opaque in scalar registers, so that every column costs one
+// address add per level side and all row offsets fit the LDS instruction's
+// immediate field.
 template <int J1, int J2, int J>
 __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int lane,
                                            const float* __restrict__ cg) {
@@ -377,6 +362,12 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
     constexpr int HN = MID ? HR - 1 : HR;  // last row formed for every column
     constexpr int W = J + 1;               // cg row stride: cg[ma1*W + ma]
     constexpr int NP = zb_pairs(J1, J2, J);
+    constexpr bool S2 = zb_scale2(J1, J2, J);
+    int off1 = half_off(J1) * kTile, off2 = half_off(J2) * kTile, off3 = half_off(J) * kTile;
+    asm volatile("" : "+s"(off1), "+s"(off2), "+s"(off3));
+    const float2* l1 = su + lane + off1;
+    const float2* l2 = su + lane + off2;
+    const float2* l3 = su + lane + off3;
     float bsum = 0.f;
 #pragma clang loop unroll(disable)
     for (int mb = 0; mb <= J; ++mb) {
@@ -401,29 +392,40 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
         auto column = [&](int mb1, auto first) {
             const int mb2 = mb + D - mb1;
             const float c2 = cg[mb1 * W + mb];
-            const float c2p = (mb1 & 1) ? -c2 : c2;          // c2 (-1)^mb1 (wave-uniform)
+            // scalar factors of the mirrored rows: (-1)^column, times c2 on the scaled side
+            const float f1 = flip_odd(S2 ? 1.f : c2, mb1);
+            const float f2 = flip_odd(S2 ? c2 : 1.f, mb2);
+            const float2* s1 = l1 + mb1 * kTile;             // stored rows of u^J1, column mb1
+            const float2* m1 = l1 + (J1 - mb1) * kTile;      // their mirror column
+            const float2* s2 = l2 + mb2 * kTile;
+            const float2* m2 = l2 + (J2 - mb2) * kTile;
             float u2r[J2 + 1], u2i[J2 + 1];
             static_for<0, J2 + 1>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
                 if constexpr (zb_row2_used(J1, J2, J, r)) {
-                    const float2 v = uload<J2, r>(su, mb2, lane);
-                    u2r[r] = v.x;
-                    u2i[r] = v.y;
+                    if constexpr (2 * r <= J2) {
+                        const float2 v = s2[r * (J2 + 1) * kTile];
+                        u2r[r] = S2 ? c2 * v.x : v.x;
+                        u2i[r] = S2 ? c2 * v.y : v.y;
+                    } else {
+                        const float2 v = m2[(J2 - r) * (J2 + 1) * kTile];
+                        const float f = (r & 1) ? -f2 : f2;
+                        u2r[r] = f * v.x;
+                        u2i[r] = -f * v.y;
+                    }
                 }
             });
             float wrs[J1 + 1], wis[J1 + 1];
             static_for<0, J1 + 1>([&](auto r1c) {
                 constexpr int ma1 = decltype(r1c)::value;
                 if constexpr (zb_row1_used(J1, J2, J, ma1)) {
-                    // scaled u1 element; a mirrored row is (-1)^(ma1-mb1) conj of
-                    // the stored one, its sign folded into the scalar factor
                     if constexpr (2 * ma1 <= J1) {
-                        const float2 v = su[(half_off(J1) + ma1 * (J1 + 1) + mb1) * kTile + lane];
-                        wrs[ma1] = c2 * v.x;
-                        wis[ma1] = c2 * v.y;
+                        const float2 v = s1[ma1 * (J1 + 1) * kTile];
+                        wrs[ma1] = S2 ? v.x : c2 * v.x;
+                        wis[ma1] = S2 ? v.y : c2 * v.y;
                     } else {
-                        const float2 v = su[(half_off(J1) + (J1 - ma1) * (J1 + 1) + (J1 - mb1)) * kTile + lane];
-                        const float f = (ma1 & 1) ? -c2p : c2p;
+                        const float2 v = m1[(J1 - ma1) * (J1 + 1) * kTile];
+                        const float f = (ma1 & 1) ? -f1 : f1;
                         wrs[ma1] = f * v.x;
                         wis[ma1] = -f * v.y;
                     }
@@ -449,6 +451,7 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
         // list is inlined into one kernel) and doubles the code size
 #pragma clang loop unroll(disable)
         for (int mb1 = lo + 1; mb1 <= hi; ++mb1) column(mb1, std::false_type{});
+        const float2* s3 = l3 + mb * kTile;
         static_for<0, HR + 1>([&](auto mc) {
             constexpr int ma = decltype(mc)::value;
             constexpr bool MIDROW = MID && ma == HR;
@@ -473,7 +476,7 @@ __device__ __forceinline__ float zb_triple(const float2* __restrict__ su, int la
                 zi = fmaf(2.f, zi2, zi);
             }
             const float w = MIDROW ? (mb < HR ? 2.f : 1.f) : 2.f;
-            const float2 uj = su[(half_off(J) + ma * (J + 1) + mb) * kTile + lane];
+            const float2 uj = s3[ma * (J + 1) * kTile];
             bsum += w * (uj.x * zr + uj.y * zi);
         });
     }

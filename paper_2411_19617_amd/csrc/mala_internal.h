@@ -80,10 +80,56 @@ __host__ __device__ constexpr bool zb_pair_doubled(int A, int B, int C, int ma, 
     return A == B && zb_pair_ok(A, B, C, ma, ma1) && ma1 < ma - ma1 + (A + B - C) / 2;
 }
 
+// Rows of u^A (ma1) and of u^B (r = ma2) that the pairs of a triple use.
+__host__ __device__ constexpr bool zb_row1_used(int A, int B, int C, int ma1) {
+    for (int ma = 0; ma <= C / 2; ++ma)
+        if (zb_pair_ok(A, B, C, ma, ma1)) return true;
+    return false;
+}
+__host__ __device__ constexpr bool zb_row2_used(int A, int B, int C, int r) {
+    const int D = (A + B - C) / 2;
+    for (int ma = 0; ma <= C / 2; ++ma)
+        for (int ma1 = 0; ma1 <= A; ++ma1)
+            if (zb_pair_ok(A, B, C, ma, ma1) && ma - ma1 + D == r) return true;
+    return false;
+}
+
+// Per output-column work of a m1' column besides the complex FMAs.  The CG
+// factor C(m1',m') scales the used rows of one of the two levels (2
+// multiplies a row); a mirrored row (past J/2) is a signed conjugate of a
+// stored one whose sign (-1)^(row - column) changes with the runtime column:
+// on the scaled side it folds into the scalar factor, on the other side it
+// costs 2 multiplies.  side 1 scales u^A, side 2 scales u^B.
+struct ZbRows {
+    int used1, mirr1, stor1, used2, mirr2, stor2;
+};
+__host__ __device__ constexpr ZbRows zb_rows(int A, int B, int C) {
+    ZbRows r{0, 0, 0, 0, 0, 0};
+    for (int i = 0; i <= A; ++i)
+        if (zb_row1_used(A, B, C, i)) {
+            ++r.used1;
+            if (2 * i > A) ++r.mirr1; else ++r.stor1;
+        }
+    for (int i = 0; i <= B; ++i)
+        if (zb_row2_used(A, B, C, i)) {
+            ++r.used2;
+            if (2 * i > B) ++r.mirr2; else ++r.stor2;
+        }
+    return r;
+}
+__host__ __device__ constexpr int zb_scale_ops(int A, int B, int C, int side) {
+    const ZbRows r = zb_rows(A, B, C);
+    return side == 1 ? 2 * r.used1 + 2 * r.mirr2 : 2 * r.used2 + 2 * r.mirr1;
+}
+__host__ __device__ constexpr bool zb_scale2(int A, int B, int C) {
+    return zb_scale_ops(A, B, C, 2) < zb_scale_ops(A, B, C, 1);
+}
+
 // Operation count of the Z/B contraction with output index C and coupled
-// pair (A, B): per output column, every m1' column of u^A updates the pairs
-// of T (4 FMA) after its loads, then the row CG fold over the half rows; the
-// middle row of an even C is formed for the columns mb <= C/2 only.
+// pair (A, B): per output column, every m1' column updates the pairs of T
+// (4 FMA) after its loads (one address add per level side in use) and
+// scaling, then the row CG fold over the half rows; the middle row of an
+// even C is formed for the columns mb <= C/2 only.
 __host__ __device__ constexpr double zb_cost(int A, int B, int C) {
     const int D = (A + B - C) / 2, HR = C / 2;
     int terms = 0, mid = 0;
@@ -93,11 +139,14 @@ __host__ __device__ constexpr double zb_cost(int A, int B, int C) {
                 if (C % 2 == 0 && ma == HR) ++mid;
                 else ++terms;
             }
+    const ZbRows r = zb_rows(A, B, C);
+    const int s1 = zb_scale_ops(A, B, C, 1), s2 = zb_scale_ops(A, B, C, 2);
+    const int col = (s1 < s2 ? s1 : s2) + (r.stor1 > 0) + (r.mirr1 > 0) + (r.stor2 > 0) + (r.mirr2 > 0) + 2;
     double tot = 0.0;
     for (int mb = 0; mb <= C; ++mb) {
         const int lo = mb + D - B > 0 ? mb + D - B : 0, hi = A < mb + D ? A : mb + D;
         const int t = terms + (mb <= HR ? mid : 0);
-        tot += (hi - lo + 1) * (4.0 * t + 2.0 * (A + 1) + (B + 1) + 2.0) + 2.0 * t + 3.0 * (HR + 1);
+        tot += (hi - lo + 1) * (4.0 * t + col) + 2.0 * t + 3.0 * (HR + 1);
     }
     return tot;
 }
