@@ -223,7 +223,15 @@ def stats_summary(prof_dir, bench_json, out_name, command):
     if not f:
         raise SystemExit("no kernel_stats.csv under %s" % prof_dir)
     rows = list(csv.DictReader(open(f[0])))
-    b = json.loads(open(bench_json).read().strip().split("\n")[-1])
+    b = None
+    for line in open(bench_json).read().split("\n"):    # the profiler may log after the bench line
+        if line.startswith("{"):
+            try:
+                b = json.loads(line)
+            except ValueError:
+                pass
+    if b is None:
+        raise SystemExit("no bench JSON line in %s" % bench_json)
     cfg, rf = b["config"], b["roofline"]
     lines = ["# rocprofv3 kernel stats: %s, %s network" % (cfg["workload"], cfg["network_precision"]), "",
              "Command (repository root = $REPO on the GPU box):", "", "```",
