@@ -59,6 +59,7 @@ def lib():
         L.oracle_descriptors.restype = i
         L.oracle_descriptors.argtypes = [p, i, p, p, d, i, p, i64, p, p, i]
         L.oracle_mlp.argtypes = [p, i64, i, p, p, p, p, p, p, p, d, i, p, i]
+        L.oracle_mlp_vjp.argtypes = [p, i64, i, p, p, p, p, p, p, d, i, p, p, p, i]
         L.oracle_dos.argtypes = [p, i64, i, d, p]
         L.oracle_li_neg.restype = d
         L.oracle_li_neg.argtypes = [i, d]
@@ -205,6 +206,28 @@ def mlp(B, net, nthreads=0):
                      _ptr(_f64(net["out_scale"])), _ptr(_f64(net["out_shift"])),
                      float(net["slope"]), int(net["output_activation"]), _ptr(out), int(nthreads))
     return out
+
+
+def mlp_vjp(B, net, v, nthreads=0):
+    """g(p) = (dd(p)/dB(p))^T v(p): the network factor of the force expression
+    (Eq. forcesmala) applied to v [n][n_e] by backpropagation in FP64.
+    Returns (g [n][n_in], margin [n]); margin is each point's smallest
+    |z| / (|b| + sum |W x|) over the units that pass through the activation
+    (its distance from a kink of the piecewise-linear network)."""
+    B = _f64(B)
+    n = B.shape[0]
+    widths = np.ascontiguousarray(net["widths"], dtype=np.int32)
+    v = _f64(v)
+    assert v.shape == (n, widths[-1])
+    Wcat = np.concatenate([_f64(w).reshape(-1) for w in net["W"]])
+    bcat = np.concatenate([_f64(b) for b in net["b"]])
+    g = np.zeros((n, widths[0]))
+    margin = np.zeros(n)
+    lib().oracle_mlp_vjp(_ptr(B), n, len(widths) - 1, _ptr(widths), _ptr(Wcat), _ptr(bcat),
+                         _ptr(_f64(net["in_mean"])), _ptr(_f64(net["in_std"])), _ptr(_f64(net["out_scale"])),
+                         float(net["slope"]), int(net["output_activation"]), _ptr(v), _ptr(g), _ptr(margin),
+                         int(nthreads))
+    return g, margin
 
 
 def dos(ldos, dV):

@@ -410,6 +410,96 @@ void oracle_mlp(const double *B, int64_t n_pts, int n_layers, const int *widths,
     }
 }
 
+/* ------------------------------------------------------------ network VJP
+ * The middle factor of the force expression (Eq. forcesmala): for a vector
+ * v(p) over the energies, g(p) = (dd(p)/dB(p))^T v(p), by backpropagation
+ * through the network of oracle_mlp in FP64.  Layer l forms
+ * z_l = W_l x_{l-1} + b_l and x_l = sigma(z_l) (on the output layer only
+ * when out_act), x_0 = (B - mean)/std, d_e = s_e x_L,e + c_e.  With
+ * sigma'(z) = 1 for z > 0 and slope otherwise:
+ *   delta_L = s .* v .* sigma'(z_L)    (sigma' = 1 without output activation)
+ *   delta_{l-1} = (W_l^T delta_l) .* sigma'(z_{l-1})
+ *   g = (W_1^T delta_1) ./ std.
+ * margin[p] (if not NULL) = min over the units that pass through sigma of
+ * |z| / (|b| + sum_i |W_i x_i|): the distance of each unit from its kink
+ * relative to the size of the terms that form z.  Evaluated in another
+ * precision, a unit can land on the other side of its kink only where this
+ * is at that precision's rounding level; there the derivative jumps.       */
+void oracle_mlp_vjp(const double *B, int64_t n_pts, int n_layers, const int *widths,
+                    const double *Wcat, const double *bcat, const double *in_mean,
+                    const double *in_std, const double *out_scale, double slope, int out_act,
+                    const double *v, double *g, double *margin, int nthreads)
+{
+    int wmax = 0;
+    for (int l = 0; l <= n_layers; l++) if (widths[l] > wmax) wmax = widths[l];
+    const double **Wl = malloc(sizeof(double *) * n_layers), **bl = malloc(sizeof(double *) * n_layers);
+    {
+        const double *W = Wcat, *b = bcat;
+        for (int l = 0; l < n_layers; l++) {
+            Wl[l] = W; bl[l] = b;
+            W += (size_t)widths[l + 1] * widths[l];
+            b += widths[l + 1];
+        }
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        /* x[l] = layer l's output (x[0] = scaled input), z[l] = its pre-activation */
+        double *x = malloc(sizeof(double) * (n_layers + 1) * wmax);
+        double *z = malloc(sizeof(double) * (n_layers + 1) * wmax);
+        double *dl = malloc(sizeof(double) * wmax), *dn = malloc(sizeof(double) * wmax);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t p = 0; p < n_pts; p++) {
+            double mrg = INFINITY;
+            for (int i = 0; i < widths[0]; i++)
+                x[i] = (B[p * widths[0] + i] - in_mean[i]) / in_std[i];
+            for (int l = 0; l < n_layers; l++) {
+                int fin = widths[l], fout = widths[l + 1];
+                const double *xi = x + (size_t)l * wmax;
+                double *zo = z + (size_t)(l + 1) * wmax, *xo = x + (size_t)(l + 1) * wmax;
+                int act = (l < n_layers - 1) || out_act;
+                for (int o = 0; o < fout; o++) {
+                    double s = bl[l][o], mag = fabs(bl[l][o]);
+                    for (int i = 0; i < fin; i++) {
+                        s += Wl[l][(size_t)o * fin + i] * xi[i];
+                        mag += fabs(Wl[l][(size_t)o * fin + i] * xi[i]);
+                    }
+                    zo[o] = s;
+                    xo[o] = (act && s <= 0.0) ? slope * s : s;
+                    if (act && mag > 0.0 && fabs(s) / mag < mrg) mrg = fabs(s) / mag;
+                }
+            }
+            /* backward */
+            int nout = widths[n_layers];
+            const double *zL = z + (size_t)n_layers * wmax;
+            for (int e = 0; e < nout; e++) {
+                double d = out_scale[e] * v[p * nout + e];
+                if (out_act && !(zL[e] > 0.0)) d *= slope;
+                dl[e] = d;
+            }
+            for (int l = n_layers - 1; l >= 0; l--) {
+                int fin = widths[l], fout = widths[l + 1];
+                for (int i = 0; i < fin; i++) {
+                    double s = 0.0;
+                    for (int o = 0; o < fout; o++) s += Wl[l][(size_t)o * fin + i] * dl[o];
+                    if (l > 0 && !(z[(size_t)l * wmax + i] > 0.0)) s *= slope;
+                    dn[i] = s;
+                }
+                memcpy(dl, dn, sizeof(double) * fin);
+            }
+            for (int i = 0; i < widths[0]; i++) g[p * widths[0] + i] = dl[i] / in_std[i];
+            if (margin) margin[p] = mrg;
+        }
+        free(x); free(z); free(dl); free(dn);
+    }
+    free(Wl);
+    free(bl);
+}
+
 /* ------------------------------------------------------------ DOS
  * D_e = dV * sum_p d_e(p): the spatial integral of the LDOS as a sum over
  * grid points times the volume element.                                    */

@@ -564,3 +564,62 @@ def test_gaussian_single_atom_closed_form_and_translation():
     # a point 1 A from the atom along x sees exp(-1/(2 sigma^2)) of the peak
     p1 = (14 * 24 + 12) * 24 + 12
     assert abs(G[p1] / G[p0] - np.exp(-1.0 / (2 * sigma ** 2))) <= 1e-14
+
+
+# ---------------------------------------------------------------- network VJP
+def _vjp_inputs(net, n, seed):
+    """Descriptor rows around the net's input scaler and an energy vector, both
+    float32-representable (the GPU path takes float32)."""
+    rng = np.random.default_rng(seed)
+    w = net["widths"]
+    B = (net["in_mean"] + net["in_std"] * rng.standard_normal((n, w[0]))).astype(np.float32)
+    v = rng.standard_normal((n, w[-1])).astype(np.float32)
+    return B.astype(np.float64), v.astype(np.float64)
+
+
+@pytest.mark.parametrize("out_act", [1, 0])
+def test_mlp_vjp_matches_central_differences(out_act):
+    """The network is piecewise linear in B, so a central difference that
+    crosses no kink is exact up to rounding: g_k = sum_e v_e dd_e/dB_k."""
+    net = mala_synth.make_net([55, 100, 100, 250], 101, 8, output_activation=out_act)
+    B, v = _vjp_inputs(net, 8, 7)
+    g, margin = oracle.mlp_vjp(B, net, v)
+    keep = margin > 1e-4                 # far from every kink: a 1e-7 std step cannot cross one
+    assert keep.sum() >= 4
+    for p in np.nonzero(keep)[0]:
+        for k in range(B.shape[1]):
+            h = 1e-7 * net["in_std"][k]
+            Bp, Bm = B[p:p + 1].copy(), B[p:p + 1].copy()
+            Bp[0, k] += h
+            Bm[0, k] -= h
+            fd = (oracle.mlp(Bp, net) - oracle.mlp(Bm, net))[0] @ v[p] / (2 * h)
+            assert abs(fd - g[p, k]) <= 1e-6 * np.max(np.abs(g[p])), (p, k, fd, g[p, k])
+
+
+@pytest.mark.parametrize("out_act", [1, 0])
+def test_mlp_vjp_linear_network_closed_form(out_act):
+    """slope = 1 makes the network affine: g = ((s .* v) W3 W2 W1) ./ std."""
+    net = mala_synth.make_net([55, 100, 100, 250], 103, 8, output_activation=out_act, slope=1.0)
+    B, v = _vjp_inputs(net, 5, 11)
+    g, _ = oracle.mlp_vjp(B, net, v)
+    W1, W2, W3 = net["W"]
+    ref = ((v * net["out_scale"]) @ W3 @ W2 @ W1) / net["in_std"]
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_mlp_vjp_kink_side_and_margin():
+    """A unit with z <= 0 passes slope * delta back (the kink belongs to the
+    negative side); the margin is the smallest relative distance to a kink."""
+    net = mala_synth.make_net([4, 3, 3, 2], 5, 2, output_activation=1, with_input_scaler=False,
+                              egrid=(-5.0, 0.1, 2))
+    net["W"] = [np.eye(3, 4), np.eye(3), np.eye(2, 3)]
+    net["b"] = [np.zeros(3), np.zeros(3), np.zeros(2)]
+    net["out_scale"], net["out_shift"] = np.ones(2), np.zeros(2)
+    B = np.array([[2.0, -3.0, 0.5, 7.0]])
+    v = np.array([[1.0, 1.0]])
+    g, margin = oracle.mlp_vjp(B, net, v)
+    s = net["slope"]
+    # unit 0 positive through all layers -> 1; unit 1 negative -> slope^3; input 3 unused
+    np.testing.assert_allclose(g[0], [1.0 / net["in_std"][0], s ** 3 / net["in_std"][1], 0.0, 0.0],
+                               rtol=1e-15)
+    assert margin[0] == pytest.approx(1.0)
