@@ -293,6 +293,37 @@ def gaussian_bench(ctx, snap, torch, reps=5):
             "sum_G_dV_over_atoms": float(G.double().sum().item()) * snap.dV / snap.n_atoms}
 
 
+def network_vjp_bench(ctx, mala, snap, net, torch, reps=5):
+    """Network vector-Jacobian product (the network factor of the force
+    expression) over the whole grid with FP32 weights, outside the metric's
+    step: descriptor rows around the input scaler and a random vector over
+    the energies (seeded, generated on the device).  Work per point: the
+    forward pass again plus the three transposed layers, 4 sum(in x out)."""
+    n, w0, wl = snap.n_points, net["widths"][0], net["widths"][-1]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17)
+    x = torch.randn((n, w0), generator=gen, device="cuda", dtype=torch.float32)
+    B = (x * torch.as_tensor(net["in_std"], dtype=torch.float32, device="cuda")
+         + torch.as_tensor(net["in_mean"], dtype=torch.float32, device="cuda")).contiguous()
+    del x
+    v = torch.randn((n, wl), generator=gen, device="cuda", dtype=torch.float32)
+    w = ctx.weights(mala_synth.net_to_blob(net), mala.PREC_FP32)
+    g = ctx.mala_ldos_vjp(w, B, v)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_ldos_vjp(w, B, v, out=g)
+    ms = ctx.profile_read()["mlp_vjp"][0] / reps
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    wd = net["widths"]
+    flops = 4.0 * sum(wd[i] * wd[i + 1] for i in range(len(wd) - 1))
+    tf = flops * n / (ms * 1e-3) / 1e12
+    del B, v, g
+    return {"ms_per_grid": ms, "points_per_s": n / (ms * 1e-3), "flops_per_point": flops,
+            "tflops": tf, "peak": PEAK_MFMA_TFLOPS["fp32"], "frac": tf / PEAK_MFMA_TFLOPS["fp32"],
+            "precision": "f32"}
+
+
 def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5, loads=(0.5, 0.7, 0.9)):
     """Poisson streams of the serving mix through the library's request loop.
 
@@ -460,6 +491,7 @@ def main():
         "errors_vs_oracle": errors_vs_oracle(a.workload, snap, dos, mala.read_result(res), dens),
     }
     out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
+    out["network_vjp"] = network_vjp_bench(ctx, mala, snap, net, torch)
     if a.serve_requests > 0:
         out["serving"] = serving_bench(mala, prec, a.serve_requests)
         out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]

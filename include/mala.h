@@ -159,6 +159,19 @@ mala_status mala_gaussian_descriptors(mala_ctx* ctx, const double* positions, in
 mala_status mala_ldos_infer(mala_ctx* ctx, const mala_weights* w, const float* B,
                             int64_t n_pts, float* ldos_out);
 
+/* Vector-Jacobian product of the network: the network factor of the force
+ * expression (Eq. forcesmala) applied to a vector over the energies,
+ *   g(p) = (dd(p)/dB(p))^T v(p),  d = LDOS of mala_ldos_infer,
+ * by backpropagation (sigma'(z) = 1 for z > 0, slope otherwise; the network
+ * is piecewise linear and g jumps where a unit crosses its kink).
+ *  B: device float32 [n_pts][w0]; v: device float32 [n_pts][wL];
+ *  g_out: device float32 [n_pts][w0] (caller-owned).
+ * FP32 weights only (MALA_E_UNSUPPORTED for BF16 weights: rounding there
+ * moves units across their kinks often enough to change g by percent).
+ * n_pts = 0 is a no-op.                                                      */
+mala_status mala_ldos_vjp(mala_ctx* ctx, const mala_weights* w, const float* B, const float* v,
+                          int64_t n_pts, float* g_out);
+
 /* Observables from a stored LDOS (Sec. 3.4): DOS, Fermi level, band
  * energy, electronic entropy (Eq. electronicentropyDOS) and density.
  *  ldos: device float32 [n_pts][eg->n]; dV = cell volume / N_points;
@@ -262,7 +275,8 @@ mala_status mala_server_destroy(mala_server* s);
 #define MALA_STAGE_ESTIMATE 8     /* E_F estimate on a point subsample       */
 #define MALA_STAGE_DENSITY_WINDOW 9 /* density from the stored energy window */
 #define MALA_STAGE_GAUSS 10       /* Gaussian descriptors                    */
-#define MALA_N_STAGES 11
+#define MALA_STAGE_MLP_VJP 11     /* network vector-Jacobian product         */
+#define MALA_N_STAGES 12
 mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
 mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
 

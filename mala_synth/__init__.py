@@ -268,6 +268,16 @@ def paper_net():
     return make_net([91, 400, 400, 250], 102, 10)
 
 
+def network_inputs(net, n, seed):
+    """Seeded descriptor rows around the net's input scaler (x0 ~ N(0, 1)) and
+    a vector over the energies ~ N(0, 1), both float32 [n][w0] and [n][wL]."""
+    rng = np.random.default_rng(seed)
+    w = net["widths"]
+    B = (net["in_mean"] + net["in_std"] * rng.standard_normal((n, w[0]))).astype(np.float32)
+    v = rng.standard_normal((n, w[-1])).astype(np.float32)
+    return B, v
+
+
 BLOB_MAGIC = b"MALANET1"
 
 

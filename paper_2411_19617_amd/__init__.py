@@ -26,7 +26,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 RESULT_BYTES = 64
 STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
-          "density_window", "gauss"]
+          "density_window", "gauss", "mlp_vjp"]
 DENSITY_WINDOW = 0
 DENSITY_RECOMPUTE = 1
 
@@ -85,6 +85,7 @@ def lib():
             ("mala_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p]),
             ("mala_gaussian_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, d, i64, i64, p]),
             ("mala_ldos_infer", [p, p, p, i64, p]),
+            ("mala_ldos_vjp", [p, p, p, p, i64, p]),
             ("mala_integrate", [p, p, i64, d, ctypes.POINTER(EGrid), d, d, p, p, p]),
             ("mala_predict", [p, p, p, i32, ctypes.POINTER(CellGrid), d, i32, ctypes.POINTER(EGrid), d, d,
                               p, p, p, p]),
@@ -259,6 +260,18 @@ class Context:
         if out is None:
             out = torch.empty((n, n_out), dtype=torch.float32, device=self.torch_device)
         _check(lib().mala_ldos_infer(self.handle, weights.handle, _ptr(B), n, _ptr(out)))
+        return out
+
+    def mala_ldos_vjp(self, weights, B, v, out=None):
+        """g = (dd/dB)^T v per point (device float32 [n][w0])."""
+        import torch
+        self._sync_stream()
+        n = int(B.shape[0])
+        if int(v.shape[0]) != n:
+            raise ValueError("B and v hold different point counts")
+        if out is None:
+            out = torch.empty((n, int(B.shape[1])), dtype=torch.float32, device=self.torch_device)
+        _check(lib().mala_ldos_vjp(self.handle, weights.handle, _ptr(B), _ptr(v), n, _ptr(out)))
         return out
 
     def mala_integrate(self, ldos, dV, egrid, T, n_electrons, density=True):

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmala.so")
-SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "gauss.hip", "mlp.hip", "fermi.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "gauss.hip", "mlp.hip", "mlp_vjp.hip",
+           "fermi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -536,6 +536,21 @@ mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32
     pack(W1, h1, n_in, h1t, KS1, P1);
     pack(W2, h2, h1, h2t, KS2, P2);
     pack(W3, n_out, h2, ot, KS3, P3);
+    // transposed weights for the network's vector-Jacobian product (FP32
+    // only): W^T is [in][out] row-major, packed like a layer with the widths
+    // swapped; its K runs over the padded output units of the forward layer
+    auto transpose = [](const std::vector<double>& W, int fout, int fin) {
+        std::vector<double> t((size_t)fin * fout);
+        for (int o = 0; o < fout; ++o)
+            for (int i = 0; i < fin; ++i) t[(size_t)i * fout + o] = W[(size_t)o * fin + i];
+        return t;
+    };
+    std::vector<float> T1, T2, T3;
+    if (!bf) {
+        pack(transpose(W1, h1, n_in), n_in, h1, in_pad / 16, h1t * 16 / KK, T1);
+        pack(transpose(W2, h2, h1), h1, h2, h1t, h2t * 16 / KK, T2);
+        pack(transpose(W3, n_out, h2), h2, n_out, h2t, ot * 16 / KK, T3);
+    }
     auto padv = [](const std::vector<double>& v, int n) {
         std::vector<float> o(n, 0.f);
         for (size_t i = 0; i < v.size() && (int)i < n; ++i) o[i] = (float)v[i];
@@ -578,6 +593,9 @@ mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32
     a.W1 = bf ? upload_bf(P1) : upload_f(P1);
     a.W2 = bf ? upload_bf(P2) : upload_f(P2);
     a.W3 = bf ? upload_bf(P3) : upload_f(P3);
+    a.W1T = bf ? nullptr : upload_f(T1);
+    a.W2T = bf ? nullptr : upload_f(T2);
+    a.W3T = bf ? nullptr : upload_f(T3);
     a.b1 = (const float*)upload_f(pb1);
     a.b2 = (const float*)upload_f(pb2);
     a.b3 = (const float*)upload_f(pb3);
@@ -585,7 +603,7 @@ mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32
     a.in_rstd = (const float*)upload_f(prs);
     a.out_scale = (const float*)upload_f(psc);
     a.out_shift = (const float*)upload_f(psh);
-    if (!a.W1 || !a.W2 || !a.W3 || !a.b1 || !a.b2 || !a.b3 || !a.in_mean || !a.in_rstd || !a.out_scale ||
+    if (!a.W1 || !a.W2 || !a.W3 || (!bf && (!a.W1T || !a.W2T || !a.W3T)) || !a.b1 || !a.b2 || !a.b3 || !a.in_mean || !a.in_rstd || !a.out_scale ||
         !a.out_shift) {
         mala_weights_free(w);
         return fail(MALA_E_OOM, "weight upload failed");
@@ -650,6 +668,20 @@ mala_status mala_ldos_infer(mala_ctx* c, const mala_weights* w, const float* B, 
     o.ldos = ldos_out;
     HIP_TRY(staged(c, MALA_STAGE_MLP_LDOS, n_pts,
                    [&] { return launch_mlp(c->stream, w->args, kModeLdos, B, n_pts, 1, mlp_blocks(n_pts), o); }));
+    return MALA_OK;
+}
+
+mala_status mala_ldos_vjp(mala_ctx* c, const mala_weights* w, const float* B, const float* v, int64_t n_pts,
+                          float* g_out) {
+    if (!c || !w) return fail(MALA_E_INVALID_ARG, "NULL argument");
+    if (w->args.precision != 0) return fail(MALA_E_UNSUPPORTED, "the network VJP needs FP32 weights");
+    if (n_pts < 0) return fail(MALA_E_INVALID_ARG, "n_pts < 0");
+    if (n_pts == 0) return MALA_OK;
+    if (!B || !v || !g_out) return fail(MALA_E_INVALID_ARG, "NULL buffer");
+    if (mlp_vjp_lds_bytes(w->args) > kMlpLdsBudget)
+        return fail(MALA_E_UNSUPPORTED, "network too wide for the VJP kernel's LDS tile");
+    DeviceGuard g(c->device);
+    HIP_TRY(staged(c, MALA_STAGE_MLP_VJP, n_pts, [&] { return launch_mlp_vjp(c->stream, w->args, B, v, n_pts, g_out); }));
     return MALA_OK;
 }
 

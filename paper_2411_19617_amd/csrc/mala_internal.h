@@ -220,6 +220,9 @@ struct MlpArgs {
     const float* in_rstd;        // [n_in] 1/std
     const float* out_scale;      // [out_tiles*16] (zeros in the padding)
     const float* out_shift;
+    const void* W1T;             // transposed weights packed as A operands (FP32 only;
+    const void* W2T;             // null for BF16 weights): [in_pad] x h1, h1 x h2,
+    const void* W3T;             // h2 x [out_tiles*16]
 };
 
 enum MlpMode { kModeLdos = 0, kModeDos = 1, kModeDensity = 2, kModeDosWindow = 3 };
@@ -251,6 +254,9 @@ struct MlpOut {
 };
 
 int mlp_blocks(int64_t n_pts);
+size_t mlp_vjp_lds_bytes(const MlpArgs& a);
+hipError_t launch_mlp_vjp(hipStream_t s, const MlpArgs& a, const float* B, const float* v, int64_t n_pts,
+                          float* g_out);
 hipError_t launch_mlp(hipStream_t s, const MlpArgs& a, int mode, const float* B, int64_t n_pts, int row_stride,
                       int n_blocks, const MlpOut& o);
 

@@ -568,12 +568,7 @@ def test_gaussian_single_atom_closed_form_and_translation():
 
 # ---------------------------------------------------------------- network VJP
 def _vjp_inputs(net, n, seed):
-    """Descriptor rows around the net's input scaler and an energy vector, both
-    float32-representable (the GPU path takes float32)."""
-    rng = np.random.default_rng(seed)
-    w = net["widths"]
-    B = (net["in_mean"] + net["in_std"] * rng.standard_normal((n, w[0]))).astype(np.float32)
-    v = rng.standard_normal((n, w[-1])).astype(np.float32)
+    B, v = mala_synth.network_inputs(net, n, seed)
     return B.astype(np.float64), v.astype(np.float64)
 
 
