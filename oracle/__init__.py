@@ -59,6 +59,13 @@ def lib():
         L.oracle_descriptors.restype = i
         L.oracle_descriptors.argtypes = [p, i, p, p, d, i, p, i64, p, p, i]
         L.oracle_mlp.argtypes = [p, i64, i, p, p, p, p, p, p, p, d, i, p, i]
+        L.oracle_u_adjoint.argtypes = [p, i, p, p]
+        L.oracle_dcayley_klein.argtypes = [d, d, d, d, p, p]
+        L.oracle_dcutoff.restype = d
+        L.oracle_dcutoff.argtypes = [d, d]
+        L.oracle_dwigner_u.argtypes = [i, d, d, d, d, d, d, d, d, p]
+        L.oracle_descriptors_vjp.restype = i
+        L.oracle_descriptors_vjp.argtypes = [p, i, p, p, d, i, p, i64, p, p, i]
         L.oracle_mlp_vjp.argtypes = [p, i64, i, p, p, p, p, p, p, d, i, p, p, p, i]
         L.oracle_dos.argtypes = [p, i64, i, d, p]
         L.oracle_li_neg.restype = d
@@ -176,6 +183,35 @@ def descriptors(snap, points=None, nthreads=0, return_meta=False):
     if return_meta:
         return B, {"max_neighbours": worst, "max_imag": mi.value}
     return B
+
+
+def descriptors_vjp(snap, gB, points=None, nthreads=0):
+    """dL/dR [n_atoms][3] for L = sum_p sum_l gB[p][l] B_l(p) over the grid
+    points `points` (default: all): the descriptor factor of the force
+    expression (Eq. forcesmala) applied to gB [n_pts][n_B]."""
+    if points is None:
+        points = np.arange(snap.n_points, dtype=np.int64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    L = _f64(snap.L)
+    pos = _f64(np.mod(snap.positions, L))
+    N = np.ascontiguousarray(snap.N, dtype=np.int32)
+    gB = _f64(gB)
+    assert gB.shape == (pts.shape[0], lib().oracle_n_triples(snap.twojmax))
+    out = np.zeros((pos.shape[0], 3))
+    if lib().oracle_descriptors_vjp(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N), float(snap.rcut),
+                                    int(snap.twojmax), _ptr(pts), pts.shape[0], _ptr(gB), _ptr(out),
+                                    int(nthreads)) < 0:
+        raise RuntimeError("oracle neighbour list overflow")
+    return out
+
+
+def u_adjoint(u_full, twojmax, gB):
+    """Y = dL/du (Y = dL/dRe u + i dL/dIm u) for L = sum_l gB_l B_l(u), all rows
+    of every level, packed like u_levels' concatenation."""
+    u = _f64(np.stack([np.real(u_full), np.imag(u_full)], -1))
+    Y = np.zeros_like(u)
+    lib().oracle_u_adjoint(_ptr(u), int(twojmax), _ptr(_f64(gB)), _ptr(Y))
+    return Y[..., 0] + 1j * Y[..., 1]
 
 
 def gaussian(snap, sigma, cutoff, points=None, nthreads=0):

@@ -410,6 +410,208 @@ void oracle_mlp(const double *B, int64_t n_pts, int n_layers, const int *widths,
     }
 }
 
+/* ------------------------------------------------------------ descriptor VJP
+ * The descriptor factor of the force expression (Eq. forcesmala): for
+ * weights gB(p) over the n_B components, the gradient of
+ * L = sum_p sum_l gB_l(p) B_l(p) with respect to every atom position.
+ * Chain rule in the order of the definitions:
+ *   B(u) is a sum of triple products Re(conj(x) C C y z) with x = u^j,
+ *   y = u^j1, z = u^j2; with dL = sum Re(conj(Y) du) the product rule gives
+ *   Y_x += g C C y z,  Y_y += g C C x conj(z),  Y_z += g C C x conj(y);
+ *   u^J = I + sum_k fc(r_k) U^J(Delta_k), Delta_k = R_atom(k) + shift - r_p,
+ *   so dL/dR_atom = sum over its images k of
+ *   sum_J sum_{m m'} Re(conj(Y^J_{m m'}) d(fc U^J_{m m'})/dDelta_k).        */
+
+/* Y [size][2] (all rows of every level) for one point's u and weights gB. */
+void oracle_u_adjoint(const double *u, int twojmax, const double *gB, double *Y)
+{
+    int nt = oracle_n_triples(twojmax), size = u_off(twojmax + 1);
+    int *tr = malloc(sizeof(int) * 3 * nt);
+    oracle_triples(twojmax, tr);
+    memset(Y, 0, sizeof(double) * 2 * size);
+    for (int t = 0; t < nt; t++) {
+        int j1 = tr[3 * t], j2 = tr[3 * t + 1], j = tr[3 * t + 2];
+        double g = gB[t];
+        for (int m = -j; m <= j; m += 2)
+            for (int mp = -j; mp <= j; mp += 2) {
+                int ex = u_off(j) + ((j + m) / 2) * (j + 1) + (j + mp) / 2;
+                cplx x = u[2 * ex] + I * u[2 * ex + 1];
+                for (int m1 = -j1; m1 <= j1; m1 += 2) {
+                    int m2 = m - m1;
+                    if (m2 < -j2 || m2 > j2) continue;
+                    double c1 = oracle_cg(j1, m1, j2, m2, j, m);
+                    for (int m1p = -j1; m1p <= j1; m1p += 2) {
+                        int m2p = mp - m1p;
+                        if (m2p < -j2 || m2p > j2) continue;
+                        double c = g * c1 * oracle_cg(j1, m1p, j2, m2p, j, mp);
+                        int ey = u_off(j1) + ((j1 + m1) / 2) * (j1 + 1) + (j1 + m1p) / 2;
+                        int ez = u_off(j2) + ((j2 + m2) / 2) * (j2 + 1) + (j2 + m2p) / 2;
+                        cplx y = u[2 * ey] + I * u[2 * ey + 1], z = u[2 * ez] + I * u[2 * ez + 1];
+                        cplx yx = c * y * z, yy = c * x * conj(z), yz = c * x * conj(y);
+                        Y[2 * ex] += creal(yx); Y[2 * ex + 1] += cimag(yx);
+                        Y[2 * ey] += creal(yy); Y[2 * ey + 1] += cimag(yy);
+                        Y[2 * ez] += creal(yz); Y[2 * ez + 1] += cimag(yz);
+                    }
+                }
+            }
+    }
+    free(tr);
+}
+
+/* d a / d Delta_d and d b / d Delta_d (complex, d = x, y, z) of the
+ * Cayley-Klein parameters of oracle_cayley_klein: with theta = k r,
+ * k = rfac0 pi / rcut, n = Delta / r, dr/dDelta_d = n_d,
+ * dn_i/dDelta_d = (delta_id - n_i n_d) / r:
+ *   a = cos theta - i n_z sin theta,  b = -sin theta (n_y + i n_x).       */
+void oracle_dcayley_klein(double dx, double dy, double dz, double rcut, double *da /* [3][2] */,
+                          double *db /* [3][2] */)
+{
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double n[3] = {dx / r, dy / r, dz / r};
+    double k = OR_RFAC0 * OR_PI / rcut, th = k * r, c = cos(th), s = sin(th);
+    for (int d = 0; d < 3; d++) {
+        double dth = k * n[d];
+        double dn[3];
+        for (int i = 0; i < 3; i++) dn[i] = ((i == d ? 1.0 : 0.0) - n[i] * n[d]) / r;
+        cplx dA = -s * dth - I * (dn[2] * s + n[2] * c * dth);
+        cplx dB = -c * dth * (n[1] + I * n[0]) - s * (dn[1] + I * dn[0]);
+        da[2 * d] = creal(dA); da[2 * d + 1] = cimag(dA);
+        db[2 * d] = creal(dB); db[2 * d + 1] = cimag(dB);
+    }
+}
+
+/* d fc / d r of oracle_cutoff (0 at and past rcut). */
+double oracle_dcutoff(double r, double rcut)
+{
+    if (r >= rcut) return 0.0;
+    return -0.5 * OR_PI / rcut * sin(OR_PI * r / rcut);
+}
+
+/* dU^J along one direction, given the parameters (a, b) and their
+ * derivatives (da, db) in that direction: the product rule applied to each
+ * monomial a^s (-conj b)^(ma-s) b^t (conj a)^(J-ma-t) of oracle_wigner_u.  */
+void oracle_dwigner_u(int J, double a_re, double a_im, double b_re, double b_im, double da_re,
+                      double da_im, double db_re, double db_im, double *out /* [(J+1)^2][2] */)
+{
+    cplx a = a_re + I * a_im, b = b_re + I * b_im, da = da_re + I * da_im, db = db_re + I * db_im;
+    cplx mbc = -conj(b), ac = conj(a), dmbc = -conj(db), dac = conj(da);
+    for (int ma = 0; ma <= J; ma++)
+        for (int mb = 0; mb <= J; mb++) {
+            cplx coef = 0.0;
+            for (int s = 0; s <= ma; s++) {
+                int t = mb - s;
+                if (t < 0 || t > J - ma) continue;
+                int p1 = s, p2 = ma - s, p3 = t, p4 = J - ma - t;
+                cplx f1 = cpow_int(a, p1), f2 = cpow_int(mbc, p2), f3 = cpow_int(b, p3), f4 = cpow_int(ac, p4);
+                cplx d = 0.0;
+                if (p1 > 0) d += p1 * cpow_int(a, p1 - 1) * da * f2 * f3 * f4;
+                if (p2 > 0) d += f1 * p2 * cpow_int(mbc, p2 - 1) * dmbc * f3 * f4;
+                if (p3 > 0) d += f1 * f2 * p3 * cpow_int(b, p3 - 1) * db * f4;
+                if (p4 > 0) d += f1 * f2 * f3 * p4 * cpow_int(ac, p4 - 1) * dac;
+                coef += binom(ma, s) * binom(J - ma, t) * d;
+            }
+            double norm = sqrt(fact(mb) * fact(J - mb) / (fact(ma) * fact(J - ma)));
+            out[2 * (ma * (J + 1) + mb)] = creal(coef * norm);
+            out[2 * (ma * (J + 1) + mb) + 1] = cimag(coef * norm);
+        }
+}
+
+/* dL/dR [n_atoms][3] for L = sum over the listed grid points p of
+ * sum_l gB[p][l] B_l(p) (gB is [n_pts][n_triples]).  Per-thread partial
+ * sums are added in thread order at the end.                              */
+int oracle_descriptors_vjp(const double *pos, int n_atoms, const double *L, const int *N,
+                           double rcut, int twojmax, const int64_t *pts, int64_t n_pts,
+                           const double *gB, double *dLdR, int nthreads)
+{
+    const int max_nbr = 4096;
+    int nt = oracle_n_triples(twojmax), usz = oracle_u_size(twojmax);
+    int nmax[3];
+    for (int d = 0; d < 3; d++) nmax[d] = (int)ceil(rcut / L[d]) + 1;
+    int nthr = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nthr = omp_get_max_threads();
+#endif
+    double *part = calloc((size_t)nthr * n_atoms * 3, sizeof(double));
+    int overflow = 0;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = part + (size_t)tid * n_atoms * 3;
+        double *disp = malloc(sizeof(double) * 3 * max_nbr);
+        int *atom = malloc(sizeof(int) * max_nbr);
+        double *u = malloc(sizeof(double) * 2 * usz), *Y = malloc(sizeof(double) * 2 * usz);
+        int w = twojmax + 1;
+        double *U = malloc(sizeof(double) * 2 * w * w), *dU = malloc(sizeof(double) * 2 * w * w);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+        for (int64_t q = 0; q < n_pts; q++) {
+            double r[3];
+            grid_point(N, L, pts[q], r);
+            int cnt = 0;
+            for (int a = 0; a < n_atoms; a++)
+                for (int nx = -nmax[0]; nx <= nmax[0]; nx++)
+                    for (int ny = -nmax[1]; ny <= nmax[1]; ny++)
+                        for (int nz = -nmax[2]; nz <= nmax[2]; nz++) {
+                            double dx = pos[3 * a] + nx * L[0] - r[0];
+                            double dy = pos[3 * a + 1] + ny * L[1] - r[1];
+                            double dz = pos[3 * a + 2] + nz * L[2] - r[2];
+                            if (dx * dx + dy * dy + dz * dz < rcut * rcut) {
+                                if (cnt < max_nbr) {
+                                    disp[3 * cnt] = dx; disp[3 * cnt + 1] = dy; disp[3 * cnt + 2] = dz;
+                                    atom[cnt] = a;
+                                }
+                                cnt++;
+                            }
+                        }
+            if (cnt > max_nbr) {
+                overflow = 1;
+                continue;
+            }
+            oracle_ui(disp, cnt, rcut, twojmax, u);
+            oracle_u_adjoint(u, twojmax, gB + q * nt, Y);
+            for (int k = 0; k < cnt; k++) {
+                double dx = disp[3 * k], dy = disp[3 * k + 1], dz = disp[3 * k + 2];
+                double rr = sqrt(dx * dx + dy * dy + dz * dz);
+                if (rr == 0.0) continue;          /* an atom on the point: u gets +I, no direction */
+                double fc = oracle_cutoff(rr, rcut), dfc = oracle_dcutoff(rr, rcut);
+                double ar, ai, br, bi, da[6], db[6];
+                oracle_cayley_klein(dx, dy, dz, rcut, &ar, &ai, &br, &bi);
+                oracle_dcayley_klein(dx, dy, dz, rcut, da, db);
+                double nrm[3] = {dx / rr, dy / rr, dz / rr};
+                for (int J = 0; J <= twojmax; J++) {
+                    int o = u_off(J), ne = (J + 1) * (J + 1);
+                    oracle_wigner_u(J, ar, ai, br, bi, U);
+                    for (int d = 0; d < 3; d++) {
+                        oracle_dwigner_u(J, ar, ai, br, bi, da[2 * d], da[2 * d + 1], db[2 * d], db[2 * d + 1], dU);
+                        double s = 0.0;
+                        for (int e = 0; e < ne; e++) {
+                            double vr = dfc * nrm[d] * U[2 * e] + fc * dU[2 * e];
+                            double vi = dfc * nrm[d] * U[2 * e + 1] + fc * dU[2 * e + 1];
+                            s += Y[2 * (o + e)] * vr + Y[2 * (o + e) + 1] * vi;   /* Re(conj(Y) v) */
+                        }
+                        acc[3 * atom[k] + d] += s;
+                    }
+                }
+            }
+        }
+        free(disp); free(atom); free(u); free(Y); free(U); free(dU);
+    }
+    for (int i = 0; i < n_atoms * 3; i++) {
+        double s = 0.0;
+        for (int t = 0; t < nthr; t++) s += part[(size_t)t * n_atoms * 3 + i];
+        dLdR[i] = s;
+    }
+    free(part);
+    return overflow ? -1 : 0;
+}
+
 /* ------------------------------------------------------------ network VJP
  * The middle factor of the force expression (Eq. forcesmala): for a vector
  * v(p) over the energies, g(p) = (dd(p)/dB(p))^T v(p), by backpropagation
