@@ -324,6 +324,49 @@ def network_vjp_bench(ctx, mala, snap, net, torch, reps=5):
             "precision": "f32"}
 
 
+def adjoint_z_terms(tj):
+    """Z terms of the descriptor adjoint: for every coupled pair (A >= B) and
+    output level C, the half rows ma <= C/2 of Z^C(A, B) over all columns,
+    each a sum over (ma1, mb1) with both coupled indices in range."""
+    tot = 0
+    for C in range(tj + 1):
+        for A in range(tj + 1):
+            for B in range(A + 1):
+                if not (A - B <= C <= A + B and (A + B + C) % 2 == 0):
+                    continue
+                D = (A + B - C) // 2
+                rows = sum(1 for ma in range(C // 2 + 1) for ma1 in range(A + 1) if 0 <= ma - ma1 + D <= B)
+                cols = sum(1 for mb in range(C + 1) for mb1 in range(A + 1) if 0 <= mb - mb1 + D <= B)
+                tot += rows * cols
+    return tot
+
+
+def descriptor_adjoint_bench(ctx, snap, torch, reps=3):
+    """Descriptor vector-Jacobian product (descriptor factor of the force
+    expression) over the whole grid with seeded weights, outside the metric's
+    step: time per grid, per stage (u again, dL/du, dL/dR), and the dL/du
+    contraction's rate at 10 flop per Z term."""
+    n, nb = snap.n_points, 91
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(23)
+    gB = torch.randn((n, nb), generator=gen, device="cuda", dtype=torch.float32)
+    out = ctx.mala_descriptors_vjp(snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, gB)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_descriptors_vjp(snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, gB, out=out)
+    p = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    st = {k: p[k][0] / reps for k in ("bin", "ui", "adj_y", "adj_dedr")}
+    ms = sum(st.values())
+    zt = adjoint_z_terms(snap.twojmax)
+    tf_y = 10.0 * zt * n / (st["adj_y"] * 1e-3) / 1e12
+    del gB, out
+    return {"ms_per_grid": ms, "points_per_s": n / (ms * 1e-3), "stages_ms": st,
+            "adj_y": {"flops_per_point": 10.0 * zt, "tflops": tf_y, "peak": PEAK_FP32_VALU_TFLOPS,
+                      "frac": tf_y / PEAK_FP32_VALU_TFLOPS}}
+
+
 def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5, loads=(0.5, 0.7, 0.9)):
     """Poisson streams of the serving mix through the library's request loop.
 
@@ -492,6 +535,7 @@ def main():
     }
     out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
     out["network_vjp"] = network_vjp_bench(ctx, mala, snap, net, torch)
+    out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, snap, torch)
     if a.serve_requests > 0:
         out["serving"] = serving_bench(mala, prec, a.serve_requests)
         out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]

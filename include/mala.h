@@ -139,6 +139,24 @@ mala_status mala_descriptors(mala_ctx* ctx, const double* positions, int32_t n_a
                              const mala_cell_grid* cg, double rcut, int32_t twojmax,
                              int64_t pt_begin, int64_t pt_end, float* B_out);
 
+/* Vector-Jacobian product of the descriptors: the descriptor factor of the
+ * force expression (Eq. forcesmala) applied to weights gB over the
+ * components, i.e. the gradient of L = sum_p sum_l gB[p][l] B_l(p) over the
+ * grid points p in [pt_begin, pt_end) with respect to every atom position
+ * (the force contribution is its negative):
+ *   dLdR_out[a][d] = dL / dR_{a,d}, summed over every periodic image.
+ *  positions, cg, rcut, twojmax as for mala_descriptors;
+ *  gB: device float32 [pt_end - pt_begin][n_B] (row = point);
+ *  dLdR_out: device float64 [n_atoms][3] (caller-owned), overwritten.
+ * An atom sitting exactly on a grid point is left out of that point's
+ * gradient (the descriptors have no derivative there).  The per-atom sums
+ * are FP64 atomic additions whose order is not fixed, so repeated calls can
+ * differ in the last bits.  An empty range writes zeros.  Capacity overflows
+ * are reported by mala_check_device_errors as for mala_descriptors.        */
+mala_status mala_descriptors_vjp(mala_ctx* ctx, const double* positions, int32_t n_atoms,
+                                 const mala_cell_grid* cg, double rcut, int32_t twojmax,
+                                 int64_t pt_begin, int64_t pt_end, const float* gB, double* dLdR_out);
+
 /* Gaussian descriptors of grid points [pt_begin, pt_end): the Gaussian
  * representation of the ionic positions behind the structure factor
  * (Eq. structurefactor_gaussian), a Gaussian of width sigma normalised to
@@ -276,7 +294,9 @@ mala_status mala_server_destroy(mala_server* s);
 #define MALA_STAGE_DENSITY_WINDOW 9 /* density from the stored energy window */
 #define MALA_STAGE_GAUSS 10       /* Gaussian descriptors                    */
 #define MALA_STAGE_MLP_VJP 11     /* network vector-Jacobian product         */
-#define MALA_N_STAGES 12
+#define MALA_STAGE_ADJ_Y 12       /* descriptor adjoint: dL/du               */
+#define MALA_STAGE_ADJ_DEDR 13    /* descriptor adjoint: dL/dR               */
+#define MALA_N_STAGES 14
 mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
 mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
 

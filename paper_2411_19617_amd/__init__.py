@@ -26,7 +26,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 RESULT_BYTES = 64
 STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
-          "density_window", "gauss", "mlp_vjp"]
+          "density_window", "gauss", "mlp_vjp", "adj_y", "adj_dedr"]
 DENSITY_WINDOW = 0
 DENSITY_RECOMPUTE = 1
 
@@ -83,6 +83,7 @@ def lib():
             ("mala_weights_load", [p, p, sz, i32, ctypes.POINTER(p)]),
             ("mala_weights_free", [p]),
             ("mala_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p]),
+            ("mala_descriptors_vjp", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p, p]),
             ("mala_gaussian_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, d, i64, i64, p]),
             ("mala_ldos_infer", [p, p, p, i64, p]),
             ("mala_ldos_vjp", [p, p, p, p, i64, p]),
@@ -238,6 +239,22 @@ class Context:
         cg = _cell_grid(L, N)
         _check(lib().mala_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(twojmax),
                                       int(pt_begin), int(pt_end), _ptr(out)))
+        return out
+
+    def mala_descriptors_vjp(self, positions, L, N, rcut, twojmax, gB, pt_begin=0, pt_end=None, out=None):
+        """dL/dR [n_atoms][3] (device float64) for L = sum_p gB[p] . B(p)."""
+        import torch
+        self._sync_stream()
+        pos, pp, n_at = _positions(positions)
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        pt_end = ntot if pt_end is None else int(pt_end)
+        if int(gB.shape[0]) != max(pt_end - pt_begin, 0) or int(gB.shape[1]) != n_descriptors(twojmax):
+            raise ValueError("gB must be [pt_end - pt_begin][n_B]")
+        if out is None:
+            out = torch.empty((n_at, 3), dtype=torch.float64, device=self.torch_device)
+        cg = _cell_grid(L, N)
+        _check(lib().mala_descriptors_vjp(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(twojmax),
+                                          int(pt_begin), int(pt_end), _ptr(gB), _ptr(out)))
         return out
 
     def mala_gaussian_descriptors(self, positions, L, N, sigma, cutoff, pt_begin=0, pt_end=None, out=None):

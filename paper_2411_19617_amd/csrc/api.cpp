@@ -74,6 +74,10 @@ struct TjTables {
     int* cg_off = nullptr;
     int* waves = nullptr;
     int zb_waves = 0;
+    bool adj_ready = false;      // descriptor adjoint: coupled-pair CG blocks, wave unit plan
+    float* cgy = nullptr;
+    int* cgy_off = nullptr;
+    int* yunits = nullptr;
 };
 
 constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
@@ -90,6 +94,7 @@ struct mala_ctx {
     DevBuf<int> cell_count, cell_start, cell_fill, atom_cell;
     DevBuf<double4> atoms_tmp, atoms_sorted;
     DevBuf<float2> u;
+    DevBuf<float2> yadj;                 // dL/du of the descriptor adjoint, laid out like u
     DevBuf<float> Bbuf;
     DevBuf<double> partials, est_partials;
     DevBuf<double> fermi_w;
@@ -187,6 +192,26 @@ mala_status ensure_tables(mala_ctx* c, int tj) {
     HIP_TRY(hipMemcpy(t.cg_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(t.waves, waves.data(), sizeof(int) * waves.size(), hipMemcpyHostToDevice));
     t.ready = true;
+    return MALA_OK;
+}
+
+mala_status ensure_adjoint_tables(mala_ctx* c, int tj) {
+    TjTables& t = c->tj[tj];
+    if (t.adj_ready) return MALA_OK;
+    std::vector<float> tab(65536);
+    std::vector<int> off(n_combos(tj));
+    const int n = build_cg_table_adjoint(tj, tab.data(), off.data(), (int)tab.size());
+    if (n < 0) return fail(MALA_E_UNSUPPORTED, "Clebsch-Gordan table of the adjoint too large");
+    const int nw = y_waves();
+    std::vector<int> units(nw * kMaxYStride, 0);
+    plan_y_units(tj, nw, units.data(), kMaxYStride);
+    HIP_TRY(hipMalloc(&t.cgy, sizeof(float) * (n > 0 ? n : 1)));
+    HIP_TRY(hipMalloc(&t.cgy_off, sizeof(int) * off.size()));
+    HIP_TRY(hipMalloc(&t.yunits, sizeof(int) * units.size()));
+    HIP_TRY(hipMemcpy(t.cgy, tab.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.cgy_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.yunits, units.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice));
+    t.adj_ready = true;
     return MALA_OK;
 }
 
@@ -303,6 +328,7 @@ void ctx_trim(mala_ctx* c) {
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     release(c->u);
+    release(c->yadj);
     release(c->Bbuf);
     release(c->window);
     release(c->prefix);
@@ -379,6 +405,9 @@ mala_status mala_destroy(mala_ctx* c) {
         if (t.cg) (void)hipFree(t.cg);
         if (t.cg_off) (void)hipFree(t.cg_off);
         if (t.waves) (void)hipFree(t.waves);
+        if (t.cgy) (void)hipFree(t.cgy);
+        if (t.cgy_off) (void)hipFree(t.cgy_off);
+        if (t.yunits) (void)hipFree(t.yunits);
     }
     if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
     for (auto& r : c->prof_pending) {
@@ -635,6 +664,46 @@ mala_status mala_descriptors(mala_ctx* c, const double* positions, int32_t n_ato
     if ((st = ensure_tables(c, twojmax))) return st;
     if ((st = upload_positions(c, positions, n_atoms))) return st;
     return run_descriptors(c, n_atoms, cg, rcut, twojmax, pt_begin, pt_end, B_out);
+}
+
+mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
+                                 double rcut, int32_t twojmax, int64_t pt_begin, int64_t pt_end, const float* gB,
+                                 double* dLdR_out) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    mala_status st = check_geometry(positions, n_atoms, cg, rcut, twojmax);
+    if (st) return st;
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    if (pt_begin < 0 || pt_end < pt_begin || pt_end > ntot) return fail(MALA_E_INVALID_ARG, "bad point range");
+    if (n_atoms == 0) return MALA_OK;
+    if (!dLdR_out) return fail(MALA_E_INVALID_ARG, "dLdR_out is NULL");
+    if (pt_end > pt_begin && !gB) return fail(MALA_E_INVALID_ARG, "gB is NULL");
+    DeviceGuard g(c->device);
+    HIP_TRY(launch_zero_f64(c->stream, dLdR_out, (int64_t)3 * n_atoms));
+    if (pt_end == pt_begin) return MALA_OK;
+    if ((st = ensure_adjoint_tables(c, twojmax))) return st;
+    if ((st = upload_positions(c, positions, n_atoms))) return st;
+    BinState bs{};
+    if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
+    const int nB = n_triples(twojmax);
+    const int64_t total = pt_end - pt_begin;
+    const int64_t chunk = total < kChunk ? total : kChunk;
+    const int64_t tiles = (chunk + kTile - 1) / kTile;
+    HIP_TRY(ensure(c->u, (size_t)tiles * n_half(twojmax) * kTile));
+    HIP_TRY(ensure(c->yadj, (size_t)tiles * n_half(twojmax) * kTile));
+    const TjTables& t = c->tj[twojmax];
+    for (int64_t off = 0; off < total; off += chunk) {
+        const int64_t n = (total - off) < chunk ? (total - off) : chunk;
+        HIP_TRY(staged(c, MALA_STAGE_UI, n, [&] {
+            return launch_ui(c->stream, twojmax, bs, cg->N, rcut, pt_begin + off, n, c->u.p, c->err);
+        }));
+        HIP_TRY(staged(c, MALA_STAGE_ADJ_Y, n, [&] {
+            return launch_yi(c->stream, twojmax, n, c->u.p, gB + off * nB, c->yadj.p, t.cgy, t.cgy_off, t.yunits);
+        }));
+        HIP_TRY(staged(c, MALA_STAGE_ADJ_DEDR, n, [&] {
+            return launch_dedr(c->stream, twojmax, bs, cg->N, rcut, pt_begin + off, n, c->yadj.p, dLdR_out, c->err);
+        }));
+    }
+    return MALA_OK;
 }
 
 mala_status mala_gaussian_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms,

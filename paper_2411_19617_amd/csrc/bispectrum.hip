@@ -29,67 +29,10 @@
 //           each exchanged pair of rows is formed.  Clebsch-Gordan values of
 //           the coupling come from a per-triple table in global memory read
 //           with wave-uniform (scalar) loads.
+#include "snap_core.h"
 #include "tile_gather.h"
 
 namespace mala {
-
-__host__ __device__ constexpr double ce_sqrt(double x) {
-    if (x <= 0.0) return 0.0;
-    double r = x > 1.0 ? x : 1.0;
-    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
-    return r;
-}
-
-// ------------------------------------------------------------------ chains
-// Chain q: rows k = 0..min(q, TJ-q) at level J = q + k, row index ma = k.
-__host__ __device__ constexpr int chain_rows(int tj, int q) { return (q < tj - q ? q : tj - q) + 1; }
-__host__ __device__ constexpr int chain_len(int tj, int q) {
-    int n = 0;
-    for (int k = 0; k < chain_rows(tj, q); ++k) n += q + k + 1;
-    return n;
-}
-// Chains are split over four waves at twojmax 8 and 10 (operation counts
-// balanced to within 4%, at most 75 complex accumulators per wave, and
-// power tables small enough that every wave keeps its share in VGPRs with
-// two waves per SIMD); one wave below that.
-__host__ __device__ constexpr int n_groups(int tj) { return tj >= 8 ? 4 : 1; }
-__host__ __device__ constexpr bool in_group(int tj, int g, int q) {
-    if (tj == 10) return g == 0 ? (q == 0 || q == 5 || q == 10)
-                       : g == 1 ? (q == 1 || q == 2 || q == 3 || q == 4)
-                       : g == 2 ? (q == 6 || q == 9)
-                                : (q == 7 || q == 8);
-    if (tj == 8) return g == 0 ? (q <= 3) : g == 1 ? (q == 4) : g == 2 ? (q == 5 || q == 8) : (q == 6 || q == 7);
-    return g == 0;
-}
-__host__ __device__ constexpr int group_size(int tj, int g) {
-    int n = 0;
-    for (int q = 0; q <= tj; ++q)
-        if (in_group(tj, g, q)) n += chain_len(tj, q);
-    return n;
-}
-__host__ __device__ constexpr int group_qmax(int tj, int g) {
-    int m = 0;
-    for (int q = 0; q <= tj; ++q)
-        if (in_group(tj, g, q)) m = q;
-    return m;
-}
-__host__ __device__ constexpr int chain_slot(int tj, int g, int q) {
-    int n = 0;
-    for (int p = 0; p < q; ++p)
-        if (in_group(tj, g, p)) n += chain_len(tj, p);
-    return n;
-}
-__host__ __device__ constexpr int row_slot(int q, int k) {
-    int n = 0;
-    for (int i = 0; i < k; ++i) n += q + i + 1;
-    return n;
-}
-
-__host__ __device__ constexpr double ce_binom(int n, int k) {
-    double r = 1.0;
-    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
-    return r;
-}
 
 // Accumulate f_c * c(g) of one neighbour into the group's registers, where
 // c^J[ma][mb] is the coefficient of xi^mb eta^(J-mb) in
@@ -201,12 +144,6 @@ __device__ __forceinline__ void ui_neighbour(float ar, float ai, float br, float
     });
 }
 
-__host__ __device__ constexpr double ce_fact(int n) {
-    double f = 1.0;
-    for (int i = 2; i <= n; ++i) f *= i;
-    return f;
-}
-
 template <int TJ>
 __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int Nx, int Ny, int Nz,
                                                           double rcut, int64_t pt_begin, int64_t n_pts,
@@ -313,30 +250,6 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
 }
 
 // ------------------------------------------------------------------ Z / B
-// x * (-1)^k for wave-uniform x and k, as a sign-bit flip on the scalar unit
-__device__ __forceinline__ float flip_odd(float x, int k) {
-    return __int_as_float(__float_as_int(x) ^ (int)((unsigned)(k & 1) << 31));
-}
-
-// Number of (ma, ma1) row pairs of a triple (rows ma <= J/2), their index,
-// and which rows of u^{J1} and u^{J2} they use.
-__host__ __device__ constexpr int zb_pairs(int J1, int J2, int J) {
-    int n = 0;
-    for (int ma = 0; ma <= J / 2; ++ma)
-        for (int ma1 = 0; ma1 <= J1; ++ma1)
-            if (zb_pair_ok(J1, J2, J, ma, ma1)) ++n;
-    return n;
-}
-__host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, int ma1) {
-    int n = 0;
-    for (int a = 0; a <= J / 2; ++a)
-        for (int a1 = 0; a1 <= J1; ++a1)
-            if (zb_pair_ok(J1, J2, J, a, a1)) {
-                if (a == ma && a1 == ma1) return n;
-                ++n;
-            }
-    return -1;
-}
 // B(j1,j2,j) of the lane's point.  For each output column mb:
 //   T[ma][ma1] = sum_mb1 C(mb1,mb) u1[ma1][mb1] u2[ma-ma1+D][mb-mb1+D]
 // (the CG factor scales the column of whichever level has fewer rows to

@@ -18,6 +18,7 @@ constexpr int kMaxCand = 1024;       // candidate atom images per tile
 constexpr int kMaxNbr = 128;         // neighbours per grid point
 constexpr int kMlpBlocks = 256;      // fixed block count of the network kernels (one per CU; deterministic partials)
 constexpr int kMaxZbStride = 64;     // per-wave triple list stride (count + indices)
+constexpr int kMaxYStride = 64;      // per-wave unit list stride of the descriptor adjoint
 constexpr int kMlpMaxIn = 128;       // padded input width limit
 constexpr int kMlpMaxHidden = 512;   // hidden width limit
 constexpr int kMlpMaxOut = 256;      // output width limit
@@ -64,6 +65,65 @@ __host__ __device__ constexpr Triple triple_of(int tj, int idx) {
                     ++n;
                 }
     return Triple{0, 0, 0};
+}
+
+// Index of a descriptor triple (j1 >= j2, j >= j1) in output order.
+__host__ __device__ constexpr int triple_index(int tj, int j1, int j2, int j) {
+    int n = 0;
+    for (int a = 0; a <= tj; ++a)
+        for (int b = 0; b <= a; ++b)
+            for (int c = a - b; c <= a + b && c <= tj; c += 2)
+                if (c >= a) {
+                    if (a == j1 && b == j2 && c == j) return n;
+                    ++n;
+                }
+    return -1;
+}
+
+// The derivative of sum_l g_l B_l with respect to u^C is a sum of Z^C(A, B)
+// over coupled pairs A >= B: every (A, B, C) with |A-B| <= C <= A+B,
+// A+B+C even (levels <= tj), ordered by C, then A, then B.  Its descriptor
+// triple is the sorted {A, B, C} (j = largest, j1 = middle, j2 = smallest)
+// and its weight mult * (j+1)/(C+1) counts the slots of that triple that
+// hold level C (each such slot leaves exactly {A, B}); a slot holding the
+// middle or smallest level enters through the identity
+// B(j1,j2,j) = (j+1)/(j1+1) I(j, j2 -> j1) = (j+1)/(j2+1) I(j, j1 -> j2).
+struct Combo {
+    int a, b, c;      // coupled levels a >= b, output level c
+    int triple;       // descriptor triple of {a, b, c}
+    int mult;         // slots of that triple holding level c
+    int jmax;
+};
+__host__ __device__ constexpr int n_combos(int tj) {
+    int n = 0;
+    for (int c = 0; c <= tj; ++c)
+        for (int a = 0; a <= tj; ++a)
+            for (int b = 0; b <= a; ++b)
+                if (a - b <= c && c <= a + b && (a + b + c) % 2 == 0) ++n;
+    return n;
+}
+__host__ __device__ constexpr Combo combo_of(int tj, int idx) {
+    int n = 0;
+    for (int c = 0; c <= tj; ++c)
+        for (int a = 0; a <= tj; ++a)
+            for (int b = 0; b <= a; ++b)
+                if (a - b <= c && c <= a + b && (a + b + c) % 2 == 0) {
+                    if (n == idx) {
+                        const int hi = a > c ? a : c;                    // a >= b
+                        const int lo = b < c ? b : c;
+                        const int mid = a + b + c - hi - lo;
+                        const int mult = (a == c) + (b == c) + 1;
+                        return Combo{a, b, c, triple_index(tj, mid, lo, hi), mult, hi};
+                    }
+                    ++n;
+                }
+    return Combo{0, 0, 0, -1, 0, 0};
+}
+__host__ __device__ constexpr int combo_first(int tj, int c) {     // first combo of output level c
+    int n = 0;
+    for (int i = 0; i < n_combos(tj); ++i)
+        if (combo_of(tj, i).c < c) ++n;
+    return n;
 }
 
 // Pairs (row ma of the output level, row ma1 of level A) of the Z/B
@@ -282,6 +342,14 @@ void ctx_trim(mala_ctx* c);
 
 // Host-side tables.
 int build_cg_table(int twojmax, float* table, int* offsets, int cap);
+int build_cg_table_adjoint(int twojmax, float* table, int* offsets, int cap);
+int y_waves();
+hipError_t launch_zero_f64(hipStream_t s, double* p, int64_t n);
+hipError_t launch_yi(hipStream_t s, int twojmax, int64_t n_pts, const float2* u, const float* gB, float2* y,
+                     const float* cg_tab, const int* cg_off, const int* wave_units);
+hipError_t launch_dedr(hipStream_t s, int twojmax, const BinState& bins, const int N[3], double rcut,
+                       int64_t pt_begin, int64_t n_pts, const float2* y, double* dLdR, int* err);
+void plan_y_units(int twojmax, int n_waves, int* wave_units, int stride);
 void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride);
 constexpr int kLiTerms = 32;
 constexpr int kLiPow = 64;

@@ -117,6 +117,76 @@ int build_cg_table(int twojmax, float* table, int* offsets, int cap) {
     return n;
 }
 
+// The same blocks for every coupled pair (A, B -> C) of the descriptor
+// adjoint (combo_of order).
+int build_cg_table_adjoint(int twojmax, float* table, int* offsets, int cap) {
+    int n = 0;
+    std::vector<Coupling> cache((twojmax + 1) * (twojmax + 1));
+    std::vector<bool> have(cache.size(), false);
+    for (int k = 0; k < n_combos(twojmax); ++k) {
+        const Combo cb = combo_of(twojmax, k);
+        const int A = cb.a, B = cb.b, C = cb.c;
+        const int key = A * (twojmax + 1) + B;
+        if (!have[key]) {
+            cache[key] = couple(A, B);
+            have[key] = true;
+        }
+        const Coupling& c = cache[key];
+        const int D = (A + B - C) / 2;
+        offsets[k] = n;
+        const int sz = (A + 1) * (C + 1);
+        if (n + sz > cap) return -1;
+        for (int ma1 = 0; ma1 <= A; ++ma1)
+            for (int ma = 0; ma <= C; ++ma) {
+                const int ma2 = ma - ma1 + D;
+                double v = 0.0;
+                if (ma2 >= 0 && ma2 <= B) v = c.vec[D][ma][pidx(B, ma1, ma2)];
+                table[n + ma1 * (C + 1) + ma] = (float)v;
+            }
+        n += sz;
+    }
+    return n;
+}
+
+// Work units of the adjoint contraction: output level C and column mb, each
+// summing Z^C(A, B)[., mb] over the coupled pairs of C.  Assigned to the
+// waves of a block by longest processing time; wave_units[w*stride] = count,
+// followed by the units (C * 32 + mb).
+void plan_y_units(int twojmax, int n_waves, int* wave_units, int stride) {
+    std::vector<std::pair<double, int>> jobs;
+    for (int C = 0; C <= twojmax; ++C)
+        for (int mb = 0; mb <= C; ++mb) {
+            double cost = 0.0;
+            for (int k = combo_first(twojmax, C); k < n_combos(twojmax) && combo_of(twojmax, k).c == C; ++k) {
+                const Combo cb = combo_of(twojmax, k);
+                const int A = cb.a, B = cb.b, D = (A + B - C) / 2, HR = C / 2;
+                int t = 0;
+                for (int ma = 0; ma <= HR; ++ma)
+                    for (int ma1 = 0; ma1 <= A; ++ma1)
+                        if (zb_pair_ok(A, B, C, ma, ma1) && (C % 2 || ma < HR || mb <= HR)) ++t;
+                const int lo = mb + D - B > 0 ? mb + D - B : 0, hi = A < mb + D ? A : mb + D;
+                const int s1 = zb_scale_ops(A, B, C, 1), s2 = zb_scale_ops(A, B, C, 2);
+                cost += (hi - lo + 1) * (4.0 * t + (s1 < s2 ? s1 : s2) + 6.0) + 2.0 * t + 4.0;
+            }
+            jobs.push_back({cost, C * 32 + mb});
+        }
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                         return a.first > b.first;
+                     });
+    std::vector<double> load(n_waves, 0.0);
+    std::vector<std::vector<int>> lists(n_waves);
+    for (auto& jb : jobs) {
+        int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[w] += jb.first;
+        lists[w].push_back(jb.second);
+    }
+    for (int w = 0; w < n_waves; ++w) {
+        wave_units[w * stride] = (int)lists[w].size();
+        for (size_t i = 0; i < lists[w].size(); ++i) wave_units[w * stride + 1 + i] = lists[w][i];
+    }
+}
+
 // Longest-processing-time assignment of triples to the waves of a block.
 // wave_triples[w*stride] = count, followed by the triple indices.
 void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride) {

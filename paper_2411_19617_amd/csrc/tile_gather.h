@@ -44,7 +44,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total)
 // Candidate atom images of a tile whose bounding box is [lo, hi]: every image
 // in the cells overlapping the box grown by rcut that lies within rcut of the
 // box, in a fixed order (cells in index order, atoms in cell order), stored
-// relative to the origin o as float4 in cand[0 .. cap).  Called by the whole
+// relative to the origin o as float4 in cand[0 .. cap) (w holds the bits of
+// the atom's index).  Called by the whole
 // block; returns the total count, which exceeds cap when the list overflowed
 // (only the first cap are stored).  scan_tmp holds blockDim/64 ints.
 __device__ __forceinline__ int gather_candidates(const BinState& bins, const double lo[3], const double hi[3],
@@ -93,7 +94,8 @@ __device__ __forceinline__ int gather_candidates(const BinState& bins, const dou
             const double dz = fmax(0.0, fmax(lo[2] - Z, Z - hi[2]));
             if (dx * dx + dy * dy + dz * dz < rc2) {
                 if (off < cap)
-                    cand[off] = make_float4((float)(X - o[0]), (float)(Y - o[1]), (float)(Z - o[2]), 0.f);
+                    cand[off] = make_float4((float)(X - o[0]), (float)(Y - o[1]), (float)(Z - o[2]),
+                                            __int_as_float((int)at.w));
                 ++off;
             }
         }
