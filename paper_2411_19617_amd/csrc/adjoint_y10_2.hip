@@ -1,0 +1,8 @@
+// dL/du contraction of the descriptor adjoint at twojmax 10, output levels
+// 6..7 (see adjoint_y.h).
+#include "adjoint_y.h"
+
+namespace mala {
+template hipError_t yi_group<10, 2>(hipStream_t, int64_t, const float2*, const float*, float2*, const float*,
+                                     const int*, const int*);
+}  // namespace mala

@@ -344,12 +344,15 @@ void ctx_trim(mala_ctx* c);
 int build_cg_table(int twojmax, float* table, int* offsets, int cap);
 int build_cg_table_adjoint(int twojmax, float* table, int* offsets, int cap);
 int y_waves();
+int y_group_count(int tj);      // kernels (groups of output levels) of the dL/du contraction
+int y_group_first(int tj, int g);
+int y_group_last(int tj, int g);
 hipError_t launch_zero_f64(hipStream_t s, double* p, int64_t n);
 hipError_t launch_yi(hipStream_t s, int twojmax, int64_t n_pts, const float2* u, const float* gB, float2* y,
                      const float* cg_tab, const int* cg_off, const int* wave_units);
 hipError_t launch_dedr(hipStream_t s, int twojmax, const BinState& bins, const int N[3], double rcut,
                        int64_t pt_begin, int64_t n_pts, const float2* y, double* dLdR, int* err);
-void plan_y_units(int twojmax, int n_waves, int* wave_units, int stride);
+void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units, int stride);
 void plan_zb_waves(int twojmax, int n_waves, int* wave_triples, int stride);
 constexpr int kLiTerms = 32;
 constexpr int kLiPow = 64;

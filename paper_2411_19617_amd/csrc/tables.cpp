@@ -148,13 +148,13 @@ int build_cg_table_adjoint(int twojmax, float* table, int* offsets, int cap) {
     return n;
 }
 
-// Work units of the adjoint contraction: output level C and column mb, each
-// summing Z^C(A, B)[., mb] over the coupled pairs of C.  Assigned to the
-// waves of a block by longest processing time; wave_units[w*stride] = count,
+// Work units of the adjoint contraction: output level C (c_lo..c_hi) and
+// column mb, each summing Z^C(A, B)[., mb] over the coupled pairs of C.
+// Assigned to the waves of a block by longest processing time; wave_units[w*stride] = count,
 // followed by the units (C * 32 + mb).
-void plan_y_units(int twojmax, int n_waves, int* wave_units, int stride) {
+void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units, int stride) {
     std::vector<std::pair<double, int>> jobs;
-    for (int C = 0; C <= twojmax; ++C)
+    for (int C = c_lo; C <= c_hi; ++C)
         for (int mb = 0; mb <= C; ++mb) {
             double cost = 0.0;
             for (int k = combo_first(twojmax, C); k < n_combos(twojmax) && combo_of(twojmax, k).c == C; ++k) {
