@@ -18,7 +18,7 @@ namespace mala {
 typedef float fv2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) const fv2 lds_float2;      // the LDS u tile
 
-constexpr int kYWaves = 8;            // two waves per SIMD: the fixed orientations need up to 256 VGPRs
+constexpr int kYMaxWaves = 12;        // plan stride: waves of the widest group
 
 // ------------------------------------------------------------------ Y
 // Column mb of Z^C(A,B) (half rows; the middle row only for mb <= C/2),
@@ -217,8 +217,12 @@ __host__ __device__ constexpr int y_group_hi(int tj, int g) {
     return g + 1 < y_groups(tj) ? y_group_lo(tj, g + 1) - 1 : tj;
 }
 
+// Waves per block: three per SIMD (168 VGPRs) where the group's coupled pairs
+// fit, two (256 VGPRs) for the two highest groups at twojmax 10.
+__host__ __device__ constexpr int y_group_waves(int tj, int g) { return tj == 10 && g >= 2 ? 8 : 12; }
+
 template <int TJ, int G>
-__global__ __launch_bounds__(kYWaves * 64) void k_yi(const float2* __restrict__ u, int64_t n_pts,
+__global__ __launch_bounds__(y_group_waves(TJ, G) * 64) void k_yi(const float2* __restrict__ u, int64_t n_pts,
                                                      const float* __restrict__ gB, float2* __restrict__ y_out,
                                                      const float* __restrict__ cg_tab, const int* __restrict__ cg_off,
                                                      const int* __restrict__ wave_units, int stride) {
@@ -259,8 +263,8 @@ hipError_t yi_group(hipStream_t s, int64_t n_pts, const float2* u, const float* 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_yi<TJ, G>), dim3((unsigned)n_tiles), dim3(kYWaves * 64), lds, s, u, n_pts, gB, y, cg_tab,
-                       cg_off, wave_units + G * kYWaves * kMaxYStride, kMaxYStride);
+    hipLaunchKernelGGL((k_yi<TJ, G>), dim3((unsigned)n_tiles), dim3(y_group_waves(TJ, G) * 64), lds, s, u, n_pts, gB,
+                       y, cg_tab, cg_off, wave_units + G * kYMaxWaves * kMaxYStride, kMaxYStride);
     return hipGetLastError();
 }
 

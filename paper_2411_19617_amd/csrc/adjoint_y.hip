@@ -14,7 +14,8 @@ extern template hipError_t yi_group<10, 2>(hipStream_t, int64_t, const float2*, 
 extern template hipError_t yi_group<10, 3>(hipStream_t, int64_t, const float2*, const float*, float2*, const float*,
                                            const int*, const int*);
 
-int y_waves() { return kYWaves; }
+int y_max_waves() { return kYMaxWaves; }
+int y_group_wave_count(int tj, int g) { return y_group_waves(tj, g); }
 int y_group_count(int tj) { return y_groups(tj); }
 int y_group_first(int tj, int g) { return y_group_lo(tj, g); }
 int y_group_last(int tj, int g) { return y_group_hi(tj, g); }

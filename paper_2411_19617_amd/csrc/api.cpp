@@ -202,11 +202,11 @@ mala_status ensure_adjoint_tables(mala_ctx* c, int tj) {
     std::vector<int> off(n_combos(tj));
     const int n = build_cg_table_adjoint(tj, tab.data(), off.data(), (int)tab.size());
     if (n < 0) return fail(MALA_E_UNSUPPORTED, "Clebsch-Gordan table of the adjoint too large");
-    const int nw = y_waves(), ng = y_group_count(tj);
+    const int nw = y_max_waves(), ng = y_group_count(tj);
     std::vector<int> units((size_t)ng * nw * kMaxYStride, 0);       // one plan per level group
     for (int g = 0; g < ng; ++g)
-        plan_y_units(tj, y_group_first(tj, g), y_group_last(tj, g), nw, units.data() + (size_t)g * nw * kMaxYStride,
-                     kMaxYStride);
+        plan_y_units(tj, y_group_first(tj, g), y_group_last(tj, g), y_group_wave_count(tj, g),
+                     units.data() + (size_t)g * nw * kMaxYStride, kMaxYStride);
     HIP_TRY(hipMalloc(&t.cgy, sizeof(float) * (n > 0 ? n : 1)));
     HIP_TRY(hipMalloc(&t.cgy_off, sizeof(int) * off.size()));
     HIP_TRY(hipMalloc(&t.yunits, sizeof(int) * units.size()));

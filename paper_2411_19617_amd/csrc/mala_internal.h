@@ -343,7 +343,8 @@ void ctx_trim(mala_ctx* c);
 // Host-side tables.
 int build_cg_table(int twojmax, float* table, int* offsets, int cap);
 int build_cg_table_adjoint(int twojmax, float* table, int* offsets, int cap);
-int y_waves();
+int y_max_waves();
+int y_group_wave_count(int tj, int g);
 int y_group_count(int tj);      // kernels (groups of output levels) of the dL/du contraction
 int y_group_first(int tj, int g);
 int y_group_last(int tj, int g);
