@@ -430,6 +430,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--serve-requests", type=int, default=48, help="0 disables the serving stream")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the lines outside the metric (Gaussian descriptors, network and descriptor VJPs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain device copies that calibrate the HBM byte counters")
     ap.add_argument("--traffic-summary", nargs=4, metavar="DIR",
@@ -533,9 +535,10 @@ def main():
                    "minus_ts_mev_per_atom": 1000 * r["e_entropy"] / snap.n_atoms, "entropy_kb": r["entropy"]},
         "errors_vs_oracle": errors_vs_oracle(a.workload, snap, dos, mala.read_result(res), dens),
     }
-    out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
-    out["network_vjp"] = network_vjp_bench(ctx, mala, snap, net, torch)
-    out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, snap, torch)
+    if not a.no_extras:
+        out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
+        out["network_vjp"] = network_vjp_bench(ctx, mala, snap, net, torch)
+        out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, snap, torch)
     if a.serve_requests > 0:
         out["serving"] = serving_bench(mala, prec, a.serve_requests)
         out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]
