@@ -124,8 +124,8 @@ def measured_traffic(workload):
 
 
 TRAFFIC_CMDS = """# commands (repository root = $REPO on the GPU box, after cd /tmp && export TMPDIR=/tmp):
-#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0
-#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
 #   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_cfetch -o run -- python $REPO/bench.py --copy-calibration
 #   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_cwrite -o run -- python $REPO/bench.py --copy-calibration
 #   python bench.py --traffic-summary gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/pmc_cfetch gpurun_out/pmc_cwrite
