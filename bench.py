@@ -123,12 +123,12 @@ def measured_traffic(workload):
     return float(kv["traffic_bytes_per_launch"])
 
 
-TRAFFIC_CMDS = """# commands (repository root = $REPO on the GPU box, after cd /tmp && export TMPDIR=/tmp):
-#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
-#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
-#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_cfetch -o run -- python $REPO/bench.py --copy-calibration
-#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_cwrite -o run -- python $REPO/bench.py --copy-calibration
-#   python bench.py --traffic-summary gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/pmc_cfetch gpurun_out/pmc_cwrite
+TRAFFIC_CMDS = """# commands (repository root = $REPO, output directory $OUT, after cd /tmp && export TMPDIR=/tmp):
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_cfetch -o run -- python $REPO/bench.py --copy-calibration
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_cwrite -o run -- python $REPO/bench.py --copy-calibration
+#   python bench.py --traffic-summary $OUT/pmc_fetch $OUT/pmc_write $OUT/pmc_cfetch $OUT/pmc_cwrite
 """
 COPY_GIB = 1
 
@@ -234,7 +234,7 @@ def stats_summary(prof_dir, bench_json, out_name, command):
         raise SystemExit("no bench JSON line in %s" % bench_json)
     cfg, rf = b["config"], b["roofline"]
     lines = ["# rocprofv3 kernel stats: %s, %s network" % (cfg["workload"], cfg["network_precision"]), "",
-             "Command (repository root = $REPO on the GPU box):", "", "```",
+             "Command (repository root = $REPO, output directory $OUT):", "", "```",
              "cd /tmp && export TMPDIR=/tmp && " + command, "```", "",
              "| kernel | calls | avg ms | min ms | max ms | total ms | share |", "|---|---|---|---|---|---|---|"]
     zb = None

@@ -121,6 +121,13 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _device_f32(name, t):
+    """The library reads raw float32 device memory: reject anything else."""
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 device tensor" % name)
+
+
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -248,6 +255,7 @@ class Context:
         pos, pp, n_at = _positions(positions)
         ntot = int(N[0]) * int(N[1]) * int(N[2])
         pt_end = ntot if pt_end is None else int(pt_end)
+        _device_f32("gB", gB)
         if int(gB.shape[0]) != max(pt_end - pt_begin, 0) or int(gB.shape[1]) != n_descriptors(twojmax):
             raise ValueError("gB must be [pt_end - pt_begin][n_B]")
         if out is None:
@@ -283,6 +291,8 @@ class Context:
         """g = (dd/dB)^T v per point (device float32 [n][w0])."""
         import torch
         self._sync_stream()
+        _device_f32("B", B)
+        _device_f32("v", v)
         n = int(B.shape[0])
         if int(v.shape[0]) != n:
             raise ValueError("B and v hold different point counts")
