@@ -101,3 +101,27 @@ def test_adjoint_full_grid_linear_and_additive(env):
     add = np.max(np.abs(fa + fb - f1)) / np.max(np.abs(f1))
     log("full grid: linearity %.3e additivity %.3e" % (lin, add))
     assert lin <= 1e-5 and add <= 1e-5
+
+
+def test_force_path_composition_matches_oracle(env):
+    """The two factors chained as the force expression applies them: B from
+    the GPU descriptors, g = (dd/dB)^T v from the network VJP, then
+    dL/dR from the descriptor VJP; the oracle chains its own three steps.
+    With slope 1 the network is affine (no kinks), so the comparison is
+    element-wise for every point."""
+    mala, ctx, torch = env
+    s = mala_synth.small()
+    net = mala_synth.make_net([55, 100, 100, 250], 104, 8, slope=1.0)
+    n = s.n_points
+    v = np.random.default_rng(77).standard_normal((n, 250)).astype(np.float32)
+    w = ctx.weights(mala_synth.net_to_blob(net), mala.PREC_FP32)
+    B = ctx.mala_descriptors(s.positions, s.L, s.N, s.rcut, s.twojmax)
+    g = ctx.mala_ldos_vjp(w, B, torch.as_tensor(v, device="cuda"))
+    F = ctx.mala_descriptors_vjp(s.positions, s.L, s.N, s.rcut, s.twojmax, g).cpu().numpy()
+    ctx.check_device_errors()
+    Bref = oracle.descriptors(s, nthreads=16)
+    gref, _ = oracle.mlp_vjp(Bref, net, v.astype(np.float64), nthreads=16)
+    Fref = oracle.descriptors_vjp(s, gref, nthreads=16)
+    err = np.max(np.abs(F - Fref)) / np.max(np.abs(Fref))
+    log("force path composition rel err %.3e (max |ref| %.3e)" % (err, np.max(np.abs(Fref))))
+    assert err <= TOL
