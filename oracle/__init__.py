@@ -60,6 +60,14 @@ def lib():
         L.oracle_descriptors.argtypes = [p, i, p, p, d, i, p, i64, p, p, i]
         L.oracle_mlp.argtypes = [p, i64, i, p, p, p, p, p, p, p, d, i, p, i]
         L.oracle_u_adjoint.argtypes = [p, i, p, p]
+        L.oracle_wigner3j.restype = d
+        L.oracle_wigner3j.argtypes = [i] * 6
+        L.oracle_ace_radial.restype = d
+        L.oracle_ace_radial.argtypes = [i, d, d]
+        L.oracle_ace_count.restype = i
+        L.oracle_ace_count.argtypes = [i, i]
+        L.oracle_ace.restype = i
+        L.oracle_ace.argtypes = [p, i, p, p, d, i, i, p, i64, p, i]
         L.oracle_dcayley_klein.argtypes = [d, d, d, d, p, p]
         L.oracle_dcutoff.restype = d
         L.oracle_dcutoff.argtypes = [d, d]
@@ -201,6 +209,46 @@ def descriptors_vjp(snap, gB, points=None, nthreads=0):
     if lib().oracle_descriptors_vjp(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N), float(snap.rcut),
                                     int(snap.twojmax), _ptr(pts), pts.shape[0], _ptr(gB), _ptr(out),
                                     int(nthreads)) < 0:
+        raise RuntimeError("oracle neighbour list overflow")
+    return out
+
+
+class _Cplx(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+def ylm(l, m, d):
+    """Orthonormal complex spherical harmonic Y_l^m of the direction d (Condon-Shortley)."""
+    f = lib().oracle_ylm
+    f.restype = _Cplx
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    v = f(int(l), int(m), float(d[0]), float(d[1]), float(d[2]))
+    return complex(v.re, v.im)
+
+
+def wigner3j(l1, l2, l3, m1, m2, m3):
+    return lib().oracle_wigner3j(l1, l2, l3, m1, m2, m3)
+
+
+def ace_radial(n, r, rcut):
+    return lib().oracle_ace_radial(int(n), float(r), float(rcut))
+
+
+def ace_count(nmax, lmax):
+    return lib().oracle_ace_count(int(nmax), int(lmax))
+
+
+def ace(snap, rcut, nmax, lmax, points=None, nthreads=0):
+    """Grid ACE descriptors [n_pts][ace_count] (ranks 1-3, one element)."""
+    if points is None:
+        points = np.arange(snap.n_points, dtype=np.int64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    L = _f64(snap.L)
+    pos = _f64(np.mod(snap.positions, L))
+    N = np.ascontiguousarray(snap.N, dtype=np.int32)
+    out = np.zeros((pts.shape[0], ace_count(nmax, lmax)))
+    if lib().oracle_ace(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N), float(rcut), int(nmax), int(lmax), _ptr(pts),
+                        pts.shape[0], _ptr(out), int(nthreads)) < 0:
         raise RuntimeError("oracle neighbour list overflow")
     return out
 

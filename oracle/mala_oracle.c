@@ -410,6 +410,167 @@ void oracle_mlp(const double *B, int64_t n_pts, int n_layers, const int *widths,
     }
 }
 
+/* ------------------------------------------------------------ grid ACE
+ * Grid-centred atomic cluster expansion descriptors (Sec. 3.2.3, Eqs.
+ * unweighted_ionicdensity, gridatom_basis, grid_base, product_grid_basis,
+ * ace_grid) with one chemical element:
+ *   phi_nlm(d) = R_n(|d|) Y_l^m(d/|d|),  R_n(r) = T_n(2 r / rcut - 1) fc(r)
+ *   (Chebyshev polynomial of the first kind times the cosine cutoff, which
+ *   makes every basis function vanish smoothly at the cutoff),
+ *   A_nlm = sum over atom images within rcut of phi_nlm(R - r) plus the
+ *   grid point's own delta, which projects onto l = 0 only:
+ *   R_n(0) Y_0^0 = (-1)^n / sqrt(4 pi);
+ *   rank 1: B = A_n00 (real);
+ *   rank 2: B = sum_m (-1)^m A_{n1 l m} A_{n2 l -m};
+ *   rank 3: B = sum_{m1+m2+m3=0} (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} A_{n3 l3 m3}
+ *   (Wigner 3j symbol), l1+l2+l3 even and triangle.
+ * Order: rank 1 for n = 0..nmax-1; rank 2 for l = 0..lmax, n1 <= n2; rank 3
+ * over multisets of three (n, l) pairs, key p = n (lmax+1) + l, p1 <= p2 <= p3.
+ * Y_l^m: orthonormal complex spherical harmonics with the Condon-Shortley
+ * phase.                                                                   */
+
+/* Y_l^m(theta, phi) from the explicit associated Legendre sum. */
+cplx oracle_ylm(int l, int m, double x, double y, double z)
+{
+    double r = sqrt(x * x + y * y + z * z);
+    double t = z / r, st = sqrt(fmax(0.0, 1.0 - t * t));
+    double phi = atan2(y, x);
+    int am = abs(m);
+    /* d^am/dt^am P_l(t), P_l(t) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) t^(l-2k) */
+    double dp = 0.0;
+    for (int k = 0; 2 * k <= l; k++) {
+        int pw = l - 2 * k;
+        if (pw < am) continue;
+        double c = ((k & 1) ? -1.0 : 1.0) * binom(l, k) * binom(2 * l - 2 * k, l) / pow(2.0, l);
+        double f = 1.0;
+        for (int i = 0; i < am; i++) f *= (pw - i);
+        dp += c * f * pow(t, pw - am);
+    }
+    double plm = ((am & 1) ? -1.0 : 1.0) * pow(st, am) * dp;     /* Condon-Shortley phase */
+    double nrm = sqrt((2 * l + 1) / (4.0 * OR_PI) * fact(l - am) / fact(l + am));
+    cplx v = nrm * plm * cexp(I * am * phi);
+    if (m < 0) v = ((am & 1) ? -1.0 : 1.0) * conj(v);
+    return v;
+}
+
+/* Wigner 3j symbol by the Racah formula (integer angular momenta). */
+double oracle_wigner3j(int l1, int l2, int l3, int m1, int m2, int m3)
+{
+    if (m1 + m2 + m3 != 0) return 0.0;
+    if (l3 < abs(l1 - l2) || l3 > l1 + l2) return 0.0;
+    if (abs(m1) > l1 || abs(m2) > l2 || abs(m3) > l3) return 0.0;
+    double tri = fact(l1 + l2 - l3) * fact(l1 - l2 + l3) * fact(-l1 + l2 + l3) / fact(l1 + l2 + l3 + 1);
+    double pre = sqrt(tri * fact(l1 + m1) * fact(l1 - m1) * fact(l2 + m2) * fact(l2 - m2) * fact(l3 + m3) *
+                      fact(l3 - m3));
+    double s = 0.0;
+    for (int k = 0; k <= l1 + l2 + l3; k++) {
+        int a = l1 + l2 - l3 - k, b = l1 - m1 - k, c = l2 + m2 - k, d = l3 - l2 + m1 + k, e = l3 - l1 - m2 + k;
+        if (a < 0 || b < 0 || c < 0 || d < 0 || e < 0) continue;
+        s += ((k & 1) ? -1.0 : 1.0) / (fact(k) * fact(a) * fact(b) * fact(c) * fact(d) * fact(e));
+    }
+    return (((l1 - l2 - m3) & 1) ? -1.0 : 1.0) * pre * s;
+}
+
+/* R_n(r) = T_n(2 r / rcut - 1) fc(r), T_n from its definition cos(n acos x). */
+double oracle_ace_radial(int n, double r, double rcut)
+{
+    if (r >= rcut) return 0.0;
+    double x = 2.0 * r / rcut - 1.0;
+    return cos(n * acos(fmax(-1.0, fmin(1.0, x)))) * oracle_cutoff(r, rcut);
+}
+
+static int ace_triangle_even(int a, int b, int c)
+{
+    return c >= abs(a - b) && c <= a + b && ((a + b + c) % 2 == 0);
+}
+
+int oracle_ace_count(int nmax, int lmax)
+{
+    int np = nmax * (lmax + 1), n3 = 0;
+    for (int p1 = 0; p1 < np; p1++)
+        for (int p2 = p1; p2 < np; p2++)
+            for (int p3 = p2; p3 < np; p3++)
+                if (ace_triangle_even(p1 % (lmax + 1), p2 % (lmax + 1), p3 % (lmax + 1))) n3++;
+    return nmax + (lmax + 1) * nmax * (nmax + 1) / 2 + n3;
+}
+
+/* Descriptors at the listed flat grid points; out is [n_pts][count]. */
+int oracle_ace(const double *pos, int n_atoms, const double *L, const int *N, double rcut, int nmax,
+               int lmax, const int64_t *pts, int64_t n_pts, double *out, int nthreads)
+{
+    const int max_nbr = 4096;
+    int nd = oracle_ace_count(nmax, lmax), nl = (lmax + 1) * (lmax + 1);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int overflow = 0;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        double *disp = malloc(sizeof(double) * 3 * max_nbr);
+        cplx *A = malloc(sizeof(cplx) * nmax * nl);     /* A[n][l*l + l + m] */
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t q = 0; q < n_pts; q++) {
+            int cnt = oracle_neighbours(pos, n_atoms, L, N, rcut, pts[q], disp, max_nbr);
+            if (cnt > max_nbr) {
+                overflow = 1;
+                continue;
+            }
+            for (int i = 0; i < nmax * nl; i++) A[i] = 0.0;
+            for (int n = 0; n < nmax; n++)                  /* the grid point's own delta */
+                A[n * nl] = ((n & 1) ? -1.0 : 1.0) / sqrt(4.0 * OR_PI);
+            for (int k = 0; k < cnt; k++) {
+                double dx = disp[3 * k], dy = disp[3 * k + 1], dz = disp[3 * k + 2];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                if (r == 0.0) {                               /* an atom on the point: l = 0 only */
+                    for (int n = 0; n < nmax; n++)
+                        A[n * nl] += oracle_ace_radial(n, 0.0, rcut) / sqrt(4.0 * OR_PI);
+                    continue;
+                }
+                for (int l = 0; l <= lmax; l++)
+                    for (int m = -l; m <= l; m++) {
+                        cplx y = oracle_ylm(l, m, dx, dy, dz);
+                        for (int n = 0; n < nmax; n++) A[n * nl + l * l + l + m] += oracle_ace_radial(n, r, rcut) * y;
+                    }
+            }
+            double *o = out + q * nd;
+            int d = 0;
+            for (int n = 0; n < nmax; n++) o[d++] = creal(A[n * nl]);
+            for (int l = 0; l <= lmax; l++)
+                for (int n1 = 0; n1 < nmax; n1++)
+                    for (int n2 = n1; n2 < nmax; n2++) {
+                        cplx s = 0.0;
+                        for (int m = -l; m <= l; m++)
+                            s += ((m & 1) ? -1.0 : 1.0) * A[n1 * nl + l * l + l + m] * A[n2 * nl + l * l + l - m];
+                        o[d++] = creal(s);
+                    }
+            int np = nmax * (lmax + 1);
+            for (int p1 = 0; p1 < np; p1++)
+                for (int p2 = p1; p2 < np; p2++)
+                    for (int p3 = p2; p3 < np; p3++) {
+                        int n1 = p1 / (lmax + 1), l1 = p1 % (lmax + 1), n2 = p2 / (lmax + 1), l2 = p2 % (lmax + 1);
+                        int n3 = p3 / (lmax + 1), l3 = p3 % (lmax + 1);
+                        if (!ace_triangle_even(l1, l2, l3)) continue;
+                        cplx s = 0.0;
+                        for (int m1 = -l1; m1 <= l1; m1++)
+                            for (int m2 = -l2; m2 <= l2; m2++) {
+                                int m3 = -m1 - m2;
+                                if (abs(m3) > l3) continue;
+                                s += oracle_wigner3j(l1, l2, l3, m1, m2, m3) * A[n1 * nl + l1 * l1 + l1 + m1] *
+                                     A[n2 * nl + l2 * l2 + l2 + m2] * A[n3 * nl + l3 * l3 + l3 + m3];
+                            }
+                        o[d++] = creal(s);
+                    }
+        }
+        free(disp);
+        free(A);
+    }
+    return overflow ? -1 : 0;
+}
+
 /* ------------------------------------------------------------ descriptor VJP
  * The descriptor factor of the force expression (Eq. forcesmala): for
  * weights gB(p) over the n_B components, the gradient of

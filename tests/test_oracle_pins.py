@@ -714,3 +714,103 @@ def test_descriptor_vjp_atom_on_grid_point_contributes_nothing():
     nb = oracle.lib().oracle_n_triples(2)
     g1 = oracle.descriptors_vjp(snap, np.ones((1, nb)), p)
     assert np.all(np.isfinite(g1))
+
+
+# ---------------------------------------------------------------- grid ACE
+def _iso_snap(pos, L=30.0, N=10):
+    return mala_synth.Snapshot("iso", np.mod(np.asarray(pos, float), L), np.array([L, L, L]),
+                               np.array([N, N, N]), 4.67, 8, 298.0, 3.0)
+
+
+def test_ace_ylm_matches_scipy_and_3j_matches_sympy():
+    import scipy.special as sp
+    from sympy.physics.wigner import wigner_3j
+    rng = np.random.default_rng(3)
+    for d in rng.normal(size=(6, 3)):
+        r = np.linalg.norm(d)
+        th, ph = np.arccos(d[2] / r), np.arctan2(d[1], d[0])
+        for l in range(5):
+            for m in range(-l, l + 1):
+                assert abs(oracle.ylm(l, m, d) - complex(sp.sph_harm_y(l, m, th, ph))) < 1e-13
+    for l1 in range(5):
+        for l2 in range(5):
+            for l3 in range(abs(l1 - l2), min(4, l1 + l2) + 1):
+                for m1 in range(-l1, l1 + 1):
+                    for m2 in range(-l2, l2 + 1):
+                        m3 = -m1 - m2
+                        if abs(m3) > l3:
+                            continue
+                        assert abs(oracle.wigner3j(l1, l2, l3, m1, m2, m3) -
+                                   float(wigner_3j(l1, l2, l3, m1, m2, m3))) < 1e-14
+
+
+def test_ace_radial_is_chebyshev_times_cutoff_and_count():
+    from numpy.polynomial import chebyshev
+    for r in (0.0, 0.7, 2.3, 4.0, 4.66, 4.67, 5.0):
+        for n in range(4):
+            x = 2 * r / 4.67 - 1
+            ref = chebyshev.chebval(x, [0] * n + [1]) * (0.5 * (np.cos(np.pi * r / 4.67) + 1) if r < 4.67 else 0.0)
+            assert abs(oracle.ace_radial(n, r, 4.67) - ref) < 1e-14
+    # count: rank 1 n, rank 2 (l, n1 <= n2), rank 3 multisets of (n, l) with even l-sum and triangle
+    nmax, lmax = 4, 4
+    pairs = [(n, l) for n in range(nmax) for l in range(lmax + 1)]
+    n3 = sum(1 for i in range(len(pairs)) for j in range(i, len(pairs)) for k in range(j, len(pairs))
+             if abs(pairs[i][1] - pairs[j][1]) <= pairs[k][1] <= pairs[i][1] + pairs[j][1]
+             and (pairs[i][1] + pairs[j][1] + pairs[k][1]) % 2 == 0)
+    assert oracle.ace_count(nmax, lmax) == nmax + (lmax + 1) * nmax * (nmax + 1) // 2 + n3 == 602
+
+
+def _ace_index(nmax, lmax):
+    """(rank, key) of every descriptor in output order."""
+    out = [(1, (n,)) for n in range(nmax)]
+    out += [(2, (l, n1, n2)) for l in range(lmax + 1) for n1 in range(nmax) for n2 in range(n1, nmax)]
+    np_ = nmax * (lmax + 1)
+    for p1 in range(np_):
+        for p2 in range(p1, np_):
+            for p3 in range(p2, np_):
+                ls = [p % (lmax + 1) for p in (p1, p2, p3)]
+                if abs(ls[0] - ls[1]) <= ls[2] <= ls[0] + ls[1] and sum(ls) % 2 == 0:
+                    out.append((3, tuple((p // (lmax + 1), p % (lmax + 1)) for p in (p1, p2, p3))))
+    return out
+
+
+def test_ace_empty_neighbourhood_and_single_atom_closed_forms():
+    """Only the grid point's own delta: A_n00 = (-1)^n / sqrt(4 pi), all other
+    A vanish.  One atom at distance r besides: for l > 0 the rank-2 value is
+    R_n1 R_n2 (2l+1)/(4 pi) by the addition theorem."""
+    idx = _ace_index(4, 4)
+    s0 = _iso_snap([[15.0, 15.0, 15.0]])
+    B0 = oracle.ace(s0, 4.67, 4, 4, np.array([0]))[0]
+    y00 = 1 / np.sqrt(4 * np.pi)
+    for v, (rank, key) in zip(B0, idx):
+        if rank == 1:
+            ref = (-1) ** key[0] * y00
+        elif rank == 2:
+            ref = (-1) ** (key[1] + key[2]) * y00 ** 2 if key[0] == 0 else 0.0
+        else:
+            ref = np.prod([(-1) ** n * y00 for n, l in key]) if all(l == 0 for n, l in key) else 0.0
+        assert abs(v - ref) < 1e-14
+    d = np.array([1.1, -0.7, 2.0])
+    s1 = _iso_snap([d])
+    B1 = oracle.ace(s1, 4.67, 4, 4, np.array([0]))[0]
+    r = np.linalg.norm(d)
+    R = [oracle.ace_radial(n, r, 4.67) for n in range(4)]
+    for v, (rank, key) in zip(B1, idx):
+        if rank == 2 and key[0] > 0:
+            l, n1, n2 = key
+            assert abs(v - R[n1] * R[n2] * (2 * l + 1) / (4 * np.pi)) < 1e-13
+
+
+def test_ace_rotation_inversion_permutation_invariance():
+    rng = np.random.default_rng(21)
+    pos = rng.normal(scale=1.7, size=(7, 3))
+    pos = pos[np.linalg.norm(pos, axis=1) < 4.5]
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    B = oracle.ace(_iso_snap(pos), 4.67, 4, 4, np.array([0]))[0]
+    Br = oracle.ace(_iso_snap(pos @ q.T), 4.67, 4, 4, np.array([0]))[0]
+    Bi = oracle.ace(_iso_snap(-pos), 4.67, 4, 4, np.array([0]))[0]
+    Bp = oracle.ace(_iso_snap(pos[::-1]), 4.67, 4, 4, np.array([0]))[0]
+    sc = np.max(np.abs(B))
+    assert np.max(np.abs(Br - B)) <= 1e-12 * sc
+    assert np.max(np.abs(Bi - B)) <= 1e-12 * sc
+    assert np.max(np.abs(Bp - B)) <= 1e-12 * sc
