@@ -157,6 +157,27 @@ mala_status mala_descriptors_vjp(mala_ctx* ctx, const double* positions, int32_t
                                  const mala_cell_grid* cg, double rcut, int32_t twojmax,
                                  int64_t pt_begin, int64_t pt_end, const float* gB, double* dLdR_out);
 
+/* Grid-centred atomic cluster expansion descriptors (Sec. 3.2.3, Eqs.
+ * unweighted_ionicdensity, gridatom_basis, grid_base, product_grid_basis,
+ * ace_grid) of grid points [pt_begin, pt_end), one chemical element:
+ *   A_nlm = R_n(0) Y_0^0 delta_l0 + sum over atom images within rcut of
+ *           R_n(r) Y_l^m(d/r),  R_n(r) = T_n(2 r / rcut - 1) fc(r)
+ *   (Chebyshev polynomials, cosine cutoff, orthonormal complex spherical
+ *   harmonics with the Condon-Shortley phase, n < nmax, l <= lmax);
+ *   rank 1: A_n00 for n < nmax;
+ *   rank 2: sum_m (-1)^m A_{n1 l m} A_{n2 l -m} for l = 0..lmax, n1 <= n2;
+ *   rank 3: sum (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} A_{n3 l3 m3}
+ *   (Wigner 3j) over multisets of three (n, l) pairs in the order of the key
+ *   p = n (lmax+1) + l, p1 <= p2 <= p3, with l1+l2+l3 even and triangle.
+ *  nmax in 1..4, lmax in 0..4 (MALA_E_UNSUPPORTED otherwise); positions,
+ *  cg, rcut as for mala_descriptors;
+ *  out: device float32 [pt_end - pt_begin][mala_ace_count(nmax, lmax)].
+ * Empty ranges are a no-op.                                                  */
+int32_t mala_ace_count(int32_t nmax, int32_t lmax);   /* descriptors per point, or < 0 */
+mala_status mala_ace_descriptors(mala_ctx* ctx, const double* positions, int32_t n_atoms,
+                                 const mala_cell_grid* cg, double rcut, int32_t nmax, int32_t lmax,
+                                 int64_t pt_begin, int64_t pt_end, float* out);
+
 /* Gaussian descriptors of grid points [pt_begin, pt_end): the Gaussian
  * representation of the ionic positions behind the structure factor
  * (Eq. structurefactor_gaussian), a Gaussian of width sigma normalised to
@@ -296,7 +317,8 @@ mala_status mala_server_destroy(mala_server* s);
 #define MALA_STAGE_MLP_VJP 11     /* network vector-Jacobian product         */
 #define MALA_STAGE_ADJ_Y 12       /* descriptor adjoint: dL/du               */
 #define MALA_STAGE_ADJ_DEDR 13    /* descriptor adjoint: dL/dR               */
-#define MALA_N_STAGES 14
+#define MALA_STAGE_ACE 14         /* grid ACE descriptors                    */
+#define MALA_N_STAGES 15
 mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
 mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
 

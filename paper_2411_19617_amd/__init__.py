@@ -26,7 +26,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 RESULT_BYTES = 64
 STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
-          "density_window", "gauss", "mlp_vjp", "adj_y", "adj_dedr"]
+          "density_window", "gauss", "mlp_vjp", "adj_y", "adj_dedr", "ace"]
 DENSITY_WINDOW = 0
 DENSITY_RECOMPUTE = 1
 
@@ -84,6 +84,8 @@ def lib():
             ("mala_weights_free", [p]),
             ("mala_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p]),
             ("mala_descriptors_vjp", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p, p]),
+            ("mala_ace_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, p]),
+            ("mala_ace_count", [i32, i32]),
             ("mala_gaussian_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, d, i64, i64, p]),
             ("mala_ldos_infer", [p, p, p, i64, p]),
             ("mala_ldos_vjp", [p, p, p, p, i64, p]),
@@ -110,6 +112,14 @@ def lib():
 
 def n_descriptors(twojmax):
     return int(lib().mala_n_descriptors(int(twojmax)))
+
+
+def ace_count(nmax, lmax):
+    """Grid ACE descriptors per point for (nmax, lmax); raises if unsupported."""
+    n = int(lib().mala_ace_count(int(nmax), int(lmax)))
+    if n < 0:
+        raise MalaError(n, "grid ACE: nmax must be 1..4 and lmax 0..4")
+    return n
 
 
 def _check(st):
@@ -263,6 +273,21 @@ class Context:
         cg = _cell_grid(L, N)
         _check(lib().mala_descriptors_vjp(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(twojmax),
                                           int(pt_begin), int(pt_end), _ptr(gB), _ptr(out)))
+        return out
+
+    def mala_ace_descriptors(self, positions, L, N, rcut, nmax=4, lmax=4, pt_begin=0, pt_end=None, out=None):
+        """Grid ACE descriptors [pt_end - pt_begin][ace_count(nmax, lmax)] (device float32)."""
+        import torch
+        self._sync_stream()
+        pos, pp, n_at = _positions(positions)
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        pt_end = ntot if pt_end is None else int(pt_end)
+        nd = ace_count(nmax, lmax)
+        if out is None:
+            out = torch.empty((max(pt_end - pt_begin, 0), nd), dtype=torch.float32, device=self.torch_device)
+        cg = _cell_grid(L, N)
+        _check(lib().mala_ace_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(nmax), int(lmax),
+                                          int(pt_begin), int(pt_end), _ptr(out)))
         return out
 
     def mala_gaussian_descriptors(self, positions, L, N, sigma, cutoff, pt_begin=0, pt_end=None, out=None):

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmala.so")
-SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "gauss.hip", "mlp.hip", "mlp_vjp.hip", "adjoint_y.hip", "adjoint_y10_0.hip", "adjoint_y10_1.hip",
+SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "gauss.hip", "ace.hip", "mlp.hip", "mlp_vjp.hip", "adjoint_y.hip", "adjoint_y10_0.hip", "adjoint_y10_1.hip",
            "adjoint_y10_2.hip", "adjoint_y10_3.hip", "adjoint_dedr.hip",
            "fermi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,192 @@
+// Grid-centred atomic cluster expansion descriptors (Sec. 3.2.3, Eqs.
+// unweighted_ionicdensity, gridatom_basis, grid_base, product_grid_basis,
+// ace_grid), one chemical element, ranks 1-3:
+//   A_nlm = sum over atom images within rcut of R_n(r) Y_l^m(d/r), plus the
+//   grid point's own delta on l = 0 (R_n(0) Y_0^0 = (-1)^n / sqrt(4 pi));
+//   R_n(r) = T_n(2 r / rcut - 1) fc(r) (Chebyshev times the cosine cutoff);
+//   rank 1: A_n00; rank 2: sum_m (-1)^m A_{n1 l m} A_{n2 l -m};
+//   rank 3: sum (l1 l2 l3; m1 m2 m3) A A A over multisets of three (n, l).
+// One wave per 64-point tile: the tile's candidate atom images are gathered
+// into LDS (shared with the other neighbour kernels), every lane visits them
+// in a fixed order and accumulates its A_nlm (m >= 0; A_{l,-m} =
+// (-1)^m conj(A_{l,m})) in registers: T_n by the three-term recurrence,
+// Y_l^m = N_lm Q_l^m(z/r) ((x + i y)/r)^m with Q_l^m = (-1)^m d^m P_l / dt^m by
+// the associated Legendre recurrence in l.  A then goes to LDS, ranks 1 and 2
+// are direct sums and rank 3 runs over a table of packed terms (storage
+// indices, conjugation flags, 3j symbol with signs) read with wave-uniform
+// loads.  Bound: FP32 VALU and LDS reads of the rank-3 terms.
+#include "ace.h"
+#include "tile_gather.h"
+
+namespace mala {
+
+constexpr int kAceN = kAceMaxN;          // radial functions held per point
+constexpr int kAceL = kAceMaxL;          // largest l held
+constexpr int kAceLm = 15;               // (l, m >= 0) entries per n: l(l+1)/2 + m
+
+__host__ __device__ constexpr double ace_fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+__host__ __device__ constexpr double ace_sqrt(double x) {
+    if (x <= 0.0) return 0.0;
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+// N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
+__host__ __device__ constexpr float ace_norm(int l, int m) {
+    return (float)ace_sqrt((2 * l + 1) / (4.0 * 3.14159265358979323846) * ace_fact(l - m) / ace_fact(l + m));
+}
+
+__global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
+                                            int64_t pt_begin, int64_t n_pts, const int* __restrict__ term_idx,
+                                            const float* __restrict__ term_coef, const int* __restrict__ desc_off,
+                                            int n3, int n_desc, float* __restrict__ out, int* __restrict__ err) {
+    __shared__ float4 cand[kMaxCand];
+    __shared__ float2 sA[kAceN * kAceLm][kTile];
+    __shared__ int scan_tmp[16];
+
+    const int lane = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t idx = tile * kTile + lane;
+    const bool valid = idx < n_pts;
+    const int64_t p = pt_begin + (valid ? idx : tile * kTile);
+    const int64_t pk = p % Nz, pj = (p / Nz) % Ny, pi = p / ((int64_t)Ny * Nz);
+    const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
+                 rz = (double)pk * bins.L[2] / Nz;
+    const int64_t p0 = pt_begin + tile * kTile;
+    const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
+    const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
+                 oz = (double)qk * bins.L[2] / Nz;
+    const double lo[3] = {wave_min_d(rx), wave_min_d(ry), wave_min_d(rz)};
+    const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
+    const double org[3] = {ox, oy, oz};
+    const int base = gather_candidates(bins, lo, hi, org, rcut, cand, kMaxCand, scan_tmp);
+    if (base > kMaxCand && lane == 0) atomicOr(err, kErrCand);
+    const int ncand = base < kMaxCand ? base : kMaxCand;
+    __syncthreads();
+
+    const float px = (float)(rx - ox), py = (float)(ry - oy), pz = (float)(rz - oz);
+    const float rcf = (float)rcut, rc2 = rcf * rcf;
+    constexpr float kpi = 3.14159265358979323846f;
+    float ar[kAceN][kAceLm], ai[kAceN][kAceLm];
+#pragma unroll
+    for (int n = 0; n < kAceN; ++n)
+#pragma unroll
+        for (int e = 0; e < kAceLm; ++e) ar[n][e] = ai[n][e] = 0.f;
+    constexpr float y00 = 0.28209479177387814f;            // 1 / sqrt(4 pi)
+#pragma unroll
+    for (int n = 0; n < kAceN; ++n) ar[n][0] = (n & 1) ? -y00 : y00;      // the grid point's own delta
+    for (int c = 0; c < ncand; ++c) {
+        const float4 q = cand[c];
+        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 < rc2)) continue;
+        const float r = sqrtf(r2);
+        // radial: T_n(x) fc(r)
+        const float x = 2.f * r / rcf - 1.f;
+        const float fc = 0.5f * (cosf(kpi * r / rcf) + 1.f);
+        float R[kAceN];
+        R[0] = fc;
+        R[1] = x * fc;
+#pragma unroll
+        for (int n = 2; n < kAceN; ++n) R[n] = 2.f * x * R[n - 1] - R[n - 2];
+        if (r2 == 0.f) {                                   // an atom on the point: l = 0 only
+#pragma unroll
+            for (int n = 0; n < kAceN; ++n) ar[n][0] += R[n] * y00;
+            continue;
+        }
+        const float inv = 1.f / r;
+        const float t = dz * inv, ur = dx * inv, ui = dy * inv;
+        // Q_l^m(t) for l <= 4, m >= 0, and ((x + i y)/r)^m
+        float Q[kAceLm];
+        float er[kAceL + 1], ei[kAceL + 1];
+        er[0] = 1.f;
+        ei[0] = 0.f;
+#pragma unroll
+        for (int m = 1; m <= kAceL; ++m) {
+            er[m] = er[m - 1] * ur - ei[m - 1] * ui;
+            ei[m] = er[m - 1] * ui + ei[m - 1] * ur;
+        }
+        static_for<0, kAceL + 1>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            // Q_m^m = (-1)^m (2m-1)!!
+            constexpr float qmm = (float)(((m & 1) ? -1.0 : 1.0) * (ace_fact(2 * m) / (ace_fact(m) * (double)(1 << m))));
+            Q[m * (m + 1) / 2 + m] = qmm;
+            if constexpr (m + 1 <= kAceL) Q[(m + 1) * (m + 2) / 2 + m] = (2 * m + 1) * t * qmm;
+            static_for<m + 2, kAceL + 1>([&](auto lc) {
+                constexpr int l = decltype(lc)::value;
+                Q[l * (l + 1) / 2 + m] = ((2 * l - 1) * t * Q[(l - 1) * l / 2 + m] -
+                                          (float)(l + m - 1) * Q[(l - 2) * (l - 1) / 2 + m]) /
+                                         (float)(l - m);
+            });
+        });
+        static_for<0, kAceL + 1>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            static_for<0, l + 1>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                constexpr int e = l * (l + 1) / 2 + m;
+                constexpr float nrm = ace_norm(l, m);
+                const float yr = nrm * Q[e] * er[m], yi = nrm * Q[e] * ei[m];
+#pragma unroll
+                for (int n = 0; n < kAceN; ++n) {
+                    ar[n][e] = fmaf(R[n], yr, ar[n][e]);
+                    ai[n][e] = fmaf(R[n], yi, ai[n][e]);
+                }
+            });
+        });
+    }
+#pragma unroll
+    for (int n = 0; n < kAceN; ++n)
+#pragma unroll
+        for (int e = 0; e < kAceLm; ++e) sA[n * kAceLm + e][lane] = make_float2(ar[n][e], ai[n][e]);
+    // the wave reads only its own lane's column of sA: no barrier needed
+
+    float* o = out + (valid ? idx : 0) * n_desc;
+    int d = 0;
+    for (int n = 0; n < nmax; ++n, ++d)
+        if (valid) o[d] = sA[n * kAceLm][lane].x;
+    for (int l = 0; l <= lmax; ++l)
+        for (int n1 = 0; n1 < nmax; ++n1)
+            for (int n2 = n1; n2 < nmax; ++n2, ++d) {
+                // sum_m (-1)^m A_{n1 l m} A_{n2 l -m} = A_{n1 l 0} A_{n2 l 0} + 2 sum_{m>0} Re(A_{n1 l m} conj(A_{n2 l m}))
+                const int e0 = l * (l + 1) / 2;
+                const float2 a0 = sA[n1 * kAceLm + e0][lane], b0 = sA[n2 * kAceLm + e0][lane];
+                float s = a0.x * b0.x + a0.y * b0.y;
+                for (int m = 1; m <= l; ++m) {
+                    const float2 a = sA[n1 * kAceLm + e0 + m][lane], b = sA[n2 * kAceLm + e0 + m][lane];
+                    s = fmaf(2.f, a.x * b.x + a.y * b.y, s);
+                }
+                if (valid) o[d] = s;
+            }
+    for (int k = 0; k < n3; ++k, ++d) {
+        const int t0 = __builtin_amdgcn_readfirstlane(desc_off[k]), t1 = __builtin_amdgcn_readfirstlane(desc_off[k + 1]);
+        float s = 0.f;
+        for (int t = t0; t < t1; ++t) {
+            const int pk3 = __builtin_amdgcn_readfirstlane(term_idx[t]);
+            const float cf = term_coef[t];
+            float2 a = sA[pk3 & 127][lane], b = sA[(pk3 >> 7) & 127][lane], cc = sA[(pk3 >> 14) & 127][lane];
+            if (pk3 & (1 << 21)) a.y = -a.y;
+            if (pk3 & (1 << 22)) b.y = -b.y;
+            if (pk3 & (1 << 23)) cc.y = -cc.y;
+            const float abr = a.x * b.x - a.y * b.y, abi = a.x * b.y + a.y * b.x;
+            s = fmaf(cf, abr * cc.x - abi * cc.y, s);
+        }
+        if (valid) o[d] = s;
+    }
+}
+
+hipError_t launch_ace(hipStream_t s, const BinState& bins, const int N[3], double rcut, int nmax, int lmax,
+                      int64_t pt_begin, int64_t n_pts, const int* term_idx, const float* term_coef,
+                      const int* desc_off, int n3, int n_desc, float* out, int* err) {
+    if (n_pts <= 0) return hipSuccess;
+    if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
+    const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64), 0, s, bins, N[0], N[1], N[2], rcut, nmax, lmax,
+                       pt_begin, n_pts, term_idx, term_coef, desc_off, n3, n_desc, out, err);
+    return hipGetLastError();
+}
+
+}  // namespace mala

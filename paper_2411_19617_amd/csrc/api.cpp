@@ -12,6 +12,7 @@
 #include <stddef.h>
 
 #include "mala.h"
+#include "ace.h"
 #include "mala_internal.h"
 
 using namespace mala;
@@ -82,6 +83,14 @@ struct TjTables {
 
 constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
 
+struct AceTables {
+    bool ready = false;
+    int n3 = 0;
+    int* idx = nullptr;
+    float* coef = nullptr;
+    int* off = nullptr;
+};
+
 }  // namespace
 
 struct mala_ctx {
@@ -105,6 +114,7 @@ struct mala_ctx {
     int* err = nullptr;
     double* li_coef = nullptr;
     TjTables tj[kMaxTwojmax + 1];
+    AceTables ace[kAceMaxN + 1][kAceMaxL + 1];
     // stage timing
     bool prof_on = false;
     struct Rec {
@@ -403,6 +413,12 @@ mala_status mala_destroy(mala_ctx* c) {
     if (c->pos_stage) (void)hipHostFree(c->pos_stage);
     if (c->err) (void)hipFree(c->err);
     if (c->li_coef) (void)hipFree(c->li_coef);
+    for (auto& row : c->ace)
+        for (auto& a : row) {
+            if (a.idx) (void)hipFree(a.idx);
+            if (a.coef) (void)hipFree(a.coef);
+            if (a.off) (void)hipFree(a.off);
+        }
     for (auto& t : c->tj) {
         if (t.cg) (void)hipFree(t.cg);
         if (t.cg_off) (void)hipFree(t.cg_off);
@@ -705,6 +721,50 @@ mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n
             return launch_dedr(c->stream, twojmax, bs, cg->N, rcut, pt_begin + off, n, c->yadj.p, dLdR_out, c->err);
         }));
     }
+    return MALA_OK;
+}
+
+int32_t mala_ace_count(int32_t nmax, int32_t lmax) {
+    if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL) return MALA_E_UNSUPPORTED;
+    std::vector<int> idx, off;
+    std::vector<float> coef;
+    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, idx, coef, off);
+}
+
+mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
+                                 double rcut, int32_t nmax, int32_t lmax, int64_t pt_begin, int64_t pt_end,
+                                 float* out) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL)
+        return fail(MALA_E_UNSUPPORTED, "grid ACE: nmax must be 1..4 and lmax 0..4");
+    mala_status st = check_geometry(positions, n_atoms, cg, rcut, 2);
+    if (st) return st;
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    if (pt_begin < 0 || pt_end < pt_begin || pt_end > ntot) return fail(MALA_E_INVALID_ARG, "bad point range");
+    if (pt_end == pt_begin) return MALA_OK;
+    if (!out) return fail(MALA_E_INVALID_ARG, "out is NULL");
+    DeviceGuard g(c->device);
+    AceTables& t = c->ace[nmax][lmax];
+    if (!t.ready) {
+        std::vector<int> idx, off;
+        std::vector<float> coef;
+        t.n3 = build_ace_tables(nmax, lmax, idx, coef, off);
+        HIP_TRY(hipMalloc(&t.idx, sizeof(int) * (idx.size() ? idx.size() : 1)));
+        HIP_TRY(hipMalloc(&t.coef, sizeof(float) * (coef.size() ? coef.size() : 1)));
+        HIP_TRY(hipMalloc(&t.off, sizeof(int) * off.size()));
+        HIP_TRY(hipMemcpy(t.idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+        t.ready = true;
+    }
+    const int n_desc = ace_count_ranks12(nmax, lmax) + t.n3;
+    if ((st = upload_positions(c, positions, n_atoms))) return st;
+    BinState bs{};
+    if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
+    HIP_TRY(staged(c, MALA_STAGE_ACE, pt_end - pt_begin, [&] {
+        return launch_ace(c->stream, bs, cg->N, rcut, nmax, lmax, pt_begin, pt_end - pt_begin, t.idx, t.coef, t.off,
+                          t.n3, n_desc, out, c->err);
+    }));
     return MALA_OK;
 }
 

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "ace.h"
 #include "mala_internal.h"
 
 namespace mala {
@@ -185,6 +186,70 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
         wave_units[w * stride] = (int)lists[w].size();
         for (size_t i = 0; i < lists[w].size(); ++i) wave_units[w * stride + 1 + i] = lists[w][i];
     }
+}
+
+// Rank-3 grid ACE terms.  For every descriptor (multisets of three (n, l)
+// pairs, key p = n (lmax+1) + l, p1 <= p2 <= p3, l1+l2+l3 even and
+// triangle) the terms (m1, m2, m3 = -m1-m2) of
+// sum (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} A_{n3 l3 m3}, with A stored
+// for m >= 0 only (A_{l,-m} = (-1)^m conj(A_{l,m})): each term packs the three
+// storage indices n*15 + l(l+1)/2 + |m| (7 bits each) and three conjugation
+// flags (bits 21-23); its coefficient carries the 3j symbol and the signs.
+// The 3j symbol comes from the coupled states of couple():
+// (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3) <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
+int build_ace_tables(int nmax, int lmax, std::vector<int>& term_idx, std::vector<float>& term_coef,
+                     std::vector<int>& desc_off) {
+    term_idx.clear();
+    term_coef.clear();
+    desc_off.assign(1, 0);
+    std::vector<Coupling> cache(25 * 25);
+    std::vector<bool> have(cache.size(), false);
+    auto three_j = [&](int l1, int l2, int l3, int m1, int m2, int m3) {
+        const int J1 = 2 * l1, J2 = 2 * l2, J = 2 * l3;
+        const int key = J1 * 25 + J2;
+        if (!have[key]) {
+            cache[key] = couple(J1, J2);
+            have[key] = true;
+        }
+        const Coupling& c = cache[key];
+        const int D = (J1 + J2 - J) / 2;
+        const int ma = l3 - m3, ma1 = l1 + m1, ma2 = l2 + m2;     // <l1 m1 l2 m2 | l3, -m3>
+        const double cg = c.vec[D][ma][pidx(J2, ma1, ma2)];
+        const int ph = l1 - l2 - m3;
+        return ((ph % 2 + 2) % 2 ? -1.0 : 1.0) * cg / sqrt(2.0 * l3 + 1.0);
+    };
+    const int np = nmax * (lmax + 1);
+    int nd = 0;
+    for (int p1 = 0; p1 < np; ++p1)
+        for (int p2 = p1; p2 < np; ++p2)
+            for (int p3 = p2; p3 < np; ++p3) {
+                const int n[3] = {p1 / (lmax + 1), p2 / (lmax + 1), p3 / (lmax + 1)};
+                const int l[3] = {p1 % (lmax + 1), p2 % (lmax + 1), p3 % (lmax + 1)};
+                if (l[2] < abs(l[0] - l[1]) || l[2] > l[0] + l[1] || (l[0] + l[1] + l[2]) % 2) continue;
+                for (int m1 = -l[0]; m1 <= l[0]; ++m1)
+                    for (int m2 = -l[1]; m2 <= l[1]; ++m2) {
+                        const int m3 = -m1 - m2;
+                        if (abs(m3) > l[2]) continue;
+                        double coef = three_j(l[0], l[1], l[2], m1, m2, m3);
+                        if (coef == 0.0) continue;
+                        const int m[3] = {m1, m2, m3};
+                        int packed = 0;
+                        for (int i = 0; i < 3; ++i) {
+                            const int am = abs(m[i]);
+                            const int idx = n[i] * 15 + l[i] * (l[i] + 1) / 2 + am;
+                            packed |= idx << (7 * i);
+                            if (m[i] < 0) {
+                                packed |= 1 << (21 + i);
+                                if (am & 1) coef = -coef;
+                            }
+                        }
+                        term_idx.push_back(packed);
+                        term_coef.push_back((float)coef);
+                    }
+                desc_off.push_back((int)term_idx.size());
+                ++nd;
+            }
+    return nd;
 }
 
 // Longest-processing-time assignment of triples to the waves of a block.
