@@ -367,6 +367,44 @@ def descriptor_adjoint_bench(ctx, snap, torch, reps=3):
                       "frac": tf_y / PEAK_FP32_VALU_TFLOPS}}
 
 
+def ace_flops(nmax, lmax, mean_nbr):
+    """Work of the grid ACE descriptors per point: 4 flop per (n, l, m >= 0)
+    and neighbour for the projections, 4 per rank-2 term (n1 <= n2, all m),
+    12 per nonzero rank-3 term (m1, m2, m3 = -m1-m2, 3j != 0)."""
+    from sympy.physics.wigner import wigner_3j
+    proj = 4.0 * nmax * (lmax + 1) * (lmax + 2) / 2 * mean_nbr
+    r2 = 4.0 * sum((2 * l + 1) * nmax * (nmax + 1) / 2 for l in range(lmax + 1))
+    keys = [(n, l) for n in range(nmax) for l in range(lmax + 1)]
+    terms = 0
+    for i in range(len(keys)):
+        for j in range(i, len(keys)):
+            for k in range(j, len(keys)):
+                l1, l2, l3 = keys[i][1], keys[j][1], keys[k][1]
+                if not (abs(l1 - l2) <= l3 <= l1 + l2 and (l1 + l2 + l3) % 2 == 0):
+                    continue
+                terms += sum(1 for m1 in range(-l1, l1 + 1) for m2 in range(-l2, l2 + 1)
+                             if abs(m1 + m2) <= l3 and wigner_3j(l1, l2, l3, m1, m2, -m1 - m2) != 0)
+    return proj + r2 + 12.0 * terms, terms
+
+
+def ace_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax=4, lmax=4):
+    """Grid ACE descriptors (ranks 1-3, nmax = lmax = 4, 602 per point) over the
+    whole grid, outside the metric's step."""
+    out = ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax, lmax)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax, lmax, out=out)
+    ms = ctx.profile_read()["ace"][0] / reps
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    fl, terms = ace_flops(nmax, lmax, mean_nbr)
+    tf = fl * snap.n_points / (ms * 1e-3) / 1e12
+    del out
+    return {"nmax": nmax, "lmax": lmax, "descriptors": mala.ace_count(nmax, lmax), "rank3_terms": terms,
+            "ms_per_grid": ms, "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl,
+            "tflops": tf, "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS}
+
+
 def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5, loads=(0.5, 0.7, 0.9)):
     """Poisson streams of the serving mix through the library's request loop.
 
@@ -539,6 +577,7 @@ def main():
         out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
         out["network_vjp"] = network_vjp_bench(ctx, mala, snap, net, torch)
         out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, snap, torch)
+        out["ace_descriptors"] = ace_bench(ctx, mala, snap, fl["mean_neighbours"], torch)
     if a.serve_requests > 0:
         out["serving"] = serving_bench(mala, prec, a.serve_requests)
         out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]

@@ -6,13 +6,15 @@
 //   R_n(r) = T_n(2 r / rcut - 1) fc(r) (Chebyshev times the cosine cutoff);
 //   rank 1: A_n00; rank 2: sum_m (-1)^m A_{n1 l m} A_{n2 l -m};
 //   rank 3: sum (l1 l2 l3; m1 m2 m3) A A A over multisets of three (n, l).
-// One wave per 64-point tile: the tile's candidate atom images are gathered
-// into LDS (shared with the other neighbour kernels), every lane visits them
-// in a fixed order and accumulates its A_nlm (m >= 0; A_{l,-m} =
-// (-1)^m conj(A_{l,m})) in registers: T_n by the three-term recurrence,
-// Y_l^m = N_lm Q_l^m(z/r) ((x + i y)/r)^m with Q_l^m = (-1)^m d^m P_l / dt^m by
-// the associated Legendre recurrence in l.  A then goes to LDS, ranks 1 and 2
-// are direct sums and rank 3 runs over a table of packed terms (storage
+// Four waves per 64-point tile (lane = point): the tile's candidate atom
+// images are gathered into LDS (shared with the other neighbour kernels);
+// wave w visits candidates w, w+4, ... and accumulates its part of the
+// lane's A_nlm (m >= 0; A_{l,-m} = (-1)^m conj(A_{l,m})) in registers: T_n by
+// the three-term recurrence, Y_l^m = N_lm Q_l^m(z/r) ((x + i y)/r)^m with
+// Q_l^m = (-1)^m d^m P_l / dt^m by the associated Legendre recurrence in l.
+// The parts are added into LDS (float atomics, so the last bits depend on
+// the order), then wave 0 forms ranks 1 and 2 and every wave takes every
+// fourth rank-3 descriptor, each a sum over a table of packed terms (storage
 // indices, conjugation flags, 3j symbol with signs) read with wave-uniform
 // loads.  Bound: FP32 VALU and LDS reads of the rank-3 terms.
 #include "ace.h"
@@ -23,6 +25,7 @@ namespace mala {
 constexpr int kAceN = kAceMaxN;          // radial functions held per point
 constexpr int kAceL = kAceMaxL;          // largest l held
 constexpr int kAceLm = 15;               // (l, m >= 0) entries per n: l(l+1)/2 + m
+constexpr int kAceWaves = 4;
 
 __host__ __device__ constexpr double ace_fact(int n) {
     double f = 1.0;
@@ -40,7 +43,7 @@ __host__ __device__ constexpr float ace_norm(int l, int m) {
     return (float)ace_sqrt((2 * l + 1) / (4.0 * 3.14159265358979323846) * ace_fact(l - m) / ace_fact(l + m));
 }
 
-__global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
+__global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
                                             int64_t pt_begin, int64_t n_pts, const int* __restrict__ term_idx,
                                             const float* __restrict__ term_coef, const int* __restrict__ desc_off,
                                             int n3, int n_desc, float* __restrict__ out, int* __restrict__ err) {
@@ -48,7 +51,8 @@ __global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int N
     __shared__ float2 sA[kAceN * kAceLm][kTile];
     __shared__ int scan_tmp[16];
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tile = blockIdx.x;
     const int64_t idx = tile * kTile + lane;
     const bool valid = idx < n_pts;
@@ -64,8 +68,10 @@ __global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int N
     const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
     const double org[3] = {ox, oy, oz};
     const int base = gather_candidates(bins, lo, hi, org, rcut, cand, kMaxCand, scan_tmp);
-    if (base > kMaxCand && lane == 0) atomicOr(err, kErrCand);
+    if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
+    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)
+        sA[e / kTile][e % kTile] = make_float2(0.f, 0.f);
     __syncthreads();
 
     const float px = (float)(rx - ox), py = (float)(ry - oy), pz = (float)(rz - oz);
@@ -77,9 +83,11 @@ __global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int N
 #pragma unroll
         for (int e = 0; e < kAceLm; ++e) ar[n][e] = ai[n][e] = 0.f;
     constexpr float y00 = 0.28209479177387814f;            // 1 / sqrt(4 pi)
+    if (wave == 0) {
 #pragma unroll
-    for (int n = 0; n < kAceN; ++n) ar[n][0] = (n & 1) ? -y00 : y00;      // the grid point's own delta
-    for (int c = 0; c < ncand; ++c) {
+        for (int n = 0; n < kAceN; ++n) ar[n][0] = (n & 1) ? -y00 : y00;  // the grid point's own delta
+    }
+    for (int c = wave; c < ncand; c += kAceWaves) {
         const float4 q = cand[c];
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -141,11 +149,16 @@ __global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int N
 #pragma unroll
     for (int n = 0; n < kAceN; ++n)
 #pragma unroll
-        for (int e = 0; e < kAceLm; ++e) sA[n * kAceLm + e][lane] = make_float2(ar[n][e], ai[n][e]);
-    // the wave reads only its own lane's column of sA: no barrier needed
+        for (int e = 0; e < kAceLm; ++e) {
+            atomicAdd(&sA[n * kAceLm + e][lane].x, ar[n][e]);
+            atomicAdd(&sA[n * kAceLm + e][lane].y, ai[n][e]);
+        }
+    __syncthreads();
 
     float* o = out + (valid ? idx : 0) * n_desc;
+    const int n12 = nmax + (lmax + 1) * nmax * (nmax + 1) / 2;
     int d = 0;
+    if (wave == 0) {
     for (int n = 0; n < nmax; ++n, ++d)
         if (valid) o[d] = sA[n * kAceLm][lane].x;
     for (int l = 0; l <= lmax; ++l)
@@ -161,9 +174,12 @@ __global__ __launch_bounds__(64) void k_ace(BinState bins, int Nx, int Ny, int N
                 }
                 if (valid) o[d] = s;
             }
-    for (int k = 0; k < n3; ++k, ++d) {
+    }
+    for (int k = wave; k < n3; k += kAceWaves) {
+        d = n12 + k;
         const int t0 = __builtin_amdgcn_readfirstlane(desc_off[k]), t1 = __builtin_amdgcn_readfirstlane(desc_off[k + 1]);
         float s = 0.f;
+#pragma unroll 4
         for (int t = t0; t < t1; ++t) {
             const int pk3 = __builtin_amdgcn_readfirstlane(term_idx[t]);
             const float cf = term_coef[t];
@@ -184,7 +200,7 @@ hipError_t launch_ace(hipStream_t s, const BinState& bins, const int N[3], doubl
     if (n_pts <= 0) return hipSuccess;
     if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64), 0, s, bins, N[0], N[1], N[2], rcut, nmax, lmax,
+    hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAceWaves), 0, s, bins, N[0], N[1], N[2], rcut, nmax, lmax,
                        pt_begin, n_pts, term_idx, term_coef, desc_off, n3, n_desc, out, err);
     return hipGetLastError();
 }
