@@ -179,16 +179,33 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
         d = n12 + k;
         const int t0 = __builtin_amdgcn_readfirstlane(desc_off[k]), t1 = __builtin_amdgcn_readfirstlane(desc_off[k + 1]);
         float s = 0.f;
-#pragma unroll 4
-        for (int t = t0; t < t1; ++t) {
-            const int pk3 = __builtin_amdgcn_readfirstlane(term_idx[t]);
-            const float cf = term_coef[t];
-            float2 a = sA[pk3 & 127][lane], b = sA[(pk3 >> 7) & 127][lane], cc = sA[(pk3 >> 14) & 127][lane];
-            if (pk3 & (1 << 21)) a.y = -a.y;
-            if (pk3 & (1 << 22)) b.y = -b.y;
-            if (pk3 & (1 << 23)) cc.y = -cc.y;
-            const float abr = a.x * b.x - a.y * b.y, abi = a.x * b.y + a.y * b.x;
-            s = fmaf(cf, abr * cc.x - abi * cc.y, s);
+        // eight terms per step (the lists are padded to multiples of eight):
+        // their indices and coefficients arrive as wave-uniform 16-byte loads
+        // and their 24 LDS reads are issued together
+        for (int t = t0; t < t1; t += 8) {
+            const int4 q0 = *reinterpret_cast<const int4*>(term_idx + t);
+            const int4 q1 = *reinterpret_cast<const int4*>(term_idx + t + 4);
+            const float4 c0 = *reinterpret_cast<const float4*>(term_coef + t);
+            const float4 c1 = *reinterpret_cast<const float4*>(term_coef + t + 4);
+            const int pk[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+            const float cf[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            float2 a[8], b[8], cc[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int pk3 = __builtin_amdgcn_readfirstlane(pk[i]);
+                a[i] = sA[pk3 & 127][lane];
+                b[i] = sA[(pk3 >> 7) & 127][lane];
+                cc[i] = sA[(pk3 >> 14) & 127][lane];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int pk3 = __builtin_amdgcn_readfirstlane(pk[i]);
+                const float ay = (pk3 & (1 << 21)) ? -a[i].y : a[i].y;
+                const float by = (pk3 & (1 << 22)) ? -b[i].y : b[i].y;
+                const float cy = (pk3 & (1 << 23)) ? -cc[i].y : cc[i].y;
+                const float abr = a[i].x * b[i].x - ay * by, abi = a[i].x * by + ay * b[i].x;
+                s = fmaf(cf[i], abr * cc[i].x - abi * cy, s);
+            }
         }
         if (valid) o[d] = s;
     }

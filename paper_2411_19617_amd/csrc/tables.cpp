@@ -195,6 +195,7 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
 // for m >= 0 only (A_{l,-m} = (-1)^m conj(A_{l,m})): each term packs the three
 // storage indices n*15 + l(l+1)/2 + |m| (7 bits each) and three conjugation
 // flags (bits 21-23); its coefficient carries the 3j symbol and the signs.
+// Every descriptor's list is padded with zero terms to a multiple of eight.
 // The 3j symbol comes from the coupled states of couple():
 // (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3) <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
 int build_ace_tables(int nmax, int lmax, std::vector<int>& term_idx, std::vector<float>& term_coef,
@@ -246,6 +247,10 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& term_idx, std::vector
                         term_idx.push_back(packed);
                         term_coef.push_back((float)coef);
                     }
+                while (term_idx.size() % 8) {           // batches of eight: zero terms on entry 0
+                    term_idx.push_back(0);
+                    term_coef.push_back(0.f);
+                }
                 desc_off.push_back((int)term_idx.size());
                 ++nd;
             }
