@@ -245,6 +245,9 @@ def stats_summary(prof_dir, bench_json, out_name, command):
             float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
         if name.startswith("mala::k_zb<"):
             zb = float(r["AverageNs"]) / 1e6
+    lines += ["", "The metric's step runs the cell list, `k_ui`, `k_zb`, `k_mlp` and `k_fermi` "
+              "(and `k_density_window`); `k_gauss`, `k_mlp_vjp`, `k_yi`, `k_dedr` and `k_ace` come from the "
+              "lines outside the metric (Gaussian descriptors, both VJPs, grid ACE) when they are run."]
     lines += ["", "Dominant kernel `k_zb`: rocprof average %.4f ms per launch; bench.py (same build, "
               "HIP events on the library stream) %.4f ms per launch over %.0f points: achieved %.1f %s = "
               "%.3f of the %.1f %s peak (%.1f kflop/point)."
