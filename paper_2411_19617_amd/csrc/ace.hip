@@ -14,9 +14,11 @@
 // Q_l^m = (-1)^m d^m P_l / dt^m by the associated Legendre recurrence in l.
 // The parts are added into LDS (float atomics, so the last bits depend on
 // the order), then wave 0 forms ranks 1 and 2 and every wave takes every
-// fourth rank-3 descriptor, each a sum over a table of packed terms (storage
-// indices, conjugation flags, 3j symbol with signs) read with wave-uniform
-// loads.  Bound: FP32 VALU and LDS reads of the rank-3 terms.
+// fourth rank-3 group (p1, p2, l3): the partial sums
+// P(m3) = sum_m1 (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} from a table of
+// packed terms (storage indices, conjugation flags, 3j symbol with signs,
+// sorted by m3) read with wave-uniform loads, then B = sum_m3 P(m3) A_{n3 l3 m3}
+// for every n3 of the group.  Bound: LDS reads and the table loads.
 #include "ace.h"
 #include "tile_gather.h"
 
@@ -44,9 +46,10 @@ __host__ __device__ constexpr float ace_norm(int l, int m) {
 }
 
 __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
-                                            int64_t pt_begin, int64_t n_pts, const int* __restrict__ term_idx,
-                                            const float* __restrict__ term_coef, const int* __restrict__ desc_off,
-                                            int n3, int n_desc, float* __restrict__ out, int* __restrict__ err) {
+                                            int64_t pt_begin, int64_t n_pts, const int* __restrict__ groups,
+                                            int n_groups, const int2* __restrict__ terms,
+                                            const int* __restrict__ outputs, int n_desc, float* __restrict__ out,
+                                            int* __restrict__ err) {
     __shared__ float4 cand[kMaxCand];
     __shared__ float2 sA[kAceN * kAceLm][kTile];
     __shared__ int scan_tmp[16];
@@ -175,50 +178,59 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
                 if (valid) o[d] = s;
             }
     }
-    for (int k = wave; k < n3; k += kAceWaves) {
-        d = n12 + k;
-        const int t0 = __builtin_amdgcn_readfirstlane(desc_off[k]), t1 = __builtin_amdgcn_readfirstlane(desc_off[k + 1]);
-        float s = 0.f;
-        // eight terms per step (the lists are padded to multiples of eight):
-        // their indices and coefficients arrive as wave-uniform 16-byte loads
-        // and their 24 LDS reads are issued together
-        for (int t = t0; t < t1; t += 8) {
-            const int4 q0 = *reinterpret_cast<const int4*>(term_idx + t);
-            const int4 q1 = *reinterpret_cast<const int4*>(term_idx + t + 4);
-            const float4 c0 = *reinterpret_cast<const float4*>(term_coef + t);
-            const float4 c1 = *reinterpret_cast<const float4*>(term_coef + t + 4);
-            const int pk[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-            const float cf[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-            float2 a[8], b[8], cc[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int pk3 = __builtin_amdgcn_readfirstlane(pk[i]);
-                a[i] = sA[pk3 & 127][lane];
-                b[i] = sA[(pk3 >> 7) & 127][lane];
-                cc[i] = sA[(pk3 >> 14) & 127][lane];
+    // rank 3 by groups (p1, p2, l3): P(m3) once, then every n3 of the group
+    for (int gi = wave; gi < n_groups; gi += kAceWaves) {
+        const int* gr = groups + 8 * gi;
+        int t = __builtin_amdgcn_readfirstlane(gr[0]);
+        const int l3 = __builtin_amdgcn_readfirstlane(gr[1]);
+        const int o0 = __builtin_amdgcn_readfirstlane(gr[2]), oc = __builtin_amdgcn_readfirstlane(gr[3]);
+        const int cnt8 = __builtin_amdgcn_readfirstlane(gr[4]), c8 = __builtin_amdgcn_readfirstlane(gr[5]);
+        float pr[9], pim[9];
+        static_for<0, 9>([&](auto sc) {
+            constexpr int slot = decltype(sc)::value;
+            const int cnt = slot < 8 ? (cnt8 >> (4 * slot)) & 15 : c8;
+            float xr = 0.f, xi = 0.f;
+            for (int k = 0; k < cnt; ++k, ++t) {
+                const int2 e = terms[t];
+                const int pk2 = __builtin_amdgcn_readfirstlane(e.x);
+                const float cf = __int_as_float(__builtin_amdgcn_readfirstlane(e.y));
+                const float2 a = sA[pk2 & 127][lane], b = sA[(pk2 >> 7) & 127][lane];
+                const float ay = (pk2 & (1 << 14)) ? -a.y : a.y;
+                const float by = (pk2 & (1 << 15)) ? -b.y : b.y;
+                xr = fmaf(cf, a.x * b.x - ay * by, xr);
+                xi = fmaf(cf, a.x * by + ay * b.x, xi);
             }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int pk3 = __builtin_amdgcn_readfirstlane(pk[i]);
-                const float ay = (pk3 & (1 << 21)) ? -a[i].y : a[i].y;
-                const float by = (pk3 & (1 << 22)) ? -b[i].y : b[i].y;
-                const float cy = (pk3 & (1 << 23)) ? -cc[i].y : cc[i].y;
-                const float abr = a[i].x * b[i].x - ay * by, abi = a[i].x * by + ay * b[i].x;
-                s = fmaf(cf[i], abr * cc[i].x - abi * cy, s);
-            }
+            pr[slot] = xr;
+            pim[slot] = xi;
+        });
+        for (int k = 0; k < oc; ++k) {
+            const int ok = __builtin_amdgcn_readfirstlane(outputs[o0 + k]);
+            const int base3 = ok & 127;
+            float v = 0.f;
+            static_for<0, 9>([&](auto sc) {
+                constexpr int slot = decltype(sc)::value;
+                constexpr int m3 = slot - 4, am = m3 < 0 ? -m3 : m3;
+                if (am <= l3) {
+                    // A_{l3,m3} = A_{l3,|m3|} for m3 >= 0, (-1)^|m3| conj(A_{l3,|m3|}) below
+                    const float2 c = sA[base3 + am][lane];
+                    constexpr float sg = (m3 < 0 && (am & 1)) ? -1.f : 1.f;
+                    const float cy = m3 < 0 ? -c.y : c.y;
+                    v = fmaf(sg, pr[slot] * c.x - pim[slot] * cy, v);    // Re(P A)
+                }
+            });
+            if (valid) o[n12 + (ok >> 7)] = v;
         }
-        if (valid) o[d] = s;
     }
 }
 
 hipError_t launch_ace(hipStream_t s, const BinState& bins, const int N[3], double rcut, int nmax, int lmax,
-                      int64_t pt_begin, int64_t n_pts, const int* term_idx, const float* term_coef,
-                      const int* desc_off, int n3, int n_desc, float* out, int* err) {
+                      int64_t pt_begin, int64_t n_pts, const int* groups, int n_groups, const int2* terms,
+                      const int* outputs, int n_desc, float* out, int* err) {
     if (n_pts <= 0) return hipSuccess;
     if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAceWaves), 0, s, bins, N[0], N[1], N[2], rcut, nmax, lmax,
-                       pt_begin, n_pts, term_idx, term_coef, desc_off, n3, n_desc, out, err);
+                       pt_begin, n_pts, groups, n_groups, terms, outputs, n_desc, out, err);
     return hipGetLastError();
 }
 

@@ -85,10 +85,10 @@ constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
 
 struct AceTables {
     bool ready = false;
-    int n3 = 0;
-    int* idx = nullptr;
-    float* coef = nullptr;
-    int* off = nullptr;
+    int n3 = 0, n_groups = 0;
+    int* groups = nullptr;
+    int2* terms = nullptr;
+    int* outputs = nullptr;
 };
 
 }  // namespace
@@ -415,9 +415,9 @@ mala_status mala_destroy(mala_ctx* c) {
     if (c->li_coef) (void)hipFree(c->li_coef);
     for (auto& row : c->ace)
         for (auto& a : row) {
-            if (a.idx) (void)hipFree(a.idx);
-            if (a.coef) (void)hipFree(a.coef);
-            if (a.off) (void)hipFree(a.off);
+            if (a.groups) (void)hipFree(a.groups);
+            if (a.terms) (void)hipFree(a.terms);
+            if (a.outputs) (void)hipFree(a.outputs);
         }
     for (auto& t : c->tj) {
         if (t.cg) (void)hipFree(t.cg);
@@ -726,9 +726,9 @@ mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n
 
 int32_t mala_ace_count(int32_t nmax, int32_t lmax) {
     if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL) return MALA_E_UNSUPPORTED;
-    std::vector<int> idx, off;
+    std::vector<int> groups, idx, outs;
     std::vector<float> coef;
-    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, idx, coef, off);
+    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, groups, idx, coef, outs);
 }
 
 mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
@@ -746,15 +746,22 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
     DeviceGuard g(c->device);
     AceTables& t = c->ace[nmax][lmax];
     if (!t.ready) {
-        std::vector<int> idx, off;
+        std::vector<int> groups, idx, outs;
         std::vector<float> coef;
-        t.n3 = build_ace_tables(nmax, lmax, idx, coef, off);
-        HIP_TRY(hipMalloc(&t.idx, sizeof(int) * (idx.size() ? idx.size() : 1)));
-        HIP_TRY(hipMalloc(&t.coef, sizeof(float) * (coef.size() ? coef.size() : 1)));
-        HIP_TRY(hipMalloc(&t.off, sizeof(int) * off.size()));
-        HIP_TRY(hipMemcpy(t.idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(t.coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(t.off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+        t.n3 = build_ace_tables(nmax, lmax, groups, idx, coef, outs);
+        t.n_groups = (int)(groups.size() / 8);
+        std::vector<int2> terms(idx.size());
+        for (size_t i = 0; i < idx.size(); ++i) {
+            int cb;
+            memcpy(&cb, &coef[i], 4);
+            terms[i] = make_int2(idx[i], cb);
+        }
+        HIP_TRY(hipMalloc(&t.groups, sizeof(int) * (groups.size() ? groups.size() : 1)));
+        HIP_TRY(hipMalloc(&t.terms, sizeof(int2) * (terms.size() ? terms.size() : 1)));
+        HIP_TRY(hipMalloc(&t.outputs, sizeof(int) * (outs.size() ? outs.size() : 1)));
+        HIP_TRY(hipMemcpy(t.groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.terms, terms.data(), sizeof(int2) * terms.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.outputs, outs.data(), sizeof(int) * outs.size(), hipMemcpyHostToDevice));
         t.ready = true;
     }
     const int n_desc = ace_count_ranks12(nmax, lmax) + t.n3;
@@ -762,8 +769,8 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
     BinState bs{};
     if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
     HIP_TRY(staged(c, MALA_STAGE_ACE, pt_end - pt_begin, [&] {
-        return launch_ace(c->stream, bs, cg->N, rcut, nmax, lmax, pt_begin, pt_end - pt_begin, t.idx, t.coef, t.off,
-                          t.n3, n_desc, out, c->err);
+        return launch_ace(c->stream, bs, cg->N, rcut, nmax, lmax, pt_begin, pt_end - pt_begin, t.groups, t.n_groups,
+                          t.terms, t.outputs, n_desc, out, c->err);
     }));
     return MALA_OK;
 }

@@ -188,21 +188,27 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
     }
 }
 
-// Rank-3 grid ACE terms.  For every descriptor (multisets of three (n, l)
-// pairs, key p = n (lmax+1) + l, p1 <= p2 <= p3, l1+l2+l3 even and
-// triangle) the terms (m1, m2, m3 = -m1-m2) of
-// sum (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} A_{n3 l3 m3}, with A stored
-// for m >= 0 only (A_{l,-m} = (-1)^m conj(A_{l,m})): each term packs the three
-// storage indices n*15 + l(l+1)/2 + |m| (7 bits each) and three conjugation
-// flags (bits 21-23); its coefficient carries the 3j symbol and the signs.
-// Every descriptor's list is padded with zero terms to a multiple of eight.
-// The 3j symbol comes from the coupled states of couple():
-// (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3) <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
-int build_ace_tables(int nmax, int lmax, std::vector<int>& term_idx, std::vector<float>& term_coef,
-                     std::vector<int>& desc_off) {
+// Rank-3 grid ACE tables.  The descriptors (multisets of three (n, l)
+// pairs, key p = n (lmax+1) + l, p1 <= p2 <= p3, l1+l2+l3 even and triangle,
+// in that order) are grouped by (p1, p2, l3).  A group's partial sums
+//   P(m3) = sum_m1 (l1 l2 l3; m1, -m1-m3, m3) A_{n1 l1 m1} A_{n2 l2 -m1-m3}
+// are formed once and every descriptor of the group is
+//   B = sum_m3 P(m3) A_{n3 l3 m3}.
+// A is stored for m >= 0 only (A_{l,-m} = (-1)^m conj(A_{l,m})) at n*15 +
+// l(l+1)/2 + |m|.  Per group: groups[8g..8g+7] = {first term, l3, first
+// output, output count, terms per m3 slot packed 4 bits x 8 (slots 0..7),
+// count of slot 8, 0, 0}; terms are sorted by slot m3 + 4 and pack the two
+// storage indices (7 bits each) and two conjugation flags (bits 14, 15),
+// the coefficient carrying the 3j symbol and the signs; outputs pack the
+// storage base n3*15 + l3(l3+1)/2 (bits 0-6) and the descriptor's rank-3
+// position (bits 7 and up).  The 3j symbol comes from the coupled states of
+// couple(): (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3) <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
+int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<int>& term_idx,
+                     std::vector<float>& term_coef, std::vector<int>& outputs) {
+    groups.clear();
     term_idx.clear();
     term_coef.clear();
-    desc_off.assign(1, 0);
+    outputs.clear();
     std::vector<Coupling> cache(25 * 25);
     std::vector<bool> have(cache.size(), false);
     auto three_j = [&](int l1, int l2, int l3, int m1, int m2, int m3) {
@@ -220,39 +226,57 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& term_idx, std::vector
         return ((ph % 2 + 2) % 2 ? -1.0 : 1.0) * cg / sqrt(2.0 * l3 + 1.0);
     };
     const int np = nmax * (lmax + 1);
+    // rank-3 position of every descriptor, in the output order
+    std::vector<int> pos_of(np * np * np, -1);
     int nd = 0;
     for (int p1 = 0; p1 < np; ++p1)
         for (int p2 = p1; p2 < np; ++p2)
             for (int p3 = p2; p3 < np; ++p3) {
-                const int n[3] = {p1 / (lmax + 1), p2 / (lmax + 1), p3 / (lmax + 1)};
-                const int l[3] = {p1 % (lmax + 1), p2 % (lmax + 1), p3 % (lmax + 1)};
-                if (l[2] < abs(l[0] - l[1]) || l[2] > l[0] + l[1] || (l[0] + l[1] + l[2]) % 2) continue;
-                for (int m1 = -l[0]; m1 <= l[0]; ++m1)
-                    for (int m2 = -l[1]; m2 <= l[1]; ++m2) {
-                        const int m3 = -m1 - m2;
-                        if (abs(m3) > l[2]) continue;
-                        double coef = three_j(l[0], l[1], l[2], m1, m2, m3);
-                        if (coef == 0.0) continue;
-                        const int m[3] = {m1, m2, m3};
-                        int packed = 0;
-                        for (int i = 0; i < 3; ++i) {
-                            const int am = abs(m[i]);
-                            const int idx = n[i] * 15 + l[i] * (l[i] + 1) / 2 + am;
-                            packed |= idx << (7 * i);
-                            if (m[i] < 0) {
-                                packed |= 1 << (21 + i);
-                                if (am & 1) coef = -coef;
-                            }
-                        }
-                        term_idx.push_back(packed);
-                        term_coef.push_back((float)coef);
-                    }
-                while (term_idx.size() % 8) {           // batches of eight: zero terms on entry 0
-                    term_idx.push_back(0);
-                    term_coef.push_back(0.f);
+                const int l1 = p1 % (lmax + 1), l2 = p2 % (lmax + 1), l3 = p3 % (lmax + 1);
+                if (l3 < abs(l1 - l2) || l3 > l1 + l2 || (l1 + l2 + l3) % 2) continue;
+                pos_of[(p1 * np + p2) * np + p3] = nd++;
+            }
+    for (int p1 = 0; p1 < np; ++p1)
+        for (int p2 = p1; p2 < np; ++p2)
+            for (int l3 = 0; l3 <= lmax; ++l3) {
+                const int n1 = p1 / (lmax + 1), l1 = p1 % (lmax + 1), n2 = p2 / (lmax + 1), l2 = p2 % (lmax + 1);
+                if (l3 < abs(l1 - l2) || l3 > l1 + l2 || (l1 + l2 + l3) % 2) continue;
+                std::vector<int> outs;
+                for (int n3 = 0; n3 < nmax; ++n3) {
+                    const int p3 = n3 * (lmax + 1) + l3;
+                    if (p3 < p2) continue;
+                    outs.push_back((n3 * 15 + l3 * (l3 + 1) / 2) | (pos_of[(p1 * np + p2) * np + p3] << 7));
                 }
-                desc_off.push_back((int)term_idx.size());
-                ++nd;
+                if (outs.empty()) continue;
+                int g[8] = {(int)term_idx.size(), l3, (int)outputs.size(), (int)outs.size(), 0, 0, 0, 0};
+                for (int slot = 0; slot < 9; ++slot) {
+                    const int m3 = slot - 4;
+                    int cnt = 0;
+                    if (abs(m3) <= l3)
+                        for (int m1 = -l1; m1 <= l1; ++m1) {
+                            const int m2 = -m1 - m3;
+                            if (abs(m2) > l2) continue;
+                            double coef = three_j(l1, l2, l3, m1, m2, m3);
+                            if (coef == 0.0) continue;
+                            const int m[2] = {m1, m2}, n[2] = {n1, n2}, l[2] = {l1, l2};
+                            int packed = 0;
+                            for (int i = 0; i < 2; ++i) {
+                                const int am = abs(m[i]);
+                                packed |= (n[i] * 15 + l[i] * (l[i] + 1) / 2 + am) << (7 * i);
+                                if (m[i] < 0) {
+                                    packed |= 1 << (14 + i);
+                                    if (am & 1) coef = -coef;
+                                }
+                            }
+                            term_idx.push_back(packed);
+                            term_coef.push_back((float)coef);
+                            ++cnt;
+                        }
+                    if (slot < 8) g[4] |= cnt << (4 * slot);
+                    else g[5] = cnt;
+                }
+                for (int i = 0; i < 8; ++i) groups.push_back(g[i]);
+                for (int o : outs) outputs.push_back(o);
             }
     return nd;
 }
