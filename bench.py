@@ -156,7 +156,8 @@ def _pmc_rows(d, counter, kernel_prefix):
     for f in files:
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] == counter and r["Kernel_Name"].startswith(kernel_prefix):
-                out.append((int(r["Dispatch_Id"]), int(r["Grid_Size"]), float(r["Counter_Value"])))
+                out.append((int(r["Dispatch_Id"]), int(r["Grid_Size"]) // int(r["Workgroup_Size"]),
+                            float(r["Counter_Value"])))
     return sorted(out)
 
 
@@ -169,7 +170,7 @@ def traffic_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload="pape
     fs, ws = copy_kib / float(np.mean(cf)), copy_kib / float(np.mean(cw))
     kz = "void mala::k_zb<10>"
     fr, wr = _pmc_rows(fetch_dir, "FETCH_SIZE", kz), _pmc_rows(write_dir, "WRITE_SIZE", kz)
-    pts = [g // 512 * 64 for _, g, _ in fr]
+    pts = [nb * 64 for _, nb, _ in fr]                  # one 64-point tile per workgroup
     fb = [v * 1024.0 * fs for _, _, v in fr]
     wb = [v * 1024.0 * ws for _, _, v in wr]
     snap = WORKLOADS[workload][0]()
