@@ -22,7 +22,9 @@ constexpr int kYMaxWaves = 12;        // plan stride: waves of the widest group
 
 // ------------------------------------------------------------------ Y
 // Column mb of Z^C(A,B) (half rows; the middle row only for mb <= C/2),
-// added to y with weight beta.
+// added to y with weight beta.  The mirrored rows of the unscaled level are
+// used unsigned, their pairs accumulating T <- P - T, with the sign put on
+// the row CG factor in the fold (zy_scale2).
 template <int A, int B, int C, int YN>
 __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane, const float* __restrict__ cg,
                                           int mb, float beta, float (&yr)[YN], float (&yi)[YN]) {
@@ -32,7 +34,7 @@ __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane,
     constexpr int HN = MID ? HR - 1 : HR;
     constexpr int W = C + 1;
     constexpr int NP = zb_pairs(A, B, C);
-    constexpr bool S2 = zb_scale2(A, B, C);
+    constexpr bool S2 = zy_scale2(A, B, C);
     int off1 = half_off(A) * kTile, off2 = half_off(B) * kTile;
     asm volatile("" : "+s"(off1), "+s"(off2));
     lds_float2* l1 = su + lane + off1;
@@ -48,17 +50,18 @@ __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane,
             tr[k] = fmaf(-wi, u2i[ma2], wr * u2r[ma2]);
             ti[k] = fmaf(wi, u2r[ma2], wr * u2i[ma2]);
         } else {
-            tr[k] = fmaf(wr, u2r[ma2], tr[k]);
+            constexpr float sa = zy_alt(A, B, C, ma, ma1) ? -1.f : 1.f;    // R <- P - R on alternating pairs
+            tr[k] = fmaf(wr, u2r[ma2], sa * tr[k]);
             tr[k] = fmaf(-wi, u2i[ma2], tr[k]);
-            ti[k] = fmaf(wr, u2i[ma2], ti[k]);
+            ti[k] = fmaf(wr, u2i[ma2], sa * ti[k]);
             ti[k] = fmaf(wi, u2r[ma2], ti[k]);
         }
     };
     auto column = [&](int mb1, auto first) {
         const int mb2 = mb + D - mb1;
         const float c2 = cg[mb1 * W + mb];
-        const float f1 = flip_odd(S2 ? 1.f : c2, mb1);
-        const float f2 = flip_odd(S2 ? c2 : 1.f, mb2);
+        const float f1 = flip_odd(c2, mb1);          // the scaled level's mirrored rows
+        const float f2 = flip_odd(c2, mb2);
         lds_float2* s1 = l1 + mb1 * kTile;
         lds_float2* m1 = l1 + (A - mb1) * kTile;
         lds_float2* s2 = l2 + mb2 * kTile;
@@ -71,11 +74,15 @@ __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane,
                     const fv2 v = s2[r * (B + 1) * kTile];
                     u2r[r] = S2 ? c2 * v.x : v.x;
                     u2i[r] = S2 ? c2 * v.y : v.y;
-                } else {
+                } else if constexpr (S2) {
                     const fv2 v = m2[(B - r) * (B + 1) * kTile];
                     const float f = (r & 1) ? -f2 : f2;
                     u2r[r] = f * v.x;
                     u2i[r] = -f * v.y;
+                } else {
+                    const fv2 v = m2[(B - r) * (B + 1) * kTile];
+                    u2r[r] = v.x;
+                    u2i[r] = -v.y;
                 }
             }
         });
@@ -87,11 +94,15 @@ __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane,
                     const fv2 v = s1[ma1 * (A + 1) * kTile];
                     wrs[ma1] = S2 ? v.x : c2 * v.x;
                     wis[ma1] = S2 ? v.y : c2 * v.y;
-                } else {
+                } else if constexpr (!S2) {
                     const fv2 v = m1[(A - ma1) * (A + 1) * kTile];
                     const float f = (ma1 & 1) ? -f1 : f1;
                     wrs[ma1] = f * v.x;
                     wis[ma1] = -f * v.y;
+                } else {
+                    const fv2 v = m1[(A - ma1) * (A + 1) * kTile];
+                    wrs[ma1] = v.x;
+                    wis[ma1] = -v.y;
                 }
                 static_for<0, HN + 1>([&](auto mc) {
                     if constexpr (zb_pair_ok(A, B, C, decltype(mc)::value, ma1))
@@ -113,6 +124,7 @@ __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane,
     column(lo, std::true_type{});
 #pragma clang loop unroll(disable)
     for (int mb1 = lo + 1; mb1 <= hi; ++mb1) column(mb1, std::false_type{});
+    const int par = S2 ? hi : mb + D + hi;         // sign parity of the alternating pairs, before the row's
     static_for<0, HR + 1>([&](auto mc) {
         constexpr int ma = decltype(mc)::value;
         constexpr bool MIDROW = MID && ma == HR;
@@ -122,7 +134,8 @@ __device__ __forceinline__ void zy_column(lds_float2* __restrict__ su, int lane,
             constexpr int ma1 = decltype(r1c)::value;
             if constexpr (zb_pair_ok(A, B, C, ma, ma1)) {
                 constexpr int k = zb_pair_index(A, B, C, ma, ma1);
-                const float c1 = cg[ma1 * W + ma];
+                float c1 = cg[ma1 * W + ma];
+                if constexpr (zy_alt(A, B, C, ma, ma1)) c1 = flip_odd(c1, par + zy_alt_row(A, B, C, ma, ma1));
                 if constexpr (zb_pair_doubled(A, B, C, ma, ma1)) {
                     zr2 = fmaf(c1, tr[k], zr2);
                     zi2 = fmaf(c1, ti[k], zi2);

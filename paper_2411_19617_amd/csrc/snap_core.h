@@ -95,4 +95,26 @@ __host__ __device__ constexpr int zb_pair_index(int J1, int J2, int J, int ma, i
             }
     return -1;
 }
+// Scaling side of the dL/du column (the Z contraction of the adjoint).  It
+// keeps the mirrored rows of the unscaled level unsigned: their sign
+// (-1)^(row - column) alternates with the m1' column, so the pairs using them
+// accumulate R <- P - R (a negated addend) and take the sign once, on the
+// row CG factor in the fold.  The per-column scaling cost is then 2
+// multiplies per used row of the scaled level, the smaller one scaled (ties
+// as zb_scale2).
+__host__ __device__ constexpr bool zy_scale2(int A, int B, int C) {
+    const ZbRows r = zb_rows(A, B, C);
+    return r.used2 < r.used1 || (r.used2 == r.used1 && zb_scale2(A, B, C));
+}
+__host__ __device__ constexpr int zy_scale_ops(int A, int B, int C) {
+    const ZbRows r = zb_rows(A, B, C);
+    return 2 * (zy_scale2(A, B, C) ? r.used2 : r.used1);
+}
+// Pair (ma, ma1) uses a mirrored row of the unscaled level, and which row.
+__host__ __device__ constexpr bool zy_alt(int A, int B, int C, int ma, int ma1) {
+    return zy_scale2(A, B, C) ? 2 * ma1 > A : 2 * (ma - ma1 + (A + B - C) / 2) > B;
+}
+__host__ __device__ constexpr int zy_alt_row(int A, int B, int C, int ma, int ma1) {
+    return zy_scale2(A, B, C) ? ma1 : ma - ma1 + (A + B - C) / 2;
+}
 }  // namespace mala

@@ -19,6 +19,7 @@
 
 #include "ace.h"
 #include "mala_internal.h"
+#include "snap_core.h"
 
 namespace mala {
 
@@ -166,8 +167,7 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
                     for (int ma1 = 0; ma1 <= A; ++ma1)
                         if (zb_pair_ok(A, B, C, ma, ma1) && (C % 2 || ma < HR || mb <= HR)) ++t;
                 const int lo = mb + D - B > 0 ? mb + D - B : 0, hi = A < mb + D ? A : mb + D;
-                const int s1 = zb_scale_ops(A, B, C, 1), s2 = zb_scale_ops(A, B, C, 2);
-                cost += (hi - lo + 1) * (4.0 * t + (s1 < s2 ? s1 : s2) + 6.0) + 2.0 * t + 4.0;
+                cost += (hi - lo + 1) * (4.0 * t + zy_scale_ops(A, B, C) + 6.0) + 2.0 * t + 4.0;
             }
             jobs.push_back({cost, C * 32 + mb});
         }
