@@ -190,8 +190,7 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
             constexpr int slot = decltype(sc)::value;
             const int cnt = slot < 8 ? (cnt8 >> (4 * slot)) & 15 : c8;
             float xr = 0.f, xi = 0.f;
-            for (int k = 0; k < cnt; ++k, ++t) {
-                const int2 e = terms[t];
+            auto term = [&](int2 e) {
                 const int pk2 = __builtin_amdgcn_readfirstlane(e.x);
                 const float cf = __int_as_float(__builtin_amdgcn_readfirstlane(e.y));
                 const float2 a = sA[pk2 & 127][lane], b = sA[(pk2 >> 7) & 127][lane];
@@ -199,7 +198,25 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
                 const float by = (pk2 & (1 << 15)) ? -b.y : b.y;
                 xr = fmaf(cf, a.x * b.x - ay * by, xr);
                 xi = fmaf(cf, a.x * by + ay * b.x, xi);
+            };
+            // four terms per step: their table loads and LDS reads are issued
+            // together, so a step waits once instead of once per term
+            int k = 0;
+            for (; k + 4 <= cnt; k += 4, t += 4) {
+                int2 e[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) e[j] = terms[t + j];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) term(e[j]);
             }
+            if (k + 2 <= cnt) {
+                const int2 e0 = terms[t], e1 = terms[t + 1];
+                term(e0);
+                term(e1);
+                k += 2;
+                t += 2;
+            }
+            if (k < cnt) term(terms[t++]);
             pr[slot] = xr;
             pim[slot] = xi;
         });
