@@ -179,12 +179,24 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
             }
     }
     // rank 3 by groups (p1, p2, l3): P(m3) once, then every n3 of the group
+    // the next group's header is loaded while the current group is formed
+    // (a wave past the last group re-reads group 0, unused)
+    auto header = [&](int gi, int (&h)[6]) {
+        const int* gr = groups + 8 * (gi < n_groups ? gi : 0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) h[i] = gr[i];
+    };
+    int nxt[6] = {0, 0, 0, 0, 0, 0};
+    if (n_groups > 0) header(wave, nxt);
     for (int gi = wave; gi < n_groups; gi += kAceWaves) {
-        const int* gr = groups + 8 * gi;
-        int t = __builtin_amdgcn_readfirstlane(gr[0]);
-        const int l3 = __builtin_amdgcn_readfirstlane(gr[1]);
-        const int o0 = __builtin_amdgcn_readfirstlane(gr[2]), oc = __builtin_amdgcn_readfirstlane(gr[3]);
-        const int cnt8 = __builtin_amdgcn_readfirstlane(gr[4]), c8 = __builtin_amdgcn_readfirstlane(gr[5]);
+        int h[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) h[i] = nxt[i];
+        header(gi + kAceWaves, nxt);
+        int t = __builtin_amdgcn_readfirstlane(h[0]);
+        const int l3 = __builtin_amdgcn_readfirstlane(h[1]);
+        const int o0 = __builtin_amdgcn_readfirstlane(h[2]), oc = __builtin_amdgcn_readfirstlane(h[3]);
+        const int cnt8 = __builtin_amdgcn_readfirstlane(h[4]), c8 = __builtin_amdgcn_readfirstlane(h[5]);
         float pr[9], pim[9];
         static_for<0, 9>([&](auto sc) {
             constexpr int slot = decltype(sc)::value;
