@@ -21,6 +21,7 @@ KB_EV = 8.617333262e-5
 BISECT_TOL = 1e-12
 
 _lib = None
+_lib_path = _LIB
 
 
 def build(force=True):
@@ -34,12 +35,29 @@ def build(force=True):
     return _LIB
 
 
+def build_native(out_dir):
+    """Compile a copy of the oracle tuned for the host it runs on (-O3
+    -march=native; ISO C, so no contraction into FMAs: the arithmetic is the
+    same as the portable build's).  Used to time the CPU baseline on the
+    machine that runs the benchmark; returns the library's path."""
+    path = os.path.join(out_dir, "liboracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", path, "-lm"]
+    subprocess.check_call(cmd)
+    return path
+
+
+def use_library(path):
+    """Load the oracle from another build of the same source (build_native)."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if _lib_path == _LIB and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_lib_path)
         d, i, i64, p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
         L.oracle_cg.restype = d
         L.oracle_cg.argtypes = [i] * 6
@@ -68,6 +86,10 @@ def lib():
         L.oracle_ace_count.argtypes = [i, i]
         L.oracle_ace.restype = i
         L.oracle_ace.argtypes = [p, i, p, p, d, i, i, p, i64, p, i]
+        L.oracle_ace_gcg4.restype = d
+        L.oracle_ace_gcg4.argtypes = [i] * 9
+        L.oracle_ace4.restype = i
+        L.oracle_ace4.argtypes = [p, i, p, p, d, i, i, p, i, p, i64, p, i]
         L.oracle_dcayley_klein.argtypes = [d, d, d, d, p, p]
         L.oracle_dcutoff.restype = d
         L.oracle_dcutoff.argtypes = [d, d]
@@ -236,6 +258,67 @@ def ace_radial(n, r, rcut):
 
 def ace_count(nmax, lmax):
     return lib().oracle_ace_count(int(nmax), int(lmax))
+
+
+def ace_gcg4(l, L, m):
+    """Generalized Clebsch-Gordan coefficient of four angular momenta l with
+    the intermediate coupling L ((l1 l2) L, (l3 l4) L -> 0) at projections m."""
+    return lib().oracle_ace_gcg4(*[int(x) for x in l], int(L), *[int(x) for x in m])
+
+
+def ace4_set(nmax4, lmax4, tol=1e-9):
+    """Rank-4 grid ACE descriptors (Eq. ace_grid with four factors), one element:
+    multisets of four keys p = n (lmax4+1) + l (n < nmax4, l <= lmax4),
+    p1 <= p2 <= p3 <= p4, with l1+l2+l3+l4 even (real and parity-even), each
+    coupled as ((p1 p2) L, (p3 p4) L) for every L allowed by both triangles.
+    Where keys repeat, the A's of equal keys are the same numbers, so a
+    coupling defines the invariant of its coefficients summed over the
+    permutations that exchange equal keys; for each multiset the couplings are
+    taken in increasing L and kept when that invariant is linearly independent
+    of the ones kept before it (the paper requires the rank >= 4 set to be
+    free of redundant descriptors).  Returns [(p1, p2, p3, p4, L), ...] in
+    output order."""
+    import itertools
+    nk = nmax4 * (lmax4 + 1)
+    out = []
+    for ps in itertools.combinations_with_replacement(range(nk), 4):
+        ls = [p % (lmax4 + 1) for p in ps]
+        if sum(ls) % 2:
+            continue
+        perms = [q for q in itertools.permutations(range(4)) if all(ps[q[i]] == ps[i] for i in range(4))]
+        kept = []
+        for L in range(max(abs(ls[0] - ls[1]), abs(ls[2] - ls[3])), min(ls[0] + ls[1], ls[2] + ls[3]) + 1):
+            T = np.zeros([2 * l + 1 for l in ls])
+            for m1 in range(-ls[0], ls[0] + 1):
+                for m2 in range(-ls[1], ls[1] + 1):
+                    for m3 in range(-ls[2], ls[2] + 1):
+                        m4 = -m1 - m2 - m3
+                        if abs(m4) <= ls[3]:
+                            T[m1 + ls[0], m2 + ls[1], m3 + ls[2], m4 + ls[3]] = ace_gcg4(ls, L, (m1, m2, m3, m4))
+            v = sum(np.transpose(T, q) for q in perms).ravel() / len(perms)
+            M = np.array(kept + [v])
+            sv = np.linalg.svd(M, compute_uv=False)
+            if np.sum(sv > tol * max(1.0, sv[0])) > len(kept):
+                kept.append(v)
+                out.append(tuple(ps) + (L,))
+    return out
+
+
+def ace4(snap, rcut, nmax4, lmax4, points=None, nthreads=0):
+    """Rank-4 grid ACE descriptors [n_pts][len(ace4_set)] (one element)."""
+    desc = np.ascontiguousarray(np.array(ace4_set(nmax4, lmax4), dtype=np.int32).reshape(-1, 5))
+    if points is None:
+        points = np.arange(snap.n_points, dtype=np.int64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    L = _f64(snap.L)
+    pos = _f64(np.mod(snap.positions, L))
+    N = np.ascontiguousarray(snap.N, dtype=np.int32)
+    out = np.zeros((pts.shape[0], desc.shape[0]))
+    if desc.shape[0] and lib().oracle_ace4(_ptr(pos), pos.shape[0], _ptr(L), _ptr(N), float(rcut), int(nmax4),
+                                           int(lmax4), _ptr(desc), desc.shape[0], _ptr(pts), pts.shape[0],
+                                           _ptr(out), int(nthreads)) < 0:
+        raise RuntimeError("oracle neighbour list overflow")
+    return out
 
 
 def ace(snap, rcut, nmax, lmax, points=None, nthreads=0):

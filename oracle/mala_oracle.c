@@ -494,6 +494,35 @@ int oracle_ace_count(int nmax, int lmax)
     return nmax + (lmax + 1) * nmax * (nmax + 1) / 2 + n3;
 }
 
+/* The grid basis A_nlm (Eq. grid_base) of flat grid point p: A[n*nl + l*l + l + m]
+ * for n < nmax, l <= lmax, nl = (lmax+1)^2.  Returns the neighbour count, or
+ * -1 if it exceeds max_nbr (disp holds 3*max_nbr doubles). */
+static int ace_point_basis(const double *pos, int n_atoms, const double *L, const int *N, double rcut, int nmax,
+                           int lmax, int64_t p, double *disp, int max_nbr, cplx *A)
+{
+    int nl = (lmax + 1) * (lmax + 1);
+    int cnt = oracle_neighbours(pos, n_atoms, L, N, rcut, p, disp, max_nbr);
+    if (cnt > max_nbr) return -1;
+    for (int i = 0; i < nmax * nl; i++) A[i] = 0.0;
+    for (int n = 0; n < nmax; n++)                  /* the grid point's own delta */
+        A[n * nl] = ((n & 1) ? -1.0 : 1.0) / sqrt(4.0 * OR_PI);
+    for (int k = 0; k < cnt; k++) {
+        double dx = disp[3 * k], dy = disp[3 * k + 1], dz = disp[3 * k + 2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r == 0.0) {                               /* an atom on the point: l = 0 only */
+            for (int n = 0; n < nmax; n++)
+                A[n * nl] += oracle_ace_radial(n, 0.0, rcut) / sqrt(4.0 * OR_PI);
+            continue;
+        }
+        for (int l = 0; l <= lmax; l++)
+            for (int m = -l; m <= l; m++) {
+                cplx y = oracle_ylm(l, m, dx, dy, dz);
+                for (int n = 0; n < nmax; n++) A[n * nl + l * l + l + m] += oracle_ace_radial(n, r, rcut) * y;
+            }
+    }
+    return cnt;
+}
+
 /* Descriptors at the listed flat grid points; out is [n_pts][count]. */
 int oracle_ace(const double *pos, int n_atoms, const double *L, const int *N, double rcut, int nmax,
                int lmax, const int64_t *pts, int64_t n_pts, double *out, int nthreads)
@@ -514,27 +543,9 @@ int oracle_ace(const double *pos, int n_atoms, const double *L, const int *N, do
 #pragma omp for schedule(dynamic, 16)
 #endif
         for (int64_t q = 0; q < n_pts; q++) {
-            int cnt = oracle_neighbours(pos, n_atoms, L, N, rcut, pts[q], disp, max_nbr);
-            if (cnt > max_nbr) {
+            if (ace_point_basis(pos, n_atoms, L, N, rcut, nmax, lmax, pts[q], disp, max_nbr, A) < 0) {
                 overflow = 1;
                 continue;
-            }
-            for (int i = 0; i < nmax * nl; i++) A[i] = 0.0;
-            for (int n = 0; n < nmax; n++)                  /* the grid point's own delta */
-                A[n * nl] = ((n & 1) ? -1.0 : 1.0) / sqrt(4.0 * OR_PI);
-            for (int k = 0; k < cnt; k++) {
-                double dx = disp[3 * k], dy = disp[3 * k + 1], dz = disp[3 * k + 2];
-                double r = sqrt(dx * dx + dy * dy + dz * dz);
-                if (r == 0.0) {                               /* an atom on the point: l = 0 only */
-                    for (int n = 0; n < nmax; n++)
-                        A[n * nl] += oracle_ace_radial(n, 0.0, rcut) / sqrt(4.0 * OR_PI);
-                    continue;
-                }
-                for (int l = 0; l <= lmax; l++)
-                    for (int m = -l; m <= l; m++) {
-                        cplx y = oracle_ylm(l, m, dx, dy, dz);
-                        for (int n = 0; n < nmax; n++) A[n * nl + l * l + l + m] += oracle_ace_radial(n, r, rcut) * y;
-                    }
             }
             double *o = out + q * nd;
             int d = 0;
@@ -564,6 +575,77 @@ int oracle_ace(const double *pos, int n_atoms, const double *L, const int *N, do
                             }
                         o[d++] = creal(s);
                     }
+        }
+        free(disp);
+        free(A);
+    }
+    return overflow ? -1 : 0;
+}
+
+/* Rank 4 (Eq. ace_grid with N = 4): the generalized Clebsch-Gordan
+ * coefficient of the coupling tree ((l1 l2) L, (l3 l4) L) -> 0,
+ *   C(m; L) = <l1 m1 l2 m2 | L M> <l3 m3 l4 m4 | L, -M> <L M L, -M | 0 0>,
+ *   M = m1 + m2 = -(m3 + m4),  <L M L, -M | 0 0> = (-1)^(L-M) / sqrt(2L+1),
+ * the intermediate coupling L being the one entry of the multiset L of the
+ * equation for four factors (zero unless m1+m2+m3+m4 = 0). */
+double oracle_ace_gcg4(int l1, int l2, int l3, int l4, int L, int m1, int m2, int m3, int m4)
+{
+    if (m1 + m2 + m3 + m4 != 0) return 0.0;
+    int M = m1 + m2;
+    if (abs(M) > L) return 0.0;
+    double c12 = oracle_cg(2 * l1, 2 * m1, 2 * l2, 2 * m2, 2 * L, 2 * M);
+    double c34 = oracle_cg(2 * l3, 2 * m3, 2 * l4, 2 * m4, 2 * L, -2 * M);
+    return c12 * c34 * (((L - M) & 1) ? -1.0 : 1.0) / sqrt(2.0 * L + 1.0);
+}
+
+/* Rank-4 descriptors B = sum over m1..m4 of C(m; L) A_{n1 l1 m1} A_{n2 l2 m2}
+ * A_{n3 l3 m3} A_{n4 l4 m4} at the listed flat grid points, for the n_desc
+ * descriptors desc[5k..5k+4] = (p1, p2, p3, p4, L) with key p = n (lmax+1) + l
+ * (the set itself, which couplings are kept, is chosen by the caller);
+ * out is [n_pts][n_desc]. */
+int oracle_ace4(const double *pos, int n_atoms, const double *L, const int *N, double rcut, int nmax, int lmax,
+                const int *desc, int n_desc, const int64_t *pts, int64_t n_pts, double *out, int nthreads)
+{
+    const int max_nbr = 4096;
+    int nl = (lmax + 1) * (lmax + 1);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int overflow = 0;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        double *disp = malloc(sizeof(double) * 3 * max_nbr);
+        cplx *A = malloc(sizeof(cplx) * nmax * nl);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t q = 0; q < n_pts; q++) {
+            if (ace_point_basis(pos, n_atoms, L, N, rcut, nmax, lmax, pts[q], disp, max_nbr, A) < 0) {
+                overflow = 1;
+                continue;
+            }
+            for (int k = 0; k < n_desc; k++) {
+                const int *d = desc + 5 * k;
+                int n[4], l[4];
+                for (int i = 0; i < 4; i++) {
+                    n[i] = d[i] / (lmax + 1);
+                    l[i] = d[i] % (lmax + 1);
+                }
+                cplx s = 0.0;
+                for (int m1 = -l[0]; m1 <= l[0]; m1++)
+                    for (int m2 = -l[1]; m2 <= l[1]; m2++)
+                        for (int m3 = -l[2]; m3 <= l[2]; m3++) {
+                            int m4 = -m1 - m2 - m3;
+                            if (abs(m4) > l[3]) continue;
+                            double c = oracle_ace_gcg4(l[0], l[1], l[2], l[3], d[4], m1, m2, m3, m4);
+                            if (c == 0.0) continue;
+                            s += c * A[n[0] * nl + l[0] * l[0] + l[0] + m1] * A[n[1] * nl + l[1] * l[1] + l[1] + m2] *
+                                 A[n[2] * nl + l[2] * l[2] + l[2] + m3] * A[n[3] * nl + l[3] * l[3] + l[3] + m4];
+                        }
+                out[q * n_desc + k] = creal(s);
+            }
         }
         free(disp);
         free(A);

@@ -337,6 +337,29 @@ def test_mlp_matches_numpy_chain():
         assert np.allclose(oracle.mlp(B, net), ref, rtol=1e-13, atol=1e-14)
 
 
+@pytest.mark.parametrize("out_act", [1, 0])
+def test_mlp_hand_built_network(out_act):
+    """A 3-2-2-2 network evaluated by hand (Eq. ffnn with the input
+    standardisation and the affine output transform): every bias, the slope
+    of a negative unit, the input scaler, the output transform and the
+    output-activation flag change the expected values below."""
+    import mala_synth
+    net = mala_synth.make_net([3, 2, 2, 2], 1, 2, output_activation=out_act, with_input_scaler=False,
+                              egrid=(-5.0, 0.1, 2))
+    net["in_mean"], net["in_std"] = np.array([1.0, 0.0, 1.0]), np.array([1.0, 2.0, 2.0])
+    net["W"] = [np.array([[1.0, -1.0, 2.0], [-2.0, -3.0, 1.0]]), np.array([[1.0, 2.0], [-1.0, 1.0]]),
+                np.array([[2.0, 0.0], [1.0, -4.0]])]
+    net["b"] = [np.array([0.5, -0.25]), np.array([-1.0, 0.5]), np.array([0.25, -1.0])]
+    net["out_scale"], net["out_shift"] = np.array([2.0, 0.5]), np.array([0.1, 0.2])
+    net["slope"] = 0.01
+    # x0 = (B - mean)/std = (0, 1, 1); layer 1: z = (1.5, -2.25) -> (1.5, -0.0225);
+    # layer 2: z = (0.455, -1.0225) -> (0.455, -0.010225); layer 3: z = (1.16, -0.5041),
+    # -> (1.16, -0.005041) with the activation on the output; d = s y + c
+    expect = [2.42, 0.1974795] if out_act else [2.42, -0.05205]
+    got = oracle.mlp(np.array([[1.0, 2.0, 3.0]]), net)
+    np.testing.assert_allclose(got[0], expect, rtol=1e-14, atol=1e-15)
+
+
 def test_dos_is_scaled_sum():
     rng = np.random.default_rng(2)
     ld = rng.uniform(size=(50, 17))
@@ -811,6 +834,143 @@ def test_ace_rotation_inversion_permutation_invariance():
     Bi = oracle.ace(_iso_snap(-pos), 4.67, 4, 4, np.array([0]))[0]
     Bp = oracle.ace(_iso_snap(pos[::-1]), 4.67, 4, 4, np.array([0]))[0]
     sc = np.max(np.abs(B))
+    assert np.max(np.abs(Br - B)) <= 1e-12 * sc
+    assert np.max(np.abs(Bi - B)) <= 1e-12 * sc
+    assert np.max(np.abs(Bp - B)) <= 1e-12 * sc
+
+
+# ---------------------------------------------------------------- grid ACE, rank 4
+def _invariant_count_by_weights(ls):
+    """Independent count of the rotation invariants of a product of four
+    spherical-harmonic sets in which equal (n, l) keys are the same factor:
+    for the representation of the symmetrised product, the multiplicity of
+    the trivial representation is (number of weight states with M = 0) -
+    (number with M = 1).  The states are, per distinct key repeated k times
+    with angular momentum l, the multisets of k projections in -l..l."""
+    import collections
+    import itertools
+    total = collections.Counter({0: 1})
+    for key, k in collections.Counter(ls).items():
+        l = key[1]
+        sums = collections.Counter(sum(c) for c in itertools.combinations_with_replacement(range(-l, l + 1), k))
+        nxt = collections.Counter()
+        for a, ca in total.items():
+            for b, cb in sums.items():
+                nxt[a + b] += ca * cb
+        total = nxt
+    return total[0] - total[1]
+
+
+@pytest.mark.parametrize("nmax4,lmax4", [(1, 1), (1, 2), (2, 2), (3, 2), (2, 3)])
+def test_ace4_set_size_equals_independent_invariant_count(nmax4, lmax4):
+    """The non-redundant rank-4 set has, for every multiset of keys with an
+    even l-sum, exactly as many descriptors as there are independent
+    rotation invariants of that symmetrised product (counted from weights
+    alone, without any coupling coefficient)."""
+    import collections
+    import itertools
+    got = collections.Counter(d[:4] for d in oracle.ace4_set(nmax4, lmax4))
+    keys = [(n, l) for n in range(nmax4) for l in range(lmax4 + 1)]
+    expect = 0
+    for ps in itertools.combinations_with_replacement(range(len(keys)), 4):
+        ks = [keys[p] for p in ps]
+        if sum(l for _, l in ks) % 2:
+            continue
+        c = _invariant_count_by_weights(ks)
+        assert got.get(tuple(ps), 0) == c, (ps, got.get(tuple(ps), 0), c)
+        expect += c
+    assert len(oracle.ace4_set(nmax4, lmax4)) == expect
+
+
+def test_ace4_gcg_against_sympy_cg():
+    """Generalized Clebsch-Gordan coefficient of the coupling tree
+    ((l1 l2) L, (l3 l4) L) -> 0 from sympy's ordinary ones."""
+    from sympy.physics.quantum.cg import CG
+    rng = np.random.default_rng(8)
+    for _ in range(60):
+        ls = rng.integers(0, 4, size=4)
+        lo, hi = max(abs(ls[0] - ls[1]), abs(ls[2] - ls[3])), min(ls[0] + ls[1], ls[2] + ls[3])
+        if lo > hi:
+            continue
+        L = int(rng.integers(lo, hi + 1))
+        m = [int(rng.integers(-l, l + 1)) for l in ls[:3]]
+        m.append(-sum(m))
+        if abs(m[3]) > ls[3]:
+            continue
+        M = m[0] + m[1]
+        ref = 0.0
+        if abs(M) <= L:
+            ref = float(CG(int(ls[0]), m[0], int(ls[1]), m[1], L, M).doit() * CG(int(ls[2]), m[2], int(ls[3]), m[3], L, -M).doit()
+                        * CG(L, M, L, -M, 0, 0).doit())
+        assert abs(oracle.ace_gcg4(ls, L, m) - ref) < 1e-14
+
+
+def test_ace4_empty_neighbourhood_single_atom_and_L0_product():
+    """No atoms: only all-l = 0 descriptors are nonzero, prod (-1)^n / (4 pi)^2.
+    One atom at distance r, all l > 0: two spherical harmonics of one
+    direction couple to sqrt((2a+1)(2b+1)/(4 pi (2L+1))) <a0 b0|L0> Y_L, so
+    B = prod R_n c12 c34 (-1)^L sqrt(2L+1) / (4 pi).  Any point, L = 0: the
+    coupling factorises into two rank-2 invariants,
+    B = (-1)^(l1+l3) / sqrt((2 l1+1)(2 l3+1)) B2(p1 p2) B2(p3 p4)."""
+    from sympy.physics.quantum.cg import CG
+    nmax4, lmax4 = 3, 2
+    desc = oracle.ace4_set(nmax4, lmax4)
+    nl = lmax4 + 1
+    B0 = oracle.ace4(_iso_snap([[15.0, 15.0, 15.0]]), 4.67, nmax4, lmax4, np.array([0]))[0]
+    for v, d in zip(B0, desc):
+        ref = np.prod([(-1) ** (p // nl) for p in d[:4]]) / (4 * np.pi) ** 2 if all(p % nl == 0 for p in d[:4]) else 0.0
+        assert abs(v - ref) < 1e-15
+    dvec = np.array([0.9, 1.3, -1.6])
+    r = np.linalg.norm(dvec)
+    R = [oracle.ace_radial(n, r, 4.67) for n in range(nmax4)]
+    B1 = oracle.ace4(_iso_snap([dvec]), 4.67, nmax4, lmax4, np.array([0]))[0]
+    checked = 0
+    for v, d in zip(B1, desc):
+        ls = [p % nl for p in d[:4]]
+        if min(ls) == 0:
+            continue
+        L = d[4]
+        c = [np.sqrt((2 * a + 1) * (2 * b + 1) / (4 * np.pi * (2 * L + 1))) * float(CG(a, 0, b, 0, L, 0).doit())
+             for a, b in ((ls[0], ls[1]), (ls[2], ls[3]))]
+        ref = np.prod([R[p // nl] for p in d[:4]]) * c[0] * c[1] * (-1) ** L * np.sqrt(2 * L + 1) / (4 * np.pi)
+        assert abs(v - ref) < 1e-13
+        checked += 1
+    assert checked > 10
+    rng = np.random.default_rng(4)
+    pos = rng.normal(scale=1.8, size=(6, 3))
+    s = _iso_snap(pos)
+    B4 = oracle.ace4(s, 4.67, nmax4, lmax4, np.array([0]))[0]
+    B = oracle.ace(s, 4.67, nmax4, lmax4, np.array([0]))[0]
+    r2 = {}
+    k = nmax4
+    for l in range(lmax4 + 1):
+        for n1 in range(nmax4):
+            for n2 in range(n1, nmax4):
+                r2[(n1 * nl + l, n2 * nl + l)] = B[k]
+                k += 1
+    n0 = 0
+    for v, d in zip(B4, desc):
+        if d[4] != 0:
+            continue
+        l1, l3 = d[0] % nl, d[2] % nl
+        ref = (-1) ** (l1 + l3) / np.sqrt((2 * l1 + 1) * (2 * l3 + 1)) * r2[(d[0], d[1])] * r2[(d[2], d[3])]
+        assert abs(v - ref) <= 1e-13 * max(1.0, abs(ref))
+        n0 += 1
+    assert n0 > 10
+
+
+def test_ace4_rotation_inversion_permutation_invariance():
+    rng = np.random.default_rng(22)
+    pos = rng.normal(scale=1.7, size=(8, 3))
+    pos = pos[np.linalg.norm(pos, axis=1) < 4.5]
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    args = (4.67, 3, 2, np.array([0]))
+    B = oracle.ace4(_iso_snap(pos), *args)[0]
+    Br = oracle.ace4(_iso_snap(pos @ q.T), *args)[0]
+    Bi = oracle.ace4(_iso_snap(-pos), *args)[0]
+    Bp = oracle.ace4(_iso_snap(pos[::-1]), *args)[0]
+    sc = np.max(np.abs(B))
+    assert sc > 0
     assert np.max(np.abs(Br - B)) <= 1e-12 * sc
     assert np.max(np.abs(Bi - B)) <= 1e-12 * sc
     assert np.max(np.abs(Bp - B)) <= 1e-12 * sc
