@@ -222,6 +222,21 @@ mala_status mala_integrate(mala_ctx* ctx, const float* ldos, int64_t n_pts, doub
                            const mala_egrid* eg, double T_kelvin, double n_electrons,
                            double* dos_out, double* density_out, mala_result* result);
 
+/* mala_integrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results (bit for bit) as mala_integrate, but
+ * its scratch (2048 FP64 partial rows of 256 energies plus 256 FP64 weights,
+ * 4 MiB + 2 KiB) is a fixed device array of the library, one per GPU, held
+ * until the process ends and looked up once per device by mala_create.  It
+ * calls no hipMalloc/hipFree and records no profiling events.  Every n_pts
+ * fits (points are split over at most 2048 partial rows); eg->n above 256 is
+ * rejected (MALA_E_UNSUPPORTED) as in mala_integrate.  All calls on one GPU
+ * share that scratch: calls that overlap on one GPU (different streams or
+ * contexts without ordering between them) race and give wrong results.     */
+mala_status mala_integrate_noalloc(mala_ctx* ctx, const float* ldos, int64_t n_pts, double dV,
+                                   const mala_egrid* eg, double T_kelvin, double n_electrons,
+                                   double* dos_out, double* density_out, mala_result* result);
+
 /* Whole path, fused: descriptors of every grid point (cached as B in
  * device memory), network with the DOS reduced in the epilogue (the full
  * LDOS is never stored), Fermi level, band energy, entropy and density.

@@ -90,6 +90,7 @@ def lib():
             ("mala_ldos_infer", [p, p, p, i64, p]),
             ("mala_ldos_vjp", [p, p, p, p, i64, p]),
             ("mala_integrate", [p, p, i64, d, ctypes.POINTER(EGrid), d, d, p, p, p]),
+            ("mala_integrate_noalloc", [p, p, i64, d, ctypes.POINTER(EGrid), d, d, p, p, p]),
             ("mala_predict", [p, p, p, i32, ctypes.POINTER(CellGrid), d, i32, ctypes.POINTER(EGrid), d, d,
                               p, p, p, p]),
             ("mala_profile_enable", [p, i32]),
@@ -336,6 +337,16 @@ class Context:
         res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=self.torch_device)
         _check(lib().mala_integrate(self.handle, _ptr(ldos), n, float(dV), ctypes.byref(eg), float(T),
                                     float(n_electrons), _ptr(dos), _ptr(dens), _ptr(res)))
+        return dos, dens, res
+
+    def mala_integrate_noalloc(self, ldos, dV, egrid, T, n_electrons, dos, dens, res):
+        """mala_integrate into caller-made outputs through the entry point that
+        allocates nothing (its scratch is the library's fixed device array)."""
+        self._sync_stream()
+        n = int(ldos.shape[0])
+        eg = _egrid(egrid)
+        _check(lib().mala_integrate_noalloc(self.handle, _ptr(ldos), n, float(dV), ctypes.byref(eg), float(T),
+                                            float(n_electrons), _ptr(dos), _ptr(dens), _ptr(res)))
         return dos, dens, res
 
     def mala_predict(self, weights, positions, L, N, rcut, twojmax, egrid, T, n_electrons, density=True,

@@ -20,7 +20,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmala.so")
 SOURCES = ["api.cpp", "serve.cpp", "tables.cpp", "bin.hip", "bispectrum.hip", "gauss.hip", "ace.hip", "mlp.hip", "mlp_vjp.hip", "adjoint_y.hip", "adjoint_y10_0.hip", "adjoint_y10_1.hip",
            "adjoint_y10_2.hip", "adjoint_y10_3.hip", "adjoint_dedr.hip",
-           "fermi.hip"]
+           "fermi.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

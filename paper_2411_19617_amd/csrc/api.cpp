@@ -310,6 +310,12 @@ mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* 
     return MALA_OK;
 }
 
+// Partial rows of the stored-LDOS column sums: one per point up to
+// kIntegrateMaxParts (the same partition in both integrate entry points).
+int integrate_parts(int64_t n_pts) {
+    return n_pts < kIntegrateMaxParts ? (int)(n_pts > 0 ? n_pts : 1) : kIntegrateMaxParts;
+}
+
 mala_status check_egrid(const mala_egrid* eg, double T, double ne) {
     if (!eg) return fail(MALA_E_INVALID_ARG, "egrid is NULL");
     if (eg->n < 2 || eg->n > kMlpMaxOut) return fail(MALA_E_UNSUPPORTED, "energy grid size must be 2..256");
@@ -317,6 +323,17 @@ mala_status check_egrid(const mala_egrid* eg, double T, double ne) {
         return fail(MALA_E_INVALID_ARG, "bad energy grid");
     if (!(T > 0.0) || !isfinite(T)) return fail(MALA_E_INVALID_ARG, "temperature must be positive");
     if (!(ne > 0.0) || !isfinite(ne)) return fail(MALA_E_INVALID_ARG, "n_electrons must be positive");
+    return MALA_OK;
+}
+
+mala_status check_integrate_args(mala_ctx* c, const float* ldos, int64_t n_pts, double dV, const mala_egrid* eg,
+                                 double T, double ne, double* dos_out, mala_result* result) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    mala_status st = check_egrid(eg, T, ne);
+    if (st) return st;
+    if (n_pts < 0) return fail(MALA_E_INVALID_ARG, "n_pts < 0");
+    if (!(dV > 0.0) || !isfinite(dV)) return fail(MALA_E_INVALID_ARG, "dV must be positive");
+    if (!dos_out || !result || (n_pts > 0 && !ldos)) return fail(MALA_E_INVALID_ARG, "NULL buffer");
     return MALA_OK;
 }
 
@@ -376,6 +393,10 @@ mala_status mala_create(int32_t device, void* stream, mala_ctx** out) {
     if (e == hipSuccess) e = hipMemset(c->err, 0, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->li_coef, sizeof(double) * kLiCoef);
     if (e == hipSuccess) e = hipMalloc(&c->win, sizeof(WindowRec));
+    if (e == hipSuccess) {      // this device's fixed scratch of mala_integrate_noalloc
+        double* scr = nullptr;
+        e = scratch_device_ptr(device, &scr);
+    }
     if (e == hipSuccess) {
         double coef[kLiCoef];
         polylog_coefficients(coef);
@@ -825,14 +846,10 @@ mala_status mala_ldos_vjp(mala_ctx* c, const mala_weights* w, const float* B, co
 
 mala_status mala_integrate(mala_ctx* c, const float* ldos, int64_t n_pts, double dV, const mala_egrid* eg,
                            double T, double ne, double* dos_out, double* density_out, mala_result* result) {
-    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
-    mala_status st = check_egrid(eg, T, ne);
+    mala_status st = check_integrate_args(c, ldos, n_pts, dV, eg, T, ne, dos_out, result);
     if (st) return st;
-    if (n_pts < 0) return fail(MALA_E_INVALID_ARG, "n_pts < 0");
-    if (!(dV > 0.0) || !isfinite(dV)) return fail(MALA_E_INVALID_ARG, "dV must be positive");
-    if (!dos_out || !result || (n_pts > 0 && !ldos)) return fail(MALA_E_INVALID_ARG, "NULL buffer");
     DeviceGuard g(c->device);
-    const int nb = n_pts < 2048 ? (int)(n_pts > 0 ? n_pts : 1) : 2048;
+    const int nb = integrate_parts(n_pts);
     HIP_TRY(ensure(c->partials, (size_t)nb * kMlpMaxOut));
     HIP_TRY(ensure(c->fermi_w, kMlpMaxOut));
     HIP_TRY(staged(c, MALA_STAGE_INTEGRATE, n_pts,
@@ -845,6 +862,28 @@ mala_status mala_integrate(mala_ctx* c, const float* ldos, int64_t n_pts, double
         HIP_TRY(staged(c, MALA_STAGE_INTEGRATE, n_pts, [&] {
             return launch_density_from_ldos(c->stream, ldos, n_pts, eg->n, c->fermi_w.p, result, density_out);
         }));
+    return MALA_OK;
+}
+
+mala_status mala_integrate_noalloc(mala_ctx* c, const float* ldos, int64_t n_pts, double dV, const mala_egrid* eg,
+                                   double T, double ne, double* dos_out, double* density_out, mala_result* result) {
+    mala_status st = check_integrate_args(c, ldos, n_pts, dV, eg, T, ne, dos_out, result);
+    if (st) return st;
+    const int nb = integrate_parts(n_pts);
+    if ((size_t)nb * kMlpMaxOut + kMlpMaxOut > (size_t)kNoallocScratchDoubles)
+        return fail(MALA_E_UNSUPPORTED, "mala_integrate_noalloc: partial rows exceed the fixed scratch");
+    DeviceGuard g(c->device);
+    double* scr = nullptr;
+    HIP_TRY(scratch_device_ptr(c->device, &scr));      // looked up by mala_create: no allocation here
+    double* partials = scr;
+    double* weights = scr + (size_t)kIntegrateMaxParts * kMlpMaxOut;
+    // every partial row is written by the column sums, the weights by the
+    // Fermi pass: nothing has to start at zero
+    HIP_TRY(launch_ldos_colsum(c->stream, ldos, n_pts, eg->n, partials, nb));
+    HIP_TRY(launch_fermi(c->stream, partials, nb, eg->n, dV, eg->e0, eg->de, kBoltzmannEv * T, ne, dos_out, weights,
+                         result, nullptr, c->li_coef));
+    if (density_out && n_pts > 0)
+        HIP_TRY(launch_density_from_ldos(c->stream, ldos, n_pts, eg->n, weights, result, density_out));
     return MALA_OK;
 }
 

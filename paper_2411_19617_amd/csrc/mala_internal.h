@@ -22,6 +22,11 @@ constexpr int kMaxYStride = 64;      // per-wave unit list stride of the descrip
 constexpr int kMlpMaxIn = 128;       // padded input width limit
 constexpr int kMlpMaxHidden = 512;   // hidden width limit
 constexpr int kMlpMaxOut = 256;      // output width limit
+// DOS partial rows of the stored-LDOS reductions (mala_integrate): one per
+// block over a fixed contiguous range of points, at most this many.
+constexpr int kIntegrateMaxParts = 2048;
+// fixed scratch of mala_integrate_noalloc: the partial rows and the weights
+constexpr int kNoallocScratchDoubles = kIntegrateMaxParts * kMlpMaxOut + kMlpMaxOut;
 constexpr double kBoltzmannEv = 8.617333262e-5;
 constexpr float kRfac0 = 0.99363f;
 
@@ -338,6 +343,7 @@ hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_
 
 // Device bytes held by a context's scratch, and releasing them (serving).
 size_t ctx_device_bytes(mala_ctx* c);
+hipError_t scratch_device_ptr(int device, double** out);   // noalloc.hip
 void ctx_trim(mala_ctx* c);
 
 // Host-side tables.
