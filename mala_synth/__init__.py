@@ -303,6 +303,14 @@ def net_to_blob(net):
     return bytes(out)
 
 
+def strided_points(n_total, stride, offset=0):
+    """Systematic sample of flat grid indices: offset, offset + stride, ..."""
+    return np.arange(offset, n_total, stride, dtype=np.int64)
+
+
+SLAB_SAMPLE = (719, 11)     # stride and offset of the slab's systematic sample (65,462 points)
+
+
 def sample_points(n_total, n_sample, seed):
     """Seeded sorted sample of distinct flat grid indices."""
     rng = SplitMix64(seed)

@@ -125,3 +125,22 @@ def test_force_path_composition_matches_oracle(env):
     err = np.max(np.abs(F - Fref)) / np.max(np.abs(Fref))
     log("force path composition rel err %.3e (max |ref| %.3e)" % (err, np.max(np.abs(Fref))))
     assert err <= TOL
+
+
+def test_adjoint_full_grid_launch_across_chunk_seam(env):
+    """The full-grid launch (729,000 points, chunks of 2^19 from point 0) with
+    weights that vanish outside a 4,096-point range straddling the chunk seam
+    at 524,288: its dL/dR is the VJP of that range alone, which the oracle
+    computes; the seam splits the range 2,048 / 2,048 between two launches."""
+    mala, ctx, torch = env
+    s = mala_synth.paper_solid()
+    n, nb = s.n_points, 91
+    b, e = (1 << 19) - 2048, (1 << 19) + 2048
+    gB = np.zeros((n, nb), dtype=np.float32)
+    gB[b:e] = weights(e - b, nb, 41)
+    log("adjoint full grid, weights on", b, e)
+    g = gpu_vjp(env, s, gB, 0, n)
+    ref = oracle.descriptors_vjp(s, gB[b:e].astype(np.float64), np.arange(b, e, dtype=np.int64), nthreads=16)
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    log("  dL/dR rel err %.3e (max |ref| %.3e)" % (err, np.max(np.abs(ref))))
+    assert err <= TOL

@@ -60,11 +60,13 @@ def rel_rows(a, b):
     return float(np.max(num / den))
 
 
-def golden(case):
+def golden(case, snap, net):
+    """Stored oracle values of a whole grid, checked to belong to these inputs."""
+    from tests.golden.make_golden import fingerprint
     path = os.path.join(GOLD, "full_%s.json" % case)
-    if not os.path.exists(path):
-        pytest.skip("golden %s not generated" % case)
-    return json.load(open(path))
+    g = json.load(open(path))
+    assert g["fingerprint"] == fingerprint(snap, net), "golden %s does not match the current inputs" % case
+    return g
 
 
 # ------------------------------------------------------------------ descriptors
@@ -254,7 +256,8 @@ def _check_full(ctx, mala, torch, snap, net, gold, prec, tol_eb_mev, tol_dos, to
 
 
 def test_predict_small_full_grid(ctx, mala, torch):
-    snap, net, gold = mala_synth.small(), mala_synth.small_net(), golden("small")
+    snap, net = mala_synth.small(), mala_synth.small_net()
+    gold = golden("small", snap, net)
     n, r = _check_full(ctx, mala, torch, snap, net, gold, mala.PREC_FP32, 0.01, 1e-6, 1e-4)
     # density at every point against the oracle's density at its own E_F
     ref = oracle.predict(snap, net, EG)
@@ -263,7 +266,8 @@ def test_predict_small_full_grid(ctx, mala, torch):
 
 @pytest.mark.parametrize("case", ["paper_solid", "paper_liquid"])
 def test_predict_paper_scale(ctx, mala, case, torch):
-    snap, net, gold = getattr(mala_synth, case)(), mala_synth.paper_net(), golden(case)
+    snap, net = getattr(mala_synth, case)(), mala_synth.paper_net()
+    gold = golden(case, snap, net)
     n, r = _check_full(ctx, mala, torch, snap, net, gold, mala.PREC_FP32, 0.01, 1e-6, 1e-4)
     assert abs(n.sum() * snap.dV - gold["density_sum_dV"]) <= 1e-6 * gold["density_sum_dV"]
     # density at sampled points: oracle LDOS there, oracle weights at the oracle E_F
@@ -276,7 +280,8 @@ def test_predict_paper_scale(ctx, mala, case, torch):
 
 @pytest.mark.parametrize("case", ["paper_solid", "paper_liquid"])
 def test_predict_precision_form(ctx, mala, case, torch):
-    snap, net, gold = getattr(mala_synth, case)(), mala_synth.paper_net(), golden(case)
+    snap, net = getattr(mala_synth, case)(), mala_synth.paper_net()
+    gold = golden(case, snap, net)
     _check_full(ctx, mala, torch, snap, net, gold, mala.PREC_BF16, 1.0, 5e-2, 5e-2)
 
 

@@ -1,6 +1,18 @@
-"""The 47,066,880-point fcc(111) slab (16,384 atoms, stacking fault, vacuum):
-sampled outputs against the oracle, and properties that hold at any size for
-the whole-grid quantities (the oracle would need ~27 core-hours for them)."""
+"""The 47,066,880-point fcc(111) slab (16,384 atoms, stacking fault, vacuum).
+
+The fused path (mala_predict, 64-point tiles in chunks of 2^19 points) writes
+its descriptors into a caller-owned B cache; its rows are compared with the
+oracle at seeded points and at forced ones (vacuum, surfaces, the fault plane,
+chunk seams, tiles that cross a z-row, the first and last point).  The
+oracle's path over a systematic sample of every 719th point
+(tests/golden/full_slab_sample.json, written by tests/golden/make_golden.py)
+is compared with the GPU network and integration applied to the same rows of
+the cache.  The whole-grid DOS cannot be computed by the oracle (~130 core-hours
+at its rate on this slab); it is checked to equal the sum of the per-row
+network outputs of the cache, and the Fermi level, band energy and entropy
+of that DOS are checked against the oracle's solve of the same DOS."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -11,6 +23,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 EG = mala_synth.EGRID
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def log(*a):
@@ -113,3 +126,133 @@ def test_slab_ldos_sampled_against_oracle(setup):
     err = np.max(np.max(np.abs(g - ld_ref), axis=1) / np.max(np.abs(ld_ref), axis=1))
     log("slab LDOS rel err", err)
     assert err <= 2e-5
+
+
+def forced_rows(snap):
+    """Flat indices of grid points the fused path handles specially."""
+    Nx, Ny, Nz = (int(v) for v in snap.N)
+    h = snap.L[2] / Nz
+    dz = mala_synth.A_AL / np.sqrt(3.0)
+    k_lo, k_hi = int(round(10.0 / h)), int(round((10.0 + 31 * dz) / h))       # outer layers
+    k_fault = int(round((10.0 + 16 * dz) / h))                                 # faulted layer
+    flat = lambda i, j, k: (i * Ny + j) * Nz + k
+    rows = [0, snap.n_points - 1]
+    for k in (0, 3, 25, k_lo - 3, k_lo, k_fault - 1, k_fault, k_fault + 1, k_hi, k_hi + 3, Nz - 1):
+        rows += [flat(5, 7, k), flat(Nx // 2, Ny // 2, k), flat(Nx - 1, Ny - 1, k)]
+    for m in (1, 2, 44, 89):                                # seams of the 2^19-point chunks
+        rows += [m * (1 << 19) - 1, m * (1 << 19), m * (1 << 19) + 1]
+    for r in (1, 98_001, 9_801):                            # tiles crossing a z-row (odd rows)
+        rows += [r * Nz - 1, r * Nz]
+    rows = np.array(sorted(set(int(x) for x in rows if 0 <= x < snap.n_points)), dtype=np.int64)
+    return rows
+
+
+@pytest.fixture(scope="module")
+def fused(setup):
+    """FP32 fused path on the slab with a caller-owned B cache."""
+    import torch
+    mala, ctx, snap, net = setup
+    w = ctx.weights(mala_synth.net_to_blob(net), 0)
+    Bc = torch.empty((snap.n_points, 91), dtype=torch.float32, device="cuda")
+    log("slab fused predict with B cache", snap.name)
+    dos, dens, res = ctx.mala_predict(w, snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, EG, snap.T,
+                                      snap.n_electrons, B_cache=Bc)
+    r = mala.read_result(res)
+    ctx.check_device_errors()
+    log("slab fused result", r)
+    yield w, Bc, dos, dens, r
+    del Bc
+    torch.cuda.empty_cache()
+
+
+def test_slab_fused_cache_rows_against_oracle(setup, fused):
+    """Rows of the fused path's B cache (64-point tiles) and their LDOS."""
+    import torch
+    mala, ctx, snap, net = setup
+    w, Bc, dos, dens, r = fused
+    pts = np.unique(np.concatenate([mala_synth.sample_points(snap.n_points, 256, 31), forced_rows(snap)]))
+    log("slab cache rows:", len(pts))
+    Bref = oracle.descriptors(snap, pts)
+    idx = torch.as_tensor(pts, device="cuda")
+    Bg_t = Bc.index_select(0, idx).contiguous()
+    Bg = Bg_t.cpu().double().numpy()
+    err = np.max(np.abs(Bg - Bref), axis=1) / np.max(np.abs(Bref), axis=1)
+    worst = int(np.argmax(err))
+    log("slab cache B max rel err %.3e at point %d" % (err[worst], pts[worst]))
+    assert err[worst] <= 1e-5
+    ld = ctx.mala_ldos_infer(w, Bg_t, EG[2]).cpu().double().numpy()
+    ld_ref = oracle.mlp(Bref, net)
+    ld_same = oracle.mlp(Bg, net)                 # the network alone, on identical input
+    e_ref = np.max(np.max(np.abs(ld - ld_ref), axis=1) / np.max(np.abs(ld_ref), axis=1))
+    e_same = np.max(np.max(np.abs(ld - ld_same), axis=1) / np.max(np.abs(ld_same), axis=1))
+    log("slab cache LDOS rel err vs oracle %.3e, network alone %.3e" % (e_ref, e_same))
+    assert e_same <= 1e-5
+    assert e_ref <= 2e-5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_slab_sample_rows_against_oracle_path(setup, fused, prec):
+    """The oracle's path over every 719th point against the GPU network and
+    integration applied to the same rows of the fused path's B cache."""
+    import torch
+    mala, ctx, snap, net = setup
+    w32, Bc, dos, dens, r = fused
+    g = json.load(open(os.path.join(GOLD, "full_slab_sample.json")))
+    from tests.golden.make_golden import fingerprint
+    assert g["fingerprint"] == fingerprint(snap, net), "slab sample golden is stale"
+    pts = mala_synth.strided_points(snap.n_points, g["stride"], g["offset"])
+    assert len(pts) == g["n_sample"]
+    w = w32 if prec == 0 else ctx.weights(mala_synth.net_to_blob(net), 1)
+    rows = Bc.index_select(0, torch.as_tensor(pts, device="cuda")).contiguous()
+    ld = ctx.mala_ldos_infer(w, rows, EG[2])
+    gs = g["sample"]
+    D, _, res = ctx.mala_integrate(ld, snap.dV, EG, snap.T, gs["n_electrons"], density=False)
+    rs = mala.read_result(res)
+    D = D.cpu().numpy()
+    Dref = np.array(gs["dos"])
+    atoms = snap.n_atoms * len(pts) / snap.n_points           # atoms the sample stands for
+    e_dos = np.max(np.abs(D - Dref)) / np.max(np.abs(Dref))
+    e_ef = abs(rs["e_fermi"] - gs["e_fermi"])
+    e_eb = abs(rs["e_band"] - gs["e_band"]) / atoms * 1000.0
+    log("slab sample prec %d: DOS %.2e  E_F %.2e eV  E_b %.2e meV/atom" % (prec, e_dos, e_ef, e_eb))
+    assert rs["status"] == 0
+    if prec == 0:
+        assert e_dos <= 1e-6 and e_ef <= 1e-4 and e_eb <= 0.01
+        assert abs(rs["entropy"] - gs["entropy_kb"]) <= 1e-4 * abs(gs["entropy_kb"])
+    else:
+        assert e_eb <= 1.0          # precision form: 1 meV/atom
+
+
+def test_slab_fused_dos_is_sum_of_rows_and_solved_like_oracle(setup, fused):
+    """Whole grid: the fused DOS equals dV times the column sums of the
+    network applied to every row of the B cache (in chunks), and E_F, E_b and
+    the entropy of the fused result equal the oracle's solve of that DOS."""
+    import torch
+    mala, ctx, snap, net = setup
+    w, Bc, dos, dens, r = fused
+    acc = torch.zeros(EG[2], dtype=torch.float64, device="cuda")
+    step = 1 << 22
+    for b in range(0, snap.n_points, step):
+        e = min(b + step, snap.n_points)
+        ld = ctx.mala_ldos_infer(w, Bc[b:e], EG[2])
+        acc += ld.double().sum(dim=0)
+        del ld
+    D_rows = acc.cpu().numpy() * snap.dV
+    D = dos.cpu().numpy()
+    e_sum = np.max(np.abs(D - D_rows)) / np.max(np.abs(D_rows))
+    ref = oracle.fermi(D, EG, snap.T, snap.n_electrons)
+    s_ref, mts_ref = oracle.entropy(D, EG, ref["e_fermi"], snap.T)
+    log("slab fused DOS vs row sums %.2e; E_F %.9f (oracle solve %.9f); E_b %.6f (%.6f)" %
+        (e_sum, r["e_fermi"], ref["e_fermi"], r["e_band"], ref["e_band"]))
+    assert e_sum <= 1e-10
+    assert abs(r["e_fermi"] - ref["e_fermi"]) <= 1e-9
+    assert abs(r["e_band"] - ref["e_band"]) <= 1e-9 * abs(ref["e_band"])
+    assert abs(r["entropy"] - s_ref) <= 1e-8 * abs(s_ref)
+    assert abs(r["e_entropy"] - mts_ref) <= 1e-8 * abs(mts_ref)
+    # the whole-grid DOS against the oracle's estimate from the systematic
+    # sample: a consistency check (the sample's own error), not parity
+    g = json.load(open(os.path.join(GOLD, "full_slab_sample.json")))
+    D_est = np.array(g["estimate"]["dos"])
+    e_est = np.max(np.abs(D - D_est)) / np.max(np.abs(D_est))
+    log("slab DOS vs sample estimate %.3e; E_F %.6f vs %.6f" % (e_est, r["e_fermi"], g["estimate"]["e_fermi"]))
+    assert e_est <= 2e-3 and abs(r["e_fermi"] - g["estimate"]["e_fermi"]) <= 2e-3
