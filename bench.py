@@ -1,14 +1,21 @@
 """Benchmark of the grid-inference path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload paper_solid]
-                    [--precision fp32|bf16] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload slab]
+                    [--no-cpu-baseline] [--serve-requests N] [--no-extras]
 
 A step is one call of the fused path (mala_predict) on one synthetic
 snapshot: atom binning, bispectrum descriptors of every grid point, an E_F
 estimate on a point subsample, the network with the DOS and the energy
-window reduced in its epilogue, Fermi level, band energy, and the density.  Inputs (positions are
-host data by the ABI; the B cache and outputs are preallocated in HBM) are
-in place before the timed region.  Prints one JSON line.
+window reduced in its epilogue, Fermi level, band energy, and the density.
+Inputs (positions are host data by the ABI; the B cache and outputs are
+preallocated in HBM) are in place before the timed region.
+
+The headline is the 47,066,880-point fcc(111) slab (16,384 atoms) with the
+FP32 network; the same line carries the precision form (BF16 network, FP32
+accumulation, FP64 reductions) on the slab, both forms on the 729,000-point
+256-atom solid, the serving streams of both forms, lines outside the
+metric (Gaussian descriptors, both VJPs, grid ACE) and the CPU oracle's
+rate.  Prints one JSON line.
 """
 import argparse
 import json
@@ -55,9 +62,11 @@ def index_counts(tj):
     return n_half, z_terms, b_terms
 
 
-def mean_neighbours(snap, n_sample=4096, seed=99):
-    """Mean number of atom images within rcut over a seeded sample of points."""
-    pts = mala_synth.sample_points(snap.n_points, n_sample, seed)
+def mean_neighbours(snap, n_sample=4096, seed=99, pts=None):
+    """Mean number of atom images within rcut over a seeded sample of points
+    (or over the given flat indices)."""
+    if pts is None:
+        pts = mala_synth.sample_points(snap.n_points, n_sample, seed)
     N, L = snap.N, snap.L
     ijk = np.stack([pts // (N[1] * N[2]), (pts // N[2]) % N[1], pts % N[2]], 1)
     r = ijk * (L / N)
@@ -83,9 +92,35 @@ def flops_per_point(snap, widths):
             "mean_neighbours": nb, "z_terms": z_terms, "b_terms": b_terms, "n_half": n_half}
 
 
+def path_ceiling(fl, precision):
+    """Roofline rate of the whole path in grid points/s: the descriptor work
+    (U and Z/B) at the FP32 vector peak plus the network at the matrix peak
+    of its precision (the reductions are below 0.1% of the work)."""
+    t = (fl["u"] + fl["zb"]) / (PEAK_FP32_VALU_TFLOPS * 1e12) + fl["mlp"] / (PEAK_MFMA_TFLOPS[precision] * 1e12)
+    return 1.0 / t
+
+
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def cpu_baseline(snap, net, n_sample):
+    """The FP64 oracle (built -O3 -march=native for this host) on a seeded
+    sample of the workload's grid points through the whole path; returns the
+    record and the oracle's B and LDOS of the sample for the error check."""
+    import tempfile
+
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    threads = min(16, len(os.sched_getaffinity(0)))          # the host share of one GPU
+    oracle.use_library(oracle.build_native(tempfile.mkdtemp(prefix="oracle_native_")))
     pts = mala_synth.sample_points(snap.n_points, n_sample, 1234)
     t0 = time.time()
     B = oracle.descriptors(snap, pts, nthreads=threads)
@@ -94,9 +129,12 @@ def cpu_baseline(snap, net, n_sample):
     fr = oracle.fermi(D, mala_synth.EGRID, snap.T, snap.n_electrons)
     oracle.density(ld, fr["weights"])
     dt = time.time() - t0
-    return {"value": n_sample / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
-            "sample": "%d seeded grid points of %s through the whole path (descriptors, network, DOS, "
-                      "E_F, E_band, density), %.1f s" % (n_sample, snap.name, dt)}
+    rec = {"value": n_sample / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
+           "sample": "%d seeded grid points of %s (mean %.1f neighbours) through the whole path (descriptors, "
+                     "network, DOS, E_F, E_band, density), %.1f s; oracle built -O3 -march=native, OpenMP over "
+                     "points" % (n_sample, snap.name, mean_neighbours(snap, pts=pts), dt),
+           "host": host_cpu()}
+    return rec, pts, B, ld
 
 
 TRAFFIC_FILES = {"paper_solid": "traffic_k_zb_al256_solid_90c_tj10.txt"}
@@ -278,6 +316,35 @@ def errors_vs_oracle(workload, snap, dos, r, dens):
             "oracle": "tests/golden/full_%s.json (FP64 oracle, all %d points)" % (workload, g["n_points"])}
 
 
+def slab_sample_errors(ctx, snap, w, Bc, dos, r, torch):
+    """The slab against the oracle's path over its systematic sample (every
+    719th point, tests/golden/full_slab_sample.json): the GPU network and
+    integration on the same rows of the fused path's B cache, and the
+    whole-grid DOS against the sample's estimate (a consistency figure)."""
+    path = os.path.join(ROOT, "tests", "golden", "full_slab_sample.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    pts = mala_synth.strided_points(snap.n_points, g["stride"], g["offset"])
+    rows = Bc.index_select(0, torch.as_tensor(pts, device="cuda")).contiguous()
+    ld = ctx.mala_ldos_infer(w, rows, mala_synth.EGRID[2])
+    gs = g["sample"]
+    D, _, res = ctx.mala_integrate(ld, snap.dV, mala_synth.EGRID, snap.T, gs["n_electrons"], density=False)
+    import paper_2411_19617_amd as mala
+    rs = mala.read_result(res)
+    Dref = np.array(gs["dos"])
+    atoms = snap.n_atoms * len(pts) / snap.n_points
+    De = np.array(g["estimate"]["dos"])
+    Dg = dos.cpu().numpy()
+    return {"sample_points": len(pts),
+            "sample_dos_max_rel": float(np.max(np.abs(D.cpu().numpy() - Dref)) / np.max(np.abs(Dref))),
+            "sample_e_fermi_ev": abs(rs["e_fermi"] - gs["e_fermi"]),
+            "sample_e_band_mev_per_atom": abs(rs["e_band"] - gs["e_band"]) * 1000.0 / atoms,
+            "whole_grid_dos_vs_sample_estimate": float(np.max(np.abs(Dg - De)) / np.max(np.abs(De))),
+            "whole_grid_e_fermi_vs_sample_estimate_ev": abs(r["e_fermi"] - g["estimate"]["e_fermi"]),
+            "oracle": "tests/golden/full_slab_sample.json (FP64 oracle, every %dth point)" % g["stride"]}
+
+
 def gaussian_bench(ctx, snap, torch, reps=5):
     """Gaussian descriptors of the whole grid (sigma = grid spacing, cutoff 8
     sigma), outside the metric's step: time per grid and the write rate (the
@@ -409,57 +476,164 @@ def ace_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax=4, lmax=4):
             "tflops": tf, "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS}
 
 
-def serving_bench(mala, prec, n_requests, slots=4, budget_gb=64, seed=5, loads=(0.5, 0.7, 0.9)):
+def serving_bench(mala, prec, reqs, n_main, n_side=200, slots=4, budget_gb=64, loads=(0.5, 0.7, 0.9), seed=5,
+                  inflight_points=0):
     """Poisson streams of the serving mix through the library's request loop.
 
-    The saturation request rate of the mix is measured first (all requests
-    submitted at once); streams then arrive at 0.5, 0.7 and 0.9 x that rate.
-    Latency = completion - arrival (server clock).  The top-level latency
-    fields are those of the 0.7 x stream.
+    At most `inflight_points` grid points run at once (a larger request runs
+    alone), with up to `slots` requests.  Every slot is sized once for the
+    largest request of the mix
+    (mala_server_reserve) and warmed by the `slots` largest requests at once;
+    the allocation counter of the slots must not move after that.  The
+    saturation request rate comes from the first n_side requests submitted
+    at once; the streams then arrive at 0.5, 0.7 and 0.9 x that rate, the
+    0.7 x stream over n_main requests and the others over n_side.  Latency =
+    completion - arrival (server clock).
     """
-    rng = mala_synth.SplitMix64(seed)
-    reqs = [mala_synth.serving_request(rng) for _ in range(n_requests)]
+    rng = mala_synth.SplitMix64(seed + 1000)
     blob = mala_synth.net_to_blob(mala_synth.paper_net())
     sv = mala.Server(blob, prec, hbm_budget=budget_gb << 30, max_inflight=slots)
+    sv.reserve([(r.n_atoms, r.L, r.N, r.rcut, r.twojmax, mala_synth.EGRID, r.T) for r in reqs])
+    sv.set_inflight_points(inflight_points)
 
     def submit(r):
         return sv.submit(r.positions, r.L, r.N, r.rcut, r.twojmax, mala_synth.EGRID, r.T, r.n_electrons)
 
-    for r in reqs[:slots]:                      # warm-up: slot buffers reach their sizes
-        sv.wait(submit(r), 600)
+    big = sorted(reqs, key=lambda r: r.n_points)[-slots:]
+    for t in [submit(r) for r in big]:            # every slot runs once, all at the same time
+        sv.wait(t, 600)
+    st0 = sv.stats()
+    side = reqs[:n_side]
     t0 = time.perf_counter()
-    outs = [sv.wait(t, 600) for t in [submit(r) for r in reqs]]
+    outs = [sv.wait(t, 600) for t in [submit(r) for r in side]]
     sat = time.perf_counter() - t0
-    sat_rate = n_requests / sat
-    pts = sum(r.n_points for r in reqs)
+    sat_rate = len(side) / sat
+    sat_pts = sum(r.n_points for r in side) / sat
     streams = []
     for load in loads:
+        sub = reqs[:n_main] if abs(load - 0.7) < 1e-9 else side
         lam = load * sat_rate
-        gaps = -np.log(1.0 - rng.uniform(n_requests)) / lam
-        arrivals = np.cumsum(gaps)
+        arrivals = np.cumsum(-np.log(1.0 - rng.uniform(len(sub))) / lam)
         tickets = []
         t0 = time.perf_counter()
-        for r, ta in zip(reqs, arrivals):
+        for r, ta in zip(sub, arrivals):
             while time.perf_counter() - t0 < ta:
                 time.sleep(0.0002)
             tickets.append(submit(r))
         outs = [sv.wait(t, 600) for t in tickets]
         span = time.perf_counter() - t0
         lat = np.array([o["t_done"] - o["t_submit"] for o in outs]) * 1000.0
-        streams.append({"load": load, "arrival_rate_req_per_s": lam,
+        streams.append({"load": load, "requests": len(sub), "arrival_rate_req_per_s": lam,
                         "p50_latency_ms": float(np.percentile(lat, 50)),
                         "p99_latency_ms": float(np.percentile(lat, 99)),
-                        "stream_points_per_s": pts / span,
+                        "stream_points_per_s": sum(r.n_points for r in sub) / span,
                         "failed": sum(1 for o in outs if o["status"] != 0)})
+    st1 = sv.stats()
     sv.close()
-    main_stream = min(streams, key=lambda st: abs(st["load"] - 0.7))
-    return {"requests": n_requests, "slots": slots, "hbm_budget_gb": budget_gb,
-            "points_total": pts, "saturation_req_per_s": sat_rate,
-            "saturation_points_per_s": pts / sat, "arrival_rate_req_per_s": main_stream["arrival_rate_req_per_s"],
+    main_stream = min(streams, key=lambda x: abs(x["load"] - 0.7))
+    return {"requests": main_stream["requests"], "slots": slots, "inflight_points_cap": inflight_points,
+            "hbm_budget_gb": budget_gb,
+            "reserved_gb_per_slot": st0["reserved_bytes_per_slot"] / 2 ** 30,
+            "allocations_after_warmup": st1["allocations"] - st0["allocations"],
+            "saturation_requests": len(side), "saturation_req_per_s": sat_rate, "saturation_points_per_s": sat_pts,
+            "arrival_rate_req_per_s": main_stream["arrival_rate_req_per_s"],
             "p50_latency_ms": main_stream["p50_latency_ms"], "p99_latency_ms": main_stream["p99_latency_ms"],
             "stream_points_per_s": main_stream["stream_points_per_s"],
-            "failed": sum(st["failed"] for st in streams), "streams": streams,
-            "mix": "fcc n^3*4 (n=2..8) or liquid N~U[32,2048], 298-933 K, ~2800 points/atom, seed %d" % seed}
+            "failed": sum(x["failed"] for x in streams), "streams": streams,
+            "mix": "fcc n^3*4 (n=2..8) or liquid N~U[32,2048], 298-933 K, ~2800 points/atom, request i from "
+                   "SplitMix64(%d * 1000003 + i)" % seed}
+
+
+def measure(ctx, mala, torch, snap, net, precision, steps, warmup, Bc, fl):
+    """Time `steps` fused-path calls after `warmup` untimed ones; stage times
+    come from HIP events the library records on its own stream."""
+    prec = mala.PREC_FP32 if precision == "fp32" else mala.PREC_BF16
+    w = ctx.weights(mala_synth.net_to_blob(net), prec)
+    dev = torch.device("cuda", 0)
+    dos = torch.empty(mala_synth.EGRID[2], dtype=torch.float64, device=dev)
+    dens = torch.empty(snap.n_points, dtype=torch.float64, device=dev)
+    res = torch.zeros(mala.RESULT_BYTES, dtype=torch.uint8, device=dev)
+
+    def step():
+        ctx.mala_predict(w, snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, mala_synth.EGRID, snap.T,
+                         snap.n_electrons, B_cache=Bc, dos=dos, dens=dens, res=res)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.check_device_errors()
+    r = mala.read_result(res)
+    if r["status"] != 0:
+        raise RuntimeError("no Fermi level in warm-up: %s" % r)
+    ctx.profile_enable(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for k in range(steps):
+        step()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    r = mala.read_result(res)
+    elapsed = t1 - t0
+    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    value = snap.n_points * steps / elapsed
+    zb_ms, zb_n, zb_pts = prof["zb"]
+    zb_avg_ms = zb_ms / max(zb_n, 1)
+    achieved = fl["zb"] * zb_pts / max(zb_n, 1) / (zb_avg_ms * 1e-3) / 1e12
+    stages = {k: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps} for k, v in prof.items() if v[1]}
+    # per-stage algorithmic rate against the peak of the unit that bounds it
+    for k, fk, peak in (("ui", "u", PEAK_FP32_VALU_TFLOPS), ("zb", "zb", PEAK_FP32_VALU_TFLOPS),
+                        ("mlp_dos", "mlp", PEAK_MFMA_TFLOPS[precision])):
+        if k in stages and prof[k][0] > 0:
+            tf = fl[fk] * prof[k][2] / (prof[k][0] * 1e-3) / 1e12
+            stages[k].update({"tflops": tf, "peak_tflops": peak, "frac": tf / peak})
+    ceiling = path_ceiling(fl, precision)
+    return {
+        "value": value, "ms_per_step": 1000.0 * elapsed / steps, "steps": steps, "warmup": warmup,
+        "dtype": "f32" if precision == "fp32" else "bf16",
+        "config": {"workload": snap.name, "n_points": snap.n_points, "n_atoms": snap.n_atoms,
+                   "twojmax": snap.twojmax, "network": "-".join(map(str, net["widths"])),
+                   "network_precision": precision, "reductions": "f64", "T_K": snap.T,
+                   "n_electrons": snap.n_electrons},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "kind": "single snapshot, back-to-back"},
+        "roofline": {"kernel": "k_zb (Z/B contraction)", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": measured_traffic(snap.name),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "flops_per_point": fl["zb"], "points_per_launch": zb_pts / max(zb_n, 1),
+                     "avg_launch_ms": zb_avg_ms},
+        "path_roofline": {"ceiling_points_per_s": ceiling, "frac": value / ceiling,
+                          "model": "(U + Z/B) at %.1f TFLOP/s FP32 vector + network at %.0f TFLOP/s %s matrix"
+                                   % (PEAK_FP32_VALU_TFLOPS, PEAK_MFMA_TFLOPS[precision], precision)},
+        "stages": stages,
+        "algorithmic_kflop_per_point": {"u": fl["u"] / 1e3, "zb": fl["zb"] / 1e3, "mlp": fl["mlp"] / 1e3,
+                                        "mean_neighbours": fl["mean_neighbours"]},
+        "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms,
+                   "minus_ts_mev_per_atom": 1000 * r["e_entropy"] / snap.n_atoms, "entropy_kb": r["entropy"]},
+        "_w": w, "_dos": dos, "_dens": dens, "_r": r,
+    }
+
+
+def public(rec):
+    return {k: v for k, v in rec.items() if not k.startswith("_")}
+
+
+def sampled_row_errors(ctx, Bc, pts, B_ref, ld_ref, w, torch):
+    """Per-row max-norm relative errors of the fused path's cached B rows and
+    of their LDOS (GPU network) against the oracle's at the CPU sample."""
+    rows = Bc.index_select(0, torch.as_tensor(pts, device="cuda")).contiguous()
+    Bg = rows.cpu().double().numpy()
+    ld = ctx.mala_ldos_infer(w, rows, mala_synth.EGRID[2]).cpu().double().numpy()
+    eb = np.max(np.abs(Bg - B_ref), axis=1) / np.max(np.abs(B_ref), axis=1)
+    el = np.max(np.abs(ld - ld_ref), axis=1) / np.max(np.abs(ld_ref), axis=1)
+    return {"points": int(len(pts)), "B_max_rel": float(np.max(eb)), "ldos_max_rel": float(np.max(el)),
+            "ldos_median_rel": float(np.median(el))}
 
 
 def main():
@@ -467,13 +641,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="paper_solid", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--workload", default="slab", choices=sorted(WORKLOADS),
+                    help="headline workload (default: the 47,066,880-point slab)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"], help="headline network precision")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline workload and precision (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768)
-    ap.add_argument("--serve-requests", type=int, default=48, help="0 disables the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the 0.7x Poisson stream per precision (0 disables serving)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the lines outside the metric (Gaussian descriptors, network and descriptor VJPs)")
+                    help="skip the lines outside the metric (Gaussian descriptors, both VJPs, grid ACE)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain device copies that calibrate the HBM byte counters")
     ap.add_argument("--traffic-summary", nargs=4, metavar="DIR",
@@ -500,94 +678,84 @@ def main():
     import paper_2411_19617_amd as mala
 
     mala.lib()
-    snap, net = WORKLOADS[a.workload][0](), WORKLOADS[a.workload][1]()
-    prec = mala.PREC_FP32 if a.precision == "fp32" else mala.PREC_BF16
     ctx = mala.Context(0)
-    w = ctx.weights(mala_synth.net_to_blob(net), prec)
     dev = torch.device("cuda", 0)
-    nB = mala.n_descriptors(snap.twojmax)
-    Bc = torch.empty((snap.n_points, nB), dtype=torch.float32, device=dev)
-    dos = torch.empty(mala_synth.EGRID[2], dtype=torch.float64, device=dev)
-    dens = torch.empty(snap.n_points, dtype=torch.float64, device=dev)
-    res = torch.zeros(mala.RESULT_BYTES, dtype=torch.uint8, device=dev)
-
-    def step():
-        ctx.mala_predict(w, snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, mala_synth.EGRID, snap.T,
-                         snap.n_electrons, B_cache=Bc, dos=dos, dens=dens, res=res)
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.check_device_errors()
-    r = mala.read_result(res)
-    if r["status"] != 0:
-        raise RuntimeError("no Fermi level in warm-up: %s" % r)
-
-    ctx.profile_enable(True)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record()
-    for k in range(a.steps):
-        step()
-        evs[k + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    ctx.check_device_errors()
-    elapsed = t1 - t0
-    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(a.steps)])
-    value = snap.n_points * a.steps / elapsed
-
+    snap, net = WORKLOADS[a.workload][0](), WORKLOADS[a.workload][1]()
     fl = flops_per_point(snap, net["widths"])
-    zb_ms, zb_n, zb_pts = prof["zb"]
-    zb_avg_ms = zb_ms / max(zb_n, 1)
-    zb_flops_per_launch = fl["zb"] * zb_pts / max(zb_n, 1)
-    achieved = zb_flops_per_launch / (zb_avg_ms * 1e-3) / 1e12
-    stages = {k: {"ms_per_step": v[0] / a.steps, "launches_per_step": v[1] / a.steps}
-              for k, v in prof.items() if v[1]}
-    # per-stage algorithmic rate against the peak of the unit that bounds it
-    for k, fk, peak in (("ui", "u", PEAK_FP32_VALU_TFLOPS), ("zb", "zb", PEAK_FP32_VALU_TFLOPS),
-                        ("mlp_dos", "mlp", PEAK_MFMA_TFLOPS[a.precision])):
-        if k in stages and prof[k][0] > 0:
-            tf = fl[fk] * prof[k][2] / (prof[k][0] * 1e-3) / 1e12
-            stages[k].update({"tflops": tf, "peak_tflops": peak, "frac": tf / peak})
-    out = {
-        "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": 1000.0 * elapsed / a.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == mala.PREC_FP32 else "bf16",
-        "data": "synthetic",
-        "config": {"workload": snap.name, "n_points": snap.n_points, "n_atoms": snap.n_atoms,
-                   "twojmax": snap.twojmax, "network": "-".join(map(str, net["widths"])),
-                   "network_precision": a.precision, "reductions": "f64", "T_K": snap.T,
-                   "n_electrons": snap.n_electrons},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "kind": "single snapshot, back-to-back"},
-        "roofline": {"kernel": "k_zb (Z/B contraction)", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": measured_traffic(a.workload),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "flops_per_point": fl["zb"], "points_per_launch": zb_pts / max(zb_n, 1),
-                     "avg_launch_ms": zb_avg_ms},
-        "stages": stages,
-        "algorithmic_kflop_per_point": {"u": fl["u"] / 1e3, "zb": fl["zb"] / 1e3, "mlp": fl["mlp"] / 1e3,
-                                        "mean_neighbours": fl["mean_neighbours"]},
-        "result": {"e_fermi": r["e_fermi"], "e_band_mev_per_atom": 1000 * r["e_band"] / snap.n_atoms,
-                   "minus_ts_mev_per_atom": 1000 * r["e_entropy"] / snap.n_atoms, "entropy_kb": r["entropy"]},
-        "errors_vs_oracle": errors_vs_oracle(a.workload, snap, dos, mala.read_result(res), dens),
-    }
-    if not a.no_extras:
-        out["gaussian_descriptors"] = gaussian_bench(ctx, snap, torch)
-        out["network_vjp"] = network_vjp_bench(ctx, mala, snap, net, torch)
-        out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, snap, torch)
-        out["ace_descriptors"] = ace_bench(ctx, mala, snap, fl["mean_neighbours"], torch)
-    if a.serve_requests > 0:
-        out["serving"] = serving_bench(mala, prec, a.serve_requests)
-        out["latency_ms"]["serving_p50"] = out["serving"]["p50_latency_ms"]
-        out["latency_ms"]["serving_p99"] = out["serving"]["p99_latency_ms"]
+    Bc = torch.empty((snap.n_points, mala.n_descriptors(snap.twojmax)), dtype=torch.float32, device=dev)
+    head = measure(ctx, mala, torch, snap, net, a.precision, a.steps, a.warmup, Bc, fl)
+    print("headline %s %s: %.4g points/s" % (snap.name, a.precision, head["value"]), file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": head["value"], "unit": "grid points/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": head["dtype"], "data": "synthetic"}
+    out.update({k: v for k, v in public(head).items() if k not in out and k not in ("steps", "warmup")})
+    if a.workload == "slab":
+        out["errors_vs_oracle"] = slab_sample_errors(ctx, snap, head["_w"], Bc, head["_dos"], head["_r"], torch)
+    else:
+        out["errors_vs_oracle"] = errors_vs_oracle(a.workload, snap, head["_dos"], head["_r"], head["_dens"])
+    cpu = None
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(snap, net, a.cpu_sample)
+        cpu, pts, B_ref, ld_ref = cpu_baseline(snap, net, a.cpu_sample)
+        cpu["errors_on_sample"] = sampled_row_errors(ctx, Bc, pts, B_ref, ld_ref, head["_w"], torch)
+        print("cpu baseline: %.4g points/s" % cpu["value"], file=sys.stderr, flush=True)
+    if a.headline_only:
+        if cpu:
+            out["cpu_baseline"] = cpu
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        return
+    other = "bf16" if a.precision == "fp32" else "fp32"
+    pf = measure(ctx, mala, torch, snap, net, other, a.steps, a.warmup, Bc, fl)
+    rec = public(pf)
+    if a.workload == "slab":
+        rec["errors_vs_oracle"] = slab_sample_errors(ctx, snap, pf["_w"], Bc, pf["_dos"], pf["_r"], torch)
+    else:
+        rec["errors_vs_oracle"] = errors_vs_oracle(a.workload, snap, pf["_dos"], pf["_r"], pf["_dens"])
+    rec["e_band_vs_headline_mev_per_atom"] = abs(pf["_r"]["e_band"] - head["_r"]["e_band"]) * 1000.0 / snap.n_atoms
+    if cpu:
+        rec["errors_on_sample"] = sampled_row_errors(ctx, Bc, pts, B_ref, ld_ref, pf["_w"], torch)
+    out["precision_form" if other == "bf16" else "plain_form"] = rec
+    print("%s %s: %.4g points/s" % (snap.name, other, pf["value"]), file=sys.stderr, flush=True)
+    del head, pf, Bc
+    torch.cuda.empty_cache()
+
+    # the 729,000-point 256-atom solid in both forms (the paper's per-GPU scale)
+    if a.workload != "paper_solid":
+        ps, pnet = WORKLOADS["paper_solid"][0](), WORKLOADS["paper_solid"][1]()
+        pfl = flops_per_point(ps, pnet["widths"])
+        pB = torch.empty((ps.n_points, mala.n_descriptors(ps.twojmax)), dtype=torch.float32, device=dev)
+        solid = {}
+        for prec in ("fp32", "bf16"):
+            m = measure(ctx, mala, torch, ps, pnet, prec, max(a.steps, 20), max(a.warmup, 3), pB, pfl)
+            rec = public(m)
+            rec["errors_vs_oracle"] = errors_vs_oracle("paper_solid", ps, m["_dos"], m["_r"], m["_dens"])
+            solid[prec] = rec
+            print("paper_solid %s: %.4g points/s" % (prec, m["value"]), file=sys.stderr, flush=True)
+        out["paper_solid"] = solid
+        del pB
+        torch.cuda.empty_cache()
+    if not a.no_extras:
+        es = WORKLOADS["paper_solid"][0]()
+        efl = flops_per_point(es, WORKLOADS["paper_solid"][1]()["widths"])
+        out["gaussian_descriptors"] = gaussian_bench(ctx, es, torch)
+        out["network_vjp"] = network_vjp_bench(ctx, mala, es, WORKLOADS["paper_solid"][1](), torch)
+        out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, es, torch)
+        out["ace_descriptors"] = ace_bench(ctx, mala, es, efl["mean_neighbours"], torch)
+        print("extras done", file=sys.stderr, flush=True)
+    if a.serve_requests > 0:
+        sv = {}
+        reqs = mala_synth.serving_mix(max(a.serve_requests, 200), 5, workers=min(16, len(os.sched_getaffinity(0))))
+        print("serving mix generated", file=sys.stderr, flush=True)
+        for prec in ("fp32", "bf16"):
+            sv[prec] = serving_bench(mala, mala.PREC_FP32 if prec == "fp32" else mala.PREC_BF16,
+                                     reqs, a.serve_requests, n_side=min(200, a.serve_requests))
+            print("serving %s: p50 %.1f ms p99 %.1f ms" % (prec, sv[prec]["p50_latency_ms"],
+                                                           sv[prec]["p99_latency_ms"]), file=sys.stderr, flush=True)
+        out["serving"] = sv
+        out["latency_ms"]["serving_p50"] = sv[a.precision]["p50_latency_ms"]
+        out["latency_ms"]["serving_p99"] = sv[a.precision]["p99_latency_ms"]
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -305,8 +305,22 @@ mala_status mala_server_submit(mala_server* s, const mala_request* req, uint64_t
 mala_status mala_server_poll(mala_server* s, uint64_t ticket, mala_result* result, double* times);
 mala_status mala_server_wait(mala_server* s, uint64_t ticket, double timeout_s,
                              mala_result* result, double* times);
-/* stats[5] = queued, running, device bytes held by the slots, peak bytes
- * held, budget.                                                             */
+/* Sizes every slot once, before a stream of requests, for the element-wise
+ * largest of the given requests (points, atoms, cell list, energy window of
+ * the hottest one): afterwards a request within those sizes makes no device
+ * or pinned allocation.  The server must be idle (MALA_E_BUSY otherwise);
+ * MALA_E_OOM if all slots at that size would exceed the HBM budget.  Only
+ * the shapes of the requests are read (positions are not).                 */
+mala_status mala_server_reserve(mala_server* s, const mala_request* reqs, int32_t n);
+/* Concurrency by work: a request is admitted next to running ones only if
+ * the grid points in flight would stay within max_points (a request larger
+ * than that runs alone; 0, the default, admits up to max_inflight requests
+ * whatever their size).  Requests that fill the GPU on their own then do
+ * not share it, which shortens their latency at the same throughput.      */
+mala_status mala_server_set_inflight_points(mala_server* s, int64_t max_points);
+/* stats[7] = queued, running, device bytes held by the slots, peak bytes
+ * held, budget, allocations (device and pinned) made by the slots so far,
+ * reserved bytes per slot (0 without mala_server_reserve).                 */
 mala_status mala_server_stats(mala_server* s, double* stats);
 const char* mala_server_last_error(void);
 mala_status mala_server_destroy(mala_server* s);

@@ -204,6 +204,23 @@ def serving_request(rng, pts_per_atom=2800.0):
                     E_PER_ATOM * float(pos.shape[0]), {})
 
 
+def _mix_request(args):
+    seed, i = args
+    return serving_request(SplitMix64(seed * 1_000_003 + i))
+
+
+def serving_mix(n_requests, seed=5, workers=16):
+    """The serving mix: request i is drawn from its own SplitMix64 stream
+    seeded with seed * 1,000,003 + i, so any request can be regenerated alone
+    and the mix is generated in a pool of spawned worker processes."""
+    jobs = [(seed, i) for i in range(n_requests)]
+    if workers <= 1 or n_requests < 8:
+        return [_mix_request(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(workers, n_requests)) as pool:
+        return pool.map(_mix_request, jobs, chunksize=4)
+
+
 def with_grid(snap, N):
     """Same atoms on another grid (used for reduced-size parity cases)."""
     return Snapshot(snap.name + "_g%dx%dx%d" % tuple(N), snap.positions, snap.L,

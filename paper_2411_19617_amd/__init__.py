@@ -100,6 +100,8 @@ def lib():
             ("mala_server_poll", [p, ctypes.c_uint64, ctypes.POINTER(Result), p]),
             ("mala_server_wait", [p, ctypes.c_uint64, d, ctypes.POINTER(Result), p]),
             ("mala_server_stats", [p, p]),
+            ("mala_server_reserve", [p, p, i32]),
+            ("mala_server_set_inflight_points", [p, i64]),
             ("mala_server_destroy", [p]),
             ("mala_set_density_mode", [p, i32]),
             ("mala_profile_read", [p, p, p, p]),
@@ -440,11 +442,37 @@ class Server:
             raise TimeoutError("ticket %d not done after %.1f s" % (ticket, timeout))
         return self._out(ticket, st, r, times)
 
+    def reserve(self, shapes, density=True):
+        """Size every slot for the largest of the given requests, each an
+        (n_atoms, L, N, rcut, twojmax, egrid, T) tuple (only shapes are read)."""
+        arr = (Request * len(shapes))()
+        for q, (n_atoms, L, N, rcut, twojmax, egrid, T) in zip(arr, shapes):
+            q.positions = None
+            q.n_atoms = int(n_atoms)
+            q.cell_grid = _cell_grid(L, N)
+            q.rcut = float(rcut)
+            q.twojmax = int(twojmax)
+            q.egrid = _egrid(egrid)
+            q.T_kelvin = float(T)
+            q.n_electrons = 1.0
+            q.dos_out = None
+            q.density_out = 1 if density else None       # only tested for NULL
+        st = lib().mala_server_reserve(self.handle, arr, len(shapes))
+        if st != MALA_OK:
+            raise MalaError(st, lib().mala_server_last_error().decode())
+
+    def set_inflight_points(self, max_points):
+        """Admit a request next to running ones only while the points in flight
+        stay within max_points (0: no limit besides the slot count)."""
+        st = lib().mala_server_set_inflight_points(self.handle, int(max_points))
+        if st != MALA_OK:
+            raise MalaError(st, lib().mala_server_last_error().decode())
+
     def stats(self):
-        s = (ctypes.c_double * 5)()
+        s = (ctypes.c_double * 7)()
         _check(lib().mala_server_stats(self.handle, s))
         return {"queued": int(s[0]), "running": int(s[1]), "bytes_held": s[2], "peak_bytes": s[3],
-                "budget": s[4]}
+                "budget": s[4], "allocations": int(s[5]), "reserved_bytes_per_slot": s[6]}
 
     def close(self):
         if self.handle:

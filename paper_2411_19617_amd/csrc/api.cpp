@@ -46,8 +46,11 @@ struct DevBuf {
     size_t cap = 0;   // elements
 };
 
+// Elements a buffer is grown to when it must hold n (slack against regrowth).
+inline size_t grown_size(size_t n) { return n + n / 8 + 64; }
+
 template <typename T>
-hipError_t ensure(DevBuf<T>& b, size_t n) {
+hipError_t ensure(uint64_t& n_allocs, DevBuf<T>& b, size_t n) {
     if (n <= b.cap) return hipSuccess;
     if (b.p) {
         hipError_t e = hipFree(b.p);    // synchronising: no kernel still uses it
@@ -55,7 +58,8 @@ hipError_t ensure(DevBuf<T>& b, size_t n) {
         b.p = nullptr;
         b.cap = 0;
     }
-    size_t want = n + n / 8 + 64;
+    size_t want = grown_size(n);
+    ++n_allocs;
     hipError_t e = hipMalloc(&b.p, want * sizeof(T));
     if (e != hipSuccess) return e;
     b.cap = want;
@@ -82,6 +86,7 @@ struct TjTables {
 };
 
 constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
+constexpr double kWindowMargin = 0.3;     // eV around the E_F estimate kept in the stored LDOS window
 
 struct AceTables {
     bool ready = false;
@@ -113,6 +118,7 @@ struct mala_ctx {
     int density_mode = 0;              // 0: stored energy window (recompute if not covered), 1: recompute
     int* err = nullptr;
     double* li_coef = nullptr;
+    uint64_t n_allocs = 0;               // device/pinned allocations made by this context
     TjTables tj[kMaxTwojmax + 1];
     AceTables ace[kAceMaxN + 1][kAceMaxL + 1];
     // stage timing
@@ -195,6 +201,7 @@ mala_status ensure_tables(mala_ctx* c, int tj) {
     t.zb_waves = 12;      // three waves per SIMD share the LDS tile
     std::vector<int> waves(t.zb_waves * kMaxZbStride, 0);
     plan_zb_waves(tj, t.zb_waves, waves.data(), kMaxZbStride);
+    c->n_allocs += 3;
     HIP_TRY(hipMalloc(&t.cg, sizeof(float) * (n > 0 ? n : 1)));
     HIP_TRY(hipMalloc(&t.cg_off, sizeof(int) * off.size()));
     HIP_TRY(hipMalloc(&t.waves, sizeof(int) * waves.size()));
@@ -217,6 +224,7 @@ mala_status ensure_adjoint_tables(mala_ctx* c, int tj) {
     for (int g = 0; g < ng; ++g)
         plan_y_units(tj, y_group_first(tj, g), y_group_last(tj, g), y_group_wave_count(tj, g),
                      units.data() + (size_t)g * nw * kMaxYStride, kMaxYStride);
+    c->n_allocs += 3;
     HIP_TRY(hipMalloc(&t.cgy, sizeof(float) * (n > 0 ? n : 1)));
     HIP_TRY(hipMalloc(&t.cgy_off, sizeof(int) * off.size()));
     HIP_TRY(hipMalloc(&t.yunits, sizeof(int) * units.size()));
@@ -248,12 +256,13 @@ mala_status check_geometry(const double* positions, int32_t n_atoms, const mala_
 
 mala_status upload_positions(mala_ctx* c, const double* positions, int32_t n_atoms) {
     const size_t n = (size_t)3 * (n_atoms > 0 ? n_atoms : 1);
-    HIP_TRY(ensure(c->pos, n));
+    HIP_TRY(ensure(c->n_allocs, c->pos, n));
     if (n_atoms == 0) return MALA_OK;
     HIP_TRY(hipEventSynchronize(c->stage_ev));          // previous copy out of the stage is done
     if (c->pos_stage_cap < n) {
         if (c->pos_stage) HIP_TRY(hipHostFree(c->pos_stage));
         c->pos_stage = nullptr;
+        ++c->n_allocs;
         HIP_TRY(hipHostMalloc(&c->pos_stage, sizeof(double) * n, hipHostMallocDefault));
         c->pos_stage_cap = n;
     }
@@ -264,21 +273,40 @@ mala_status upload_positions(mala_ctx* c, const double* positions, int32_t n_ato
     return MALA_OK;
 }
 
-// Cell list of the uploaded atoms for neighbour searches within rcut.
-mala_status bin_atoms(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut, BinState* bs) {
-    int nc_est = 1;
+// Entries of the cell-count arrays of a cell list for cutoff rcut (cells of
+// edge >= rcut / 2, at most 256 per edge, plus one).
+size_t cell_entries(const mala_cell_grid* cg, double rcut) {
+    size_t nc_est = 1;
     for (int d = 0; d < 3; ++d) {
         int nc = (int)floor(cg->L[d] / (0.5 * rcut));
         nc = nc < 1 ? 1 : (nc > 256 ? 256 : nc);
         nc_est *= nc;
     }
+    return nc_est + 1;
+}
+
+// u scratch elements of one descriptor chunk of a grid of ntot points.
+size_t u_elements(int64_t ntot, int twojmax) {
+    const int64_t chunk = ntot < kChunk ? ntot : kChunk;
+    return (size_t)((chunk + kTile - 1) / kTile) * n_half(twojmax) * kTile;
+}
+
+// Energies of the stored LDOS window of the single-pass density.
+int window_width(const mala_egrid* eg, double T) {
+    const double kT = kBoltzmannEv * T;
+    return std::min(eg->n, (int)ceil(2.0 * (40.0 * kT + kWindowMargin) / eg->de) + 3);
+}
+
+// Cell list of the uploaded atoms for neighbour searches within rcut.
+mala_status bin_atoms(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut, BinState* bs) {
+    const size_t ncell = cell_entries(cg, rcut);
     const size_t na = n_atoms > 0 ? n_atoms : 1;
-    HIP_TRY(ensure(c->cell_count, nc_est + 1));
-    HIP_TRY(ensure(c->cell_start, nc_est + 1));
-    HIP_TRY(ensure(c->cell_fill, nc_est + 1));
-    HIP_TRY(ensure(c->atom_cell, na));
-    HIP_TRY(ensure(c->atoms_tmp, na));
-    HIP_TRY(ensure(c->atoms_sorted, na));
+    HIP_TRY(ensure(c->n_allocs, c->cell_count, ncell));
+    HIP_TRY(ensure(c->n_allocs, c->cell_start, ncell));
+    HIP_TRY(ensure(c->n_allocs, c->cell_fill, ncell));
+    HIP_TRY(ensure(c->n_allocs, c->atom_cell, na));
+    HIP_TRY(ensure(c->n_allocs, c->atoms_tmp, na));
+    HIP_TRY(ensure(c->n_allocs, c->atoms_sorted, na));
     HIP_TRY(staged(c, MALA_STAGE_BIN, 0, [&] {
         return launch_bin(c->stream, c->pos.p, n_atoms, cg->L, rcut, c->cell_count.p, c->cell_start.p,
                           c->cell_fill.p, c->atoms_tmp.p, c->atom_cell.p, c->atoms_sorted.p, bs);
@@ -294,8 +322,7 @@ mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* 
     const int nB = n_triples(twojmax);
     const int64_t total = pt_end - pt_begin;
     const int64_t chunk = total < kChunk ? total : kChunk;
-    const int64_t tiles = (chunk + kTile - 1) / kTile;
-    HIP_TRY(ensure(c->u, (size_t)tiles * n_half(twojmax) * kTile));
+    HIP_TRY(ensure(c->n_allocs, c->u, u_elements(total, twojmax)));
     const TjTables& t = c->tj[twojmax];
     for (int64_t off = 0; off < total; off += chunk) {
         const int64_t n = (total - off) < chunk ? (total - off) : chunk;
@@ -351,6 +378,96 @@ size_t ctx_device_bytes(mala_ctx* c) {
            bytes_of(c->atom_cell) + bytes_of(c->atoms_tmp) + bytes_of(c->atoms_sorted) + bytes_of(c->u) +
            bytes_of(c->Bbuf) + bytes_of(c->partials) + bytes_of(c->est_partials) + bytes_of(c->fermi_w) +
            bytes_of(c->window) + bytes_of(c->prefix);
+}
+
+uint64_t ctx_alloc_count(mala_ctx* c) { return c->n_allocs; }
+
+int* ctx_error_flags(mala_ctx* c) { return c->err; }
+
+// Elements of every context buffer mala_predict uses for one request
+// (positions, cell list, u scratch, B cache unless the caller owns it,
+// partial rows, window and prefix of the single-pass density).
+PredictPlan plan_predict(const mala_cell_grid* cg, int32_t n_atoms, double rcut, int32_t twojmax,
+                         const mala_egrid* eg, double T, bool density, int density_mode, bool caller_b_cache) {
+    PredictPlan p{};
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    const size_t na = n_atoms > 0 ? (size_t)n_atoms : 1;
+    p.twojmax = twojmax;
+    p.pos = 3 * na;
+    p.cells = cell_entries(cg, rcut);
+    p.atoms = na;
+    p.u = u_elements(ntot, twojmax);
+    p.B = caller_b_cache ? 0 : (size_t)ntot * n_triples(twojmax);
+    p.partials = (size_t)mlp_blocks(ntot) * kMlpMaxOut;
+    p.fermi_w = kMlpMaxOut;
+    if (density && density_mode == 0) {
+        const int64_t n_est = (ntot + kEstStride - 1) / kEstStride;
+        p.est_partials = (size_t)mlp_blocks(n_est) * kMlpMaxOut;
+        p.window = (size_t)ntot * window_width(eg, T);
+        p.prefix = (size_t)ntot;
+    }
+    return p;
+}
+
+PredictPlan plan_max(const PredictPlan& a, const PredictPlan& b) {
+    PredictPlan p{};
+    p.twojmax = a.twojmax > b.twojmax ? a.twojmax : b.twojmax;
+#define MALA_PLAN_MAX(f) p.f = a.f > b.f ? a.f : b.f
+    MALA_PLAN_MAX(pos); MALA_PLAN_MAX(cells); MALA_PLAN_MAX(atoms); MALA_PLAN_MAX(u); MALA_PLAN_MAX(B);
+    MALA_PLAN_MAX(partials); MALA_PLAN_MAX(fermi_w); MALA_PLAN_MAX(est_partials); MALA_PLAN_MAX(window);
+    MALA_PLAN_MAX(prefix);
+#undef MALA_PLAN_MAX
+    return p;
+}
+
+// Device bytes the context would add to run a request of this plan: the sum
+// over buffers of what each one grows by (a buffer that already holds enough
+// adds nothing; one that grows is reallocated at grown_size).
+size_t plan_growth_bytes(mala_ctx* c, const PredictPlan& p) {
+    size_t g = 0;
+    auto add = [&](const auto& b, size_t n, size_t elem) {
+        if (n > b.cap) g += grown_size(n) * elem - b.cap * elem;
+    };
+    add(c->pos, p.pos, 8);
+    add(c->cell_count, p.cells, 4); add(c->cell_start, p.cells, 4); add(c->cell_fill, p.cells, 4);
+    add(c->atom_cell, p.atoms, 4); add(c->atoms_tmp, p.atoms, 32); add(c->atoms_sorted, p.atoms, 32);
+    add(c->u, p.u, 8); add(c->Bbuf, p.B, 4); add(c->partials, p.partials, 8); add(c->fermi_w, p.fermi_w, 8);
+    add(c->est_partials, p.est_partials, 8); add(c->window, p.window, 4); add(c->prefix, p.prefix, 8);
+    return g;
+}
+
+// Grow every buffer of the plan now (and upload the Clebsch-Gordan tables
+// and size the pinned position stage), so that later requests within the
+// plan allocate nothing.
+mala_status ctx_reserve(mala_ctx* c, const PredictPlan& p) {
+    DeviceGuard g(c->device);
+    mala_status st = ensure_tables(c, p.twojmax);
+    if (st) return st;
+    HIP_TRY(ensure(c->n_allocs, c->pos, p.pos));
+    HIP_TRY(ensure(c->n_allocs, c->cell_count, p.cells));
+    HIP_TRY(ensure(c->n_allocs, c->cell_start, p.cells));
+    HIP_TRY(ensure(c->n_allocs, c->cell_fill, p.cells));
+    HIP_TRY(ensure(c->n_allocs, c->atom_cell, p.atoms));
+    HIP_TRY(ensure(c->n_allocs, c->atoms_tmp, p.atoms));
+    HIP_TRY(ensure(c->n_allocs, c->atoms_sorted, p.atoms));
+    HIP_TRY(ensure(c->n_allocs, c->u, p.u));
+    if (p.B) HIP_TRY(ensure(c->n_allocs, c->Bbuf, p.B));
+    HIP_TRY(ensure(c->n_allocs, c->partials, p.partials));
+    HIP_TRY(ensure(c->n_allocs, c->fermi_w, p.fermi_w));
+    if (p.window) {
+        HIP_TRY(ensure(c->n_allocs, c->est_partials, p.est_partials));
+        HIP_TRY(ensure(c->n_allocs, c->window, p.window));
+        HIP_TRY(ensure(c->n_allocs, c->prefix, p.prefix));
+    }
+    if (c->pos_stage_cap < p.pos) {
+        HIP_TRY(hipEventSynchronize(c->stage_ev));
+        if (c->pos_stage) HIP_TRY(hipHostFree(c->pos_stage));
+        c->pos_stage = nullptr;
+        ++c->n_allocs;
+        HIP_TRY(hipHostMalloc(&c->pos_stage, sizeof(double) * p.pos, hipHostMallocDefault));
+        c->pos_stage_cap = p.pos;
+    }
+    return MALA_OK;
 }
 
 void ctx_trim(mala_ctx* c) {
@@ -727,8 +844,8 @@ mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n
     const int64_t total = pt_end - pt_begin;
     const int64_t chunk = total < kChunk ? total : kChunk;
     const int64_t tiles = (chunk + kTile - 1) / kTile;
-    HIP_TRY(ensure(c->u, (size_t)tiles * n_half(twojmax) * kTile));
-    HIP_TRY(ensure(c->yadj, (size_t)tiles * n_half(twojmax) * kTile));
+    HIP_TRY(ensure(c->n_allocs, c->u, (size_t)tiles * n_half(twojmax) * kTile));
+    HIP_TRY(ensure(c->n_allocs, c->yadj, (size_t)tiles * n_half(twojmax) * kTile));
     const TjTables& t = c->tj[twojmax];
     for (int64_t off = 0; off < total; off += chunk) {
         const int64_t n = (total - off) < chunk ? (total - off) : chunk;
@@ -850,8 +967,8 @@ mala_status mala_integrate(mala_ctx* c, const float* ldos, int64_t n_pts, double
     if (st) return st;
     DeviceGuard g(c->device);
     const int nb = integrate_parts(n_pts);
-    HIP_TRY(ensure(c->partials, (size_t)nb * kMlpMaxOut));
-    HIP_TRY(ensure(c->fermi_w, kMlpMaxOut));
+    HIP_TRY(ensure(c->n_allocs, c->partials, (size_t)nb * kMlpMaxOut));
+    HIP_TRY(ensure(c->n_allocs, c->fermi_w, kMlpMaxOut));
     HIP_TRY(staged(c, MALA_STAGE_INTEGRATE, n_pts,
                    [&] { return launch_ldos_colsum(c->stream, ldos, n_pts, eg->n, c->partials.p, nb); }));
     HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
@@ -903,14 +1020,14 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
     if ((st = ensure_tables(c, twojmax))) return st;
     float* B = B_cache;
     if (!B) {
-        HIP_TRY(ensure(c->Bbuf, (size_t)ntot * n_triples(twojmax)));
+        HIP_TRY(ensure(c->n_allocs, c->Bbuf, (size_t)ntot * n_triples(twojmax)));
         B = c->Bbuf.p;
     }
     if ((st = upload_positions(c, positions, n_atoms))) return st;
     if ((st = run_descriptors(c, n_atoms, cg, rcut, twojmax, 0, ntot, B))) return st;
     const int nb = mlp_blocks(ntot);
-    HIP_TRY(ensure(c->partials, (size_t)nb * kMlpMaxOut));
-    HIP_TRY(ensure(c->fermi_w, kMlpMaxOut));
+    HIP_TRY(ensure(c->n_allocs, c->partials, (size_t)nb * kMlpMaxOut));
+    HIP_TRY(ensure(c->n_allocs, c->fermi_w, kMlpMaxOut));
     const double dV = cg->L[0] * cg->L[1] * cg->L[2] / (double)ntot;
     const double kT = kBoltzmannEv * T;
     MlpOut o;
@@ -921,11 +1038,11 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
         // E_F estimate from every kEstStride-th point -> energy window of the stored LDOS
         const int64_t n_est = (ntot + kEstStride - 1) / kEstStride;
         const int nbe = mlp_blocks(n_est);
-        const double margin = 0.3;                       // eV, covers the estimate's error
-        const int w_max = std::min(eg->n, (int)ceil(2.0 * (40.0 * kT + margin) / eg->de) + 3);
-        HIP_TRY(ensure(c->est_partials, (size_t)nbe * kMlpMaxOut));
-        HIP_TRY(ensure(c->window, (size_t)ntot * w_max));
-        HIP_TRY(ensure(c->prefix, (size_t)ntot));
+        const double margin = kWindowMargin;            // eV, covers the estimate's error
+        const int w_max = window_width(eg, T);
+        HIP_TRY(ensure(c->n_allocs, c->est_partials, (size_t)nbe * kMlpMaxOut));
+        HIP_TRY(ensure(c->n_allocs, c->window, (size_t)ntot * w_max));
+        HIP_TRY(ensure(c->n_allocs, c->prefix, (size_t)ntot));
         MlpOut oe;
         oe.partials = c->est_partials.p;
         HIP_TRY(staged(c, MALA_STAGE_ESTIMATE, n_est, [&] {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include "mala.h"
 #include <stdint.h>
 
 #include <algorithm>
@@ -343,6 +344,18 @@ hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_
 
 // Device bytes held by a context's scratch, and releasing them (serving).
 size_t ctx_device_bytes(mala_ctx* c);
+uint64_t ctx_alloc_count(mala_ctx* c);      // device and pinned allocations so far
+int* ctx_error_flags(mala_ctx* c);          // device word of the kernels' capacity flags
+// Buffer sizes (elements) mala_predict needs for one request.
+struct PredictPlan {
+    int twojmax;
+    size_t pos, cells, atoms, u, B, partials, fermi_w, est_partials, window, prefix;
+};
+PredictPlan plan_predict(const mala_cell_grid* cg, int32_t n_atoms, double rcut, int32_t twojmax,
+                         const mala_egrid* eg, double T, bool density, int density_mode, bool caller_b_cache);
+PredictPlan plan_max(const PredictPlan& a, const PredictPlan& b);
+size_t plan_growth_bytes(mala_ctx* c, const PredictPlan& p);
+mala_status ctx_reserve(mala_ctx* c, const PredictPlan& p);
 hipError_t scratch_device_ptr(int device, double** out);   // noalloc.hip
 void ctx_trim(mala_ctx* c);
 

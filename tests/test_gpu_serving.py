@@ -90,3 +90,25 @@ def test_tiny_budget_serialises(mala):
     log("peak bytes", st["peak_bytes"], "budget", st["budget"])
     assert all(o["status"] == 0 for o in outs)
     assert st["peak_bytes"] <= st["budget"]
+
+
+def test_reserved_slots_allocate_nothing_and_match(mala):
+    """After mala_server_reserve for the mix and one warm-up round, a stream
+    of requests makes no device or pinned allocation, the capacity flags come
+    back clean, and results still equal the single-request ones."""
+    net = mala_synth.paper_net()
+    reqs = small_requests(8, seed=55)
+    sv = mala.Server(mala_synth.net_to_blob(net), mala.PREC_FP32, hbm_budget=32 << 30, max_inflight=3)
+    sv.reserve([(r.n_atoms, r.L, r.N, r.rcut, r.twojmax, EG, r.T) for r in reqs])
+    warm = [sv.wait(t, 300) for t in [run(sv, r) for r in reqs[:3]]]
+    st0 = sv.stats()
+    outs = [sv.wait(t, 300) for t in [run(sv, r) for r in reqs]]
+    st1 = sv.stats()
+    sv.close()
+    log("reserved GB per slot %.2f, allocations %d -> %d" % (st0["reserved_bytes_per_slot"] / 2 ** 30,
+                                                               st0["allocations"], st1["allocations"]))
+    assert st1["allocations"] == st0["allocations"]
+    assert all(o["status"] == 0 for o in warm + outs)
+    for a, b in zip(warm, outs[:3]):
+        assert np.array_equal(a["dos"], b["dos"]) and a["e_fermi"] == b["e_fermi"]
+        assert np.array_equal(a["density"], b["density"])

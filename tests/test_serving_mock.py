@@ -80,3 +80,51 @@ def test_invalid_requests(mala):
     with pytest.raises(mala.MalaError):
         sv.submit(pos, L, N, rc, tj, eg, -5.0, ne)
     sv.close()
+
+
+def test_reserve_checks_budget_and_idleness(mala):
+    shape = (4, np.array([8.1] * 3), np.array([40] * 3), 4.67, 10, mala_synth.EGRID, 933.0)
+    sv = mala.Server(max_inflight=2, hbm_budget=1 << 40, mock_ns_per_point=0.0)
+    sv.reserve([shape, shape])
+    st = sv.stats()
+    assert st["reserved_bytes_per_slot"] > 0 and st["allocations"] == 0
+    sv.close()
+    # two slots at the reserved size do not fit a budget of one
+    probe = mala.Server(max_inflight=1, hbm_budget=1 << 40, mock_ns_per_point=0.0)
+    probe.reserve([shape])
+    per_slot = probe.stats()["reserved_bytes_per_slot"]
+    probe.close()
+    tight = mala.Server(max_inflight=2, hbm_budget=int(1.5 * per_slot), mock_ns_per_point=0.0)
+    with pytest.raises(mala.MalaError) as e:
+        tight.reserve([shape])
+    assert e.value.status == mala.MALA_E_OOM
+    tight.close()
+    # a server with work in flight refuses to resize its slots
+    busy = mala.Server(max_inflight=1, hbm_budget=1 << 40, mock_ns_per_point=1e4)
+    t = busy.submit(*_req(40))
+    with pytest.raises(mala.MalaError) as e:
+        busy.reserve([shape])
+    assert e.value.status == mala.MALA_E_BUSY
+    busy.wait(t, 30)
+    busy.close()
+
+
+def test_allocation_counter_counts_slot_growth(mala):
+    sv = mala.Server(max_inflight=1, hbm_budget=1 << 40, mock_ns_per_point=0.0)
+    for n in (20, 10, 40, 30):
+        sv.wait(sv.submit(*_req(n)), 30)
+    # the slot grows for the first request and for the larger third one only
+    assert sv.stats()["allocations"] == 2
+    sv.close()
+
+
+def test_inflight_points_cap_runs_large_requests_alone(mala):
+    sv = mala.Server(max_inflight=3, hbm_budget=1 << 40, mock_ns_per_point=500.0)
+    sv.set_inflight_points(40 ** 3)
+    # 40^3 fills the cap alone; the two 20^3 requests may run together
+    tickets = [sv.submit(*_req(n)) for n in (40, 20, 20, 40)]
+    o = [sv.wait(t, 30) for t in tickets]
+    sv.close()
+    assert o[1]["t_start"] >= o[0]["t_done"]            # waits for the large one
+    assert o[2]["t_start"] < o[1]["t_done"]             # small ones overlap
+    assert o[3]["t_start"] >= max(o[1]["t_done"], o[2]["t_done"])
