@@ -247,6 +247,10 @@ mala_status mala_integrate_noalloc(mala_ctx* ctx, const float* ldos, int64_t n_p
  * is solved, the density is finished from those.  If the window does not
  * contain E_F +- 40 kT, a second network pass recomputes the density
  * (decided on the device, no host round trip).
+ *  result->status is MALA_E_CAPACITY (and the density is not written) when
+ *  the context's capacity flags are set: a fixed neighbour capacity was
+ *  exceeded by this call's descriptors or by an earlier call since the last
+ *  mala_check_device_errors (which reports and clears them).
  *  B_cache: device float32 [N_points][n_B] or NULL (then context scratch).
  *  Outputs as in mala_integrate; density_out may be NULL.                   */
 mala_status mala_predict(mala_ctx* ctx, const mala_weights* w, const double* positions,

@@ -67,10 +67,9 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
     const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
     const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
                  oz = (double)qk * bins.L[2] / Nz;
-    const double lo[3] = {wave_min_d(rx), wave_min_d(ry), wave_min_d(rz)};
-    const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
+    const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
     const double org[3] = {ox, oy, oz};
-    const int base = gather_candidates(bins, lo, hi, org, rcut, cand, kMaxCand, scan_tmp);
+    const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)

@@ -188,11 +188,10 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
     const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
     const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
                  oz = (double)qk * bins.L[2] / Nz;
-    const double lo[3] = {wave_min_d(rx), wave_min_d(ry), wave_min_d(rz)};
-    const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
+    const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
     const double org[3] = {ox, oy, oz};
 
-    const int base = gather_candidates(bins, lo, hi, org, rcut, cand, kMaxCand, scan_tmp);
+    const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     for (int c = threadIdx.x; c < ncand; c += blockDim.x) cgrad[c][0] = cgrad[c][1] = cgrad[c][2] = 0.f;

@@ -1062,7 +1062,7 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
     }
     HIP_TRY(staged(c, MALA_STAGE_FERMI, 0, [&] {
         return launch_fermi(c->stream, c->partials.p, nb, eg->n, dV, eg->e0, eg->de, kT, ne, dos_out, c->fermi_w.p,
-                            result, window ? c->win : nullptr, c->li_coef);
+                            result, window ? c->win : nullptr, c->li_coef, c->err);
     }));
     if (density_out) {
         if (window)

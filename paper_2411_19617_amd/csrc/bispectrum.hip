@@ -29,6 +29,8 @@
 //           each exchanged pair of rows is formed.  Clebsch-Gordan values of
 //           the coupling come from a per-triple table in global memory read
 //           with wave-uniform (scalar) loads.
+#include <mutex>
+
 #include "snap_core.h"
 #include "tile_gather.h"
 
@@ -169,12 +171,11 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
     const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
                  oz = (double)qk * bins.L[2] / Nz;
     // bounding box of the tile's points
-    const double lo[3] = {wave_min_d(rx), wave_min_d(ry), wave_min_d(rz)};
-    const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
+    const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
     const double org[3] = {ox, oy, oz};
 
     // ---- candidate atom images within rcut of the box, in a fixed order
-    const int base = gather_candidates(bins, lo, hi, org, rcut, cand, kMaxCand, scan_tmp);
+    const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     __syncthreads();
@@ -458,12 +459,14 @@ static hipError_t zb_tj(hipStream_t s, int64_t n_pts, const float2* u_scratch, f
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
     if (n_tiles == 0) return hipSuccess;
     const size_t lds = sizeof(float2) * n_half(TJ) * kTile;
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zb<TJ>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+    // once per process for this instantiation, whichever thread launches first
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [&] {
+        attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zb<TJ>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    });
+    if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(k_zb<TJ>, dim3((unsigned)n_tiles), dim3(64 * zb_waves), lds, s, u_scratch, n_pts, B_out,
                        cg_table, cg_offsets, wave_triples, kMaxZbStride);
     return hipGetLastError();

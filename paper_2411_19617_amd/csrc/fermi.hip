@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
                                                double* __restrict__ dos_out, double* __restrict__ w_out,
                                                ResultRec* __restrict__ res, WindowRec* __restrict__ win,
                                                const double* __restrict__ coef, int mode, int w_max,
-                                               double margin) {
+                                               double margin, const int* __restrict__ cap_err) {
     __shared__ FermiShared sh;
     const int e = threadIdx.x;
     double d = 0.0;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
                 res->e_entropy = NAN;
                 res->n_target = n_target;
                 res->iterations = 0;
-                res->status = -4;
+                res->status = (cap_err && *cap_err) ? -7 : -4;     // MALA_E_CAPACITY first, else MALA_E_NO_ROOT
                 res->density_from_window = 0;
                 if (win) win->covered = 0;
             } else {
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
         res->e_entropy = -kT * s_kb;
         res->n_target = n_target;
         res->iterations = it;
-        res->status = 0;
+        res->status = (cap_err && *cap_err) ? -7 : 0;     // MALA_E_CAPACITY: neighbour lists were truncated
         res->density_from_window = 0;
         if (win) {
             const bool lo_ok = win->lo == 0 || e0 + win->lo * de <= ef - reach;
@@ -379,9 +379,9 @@ __global__ __launch_bounds__(256) void k_density_ldos(const float* __restrict__ 
 
 hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int n_e, double dV, double e0,
                         double de, double kT, double n_target, double* dos_out, double* weights_out,
-                        void* result, WindowRec* win, const double* li_coef) {
+                        void* result, WindowRec* win, const double* li_coef, const int* cap_err) {
     hipLaunchKernelGGL(k_fermi, dim3(1), dim3(256), 0, s, partials, n_parts, n_e, dV, e0, de, kT, n_target,
-                       dos_out, weights_out, static_cast<ResultRec*>(result), win, li_coef, 0, 0, 0.0);
+                       dos_out, weights_out, static_cast<ResultRec*>(result), win, li_coef, 0, 0, 0.0, cap_err);
     return hipGetLastError();
 }
 
@@ -389,7 +389,7 @@ hipError_t launch_fermi_estimate(hipStream_t s, const double* partials, int n_pa
                                  double e0, double de, double kT, double n_target, WindowRec* win,
                                  const double* li_coef, int w_max, double margin) {
     hipLaunchKernelGGL(k_fermi, dim3(1), dim3(256), 0, s, partials, n_parts, n_e, dV, e0, de, kT, n_target,
-                       nullptr, nullptr, nullptr, win, li_coef, 1, w_max, margin);
+                       nullptr, nullptr, nullptr, win, li_coef, 1, w_max, margin, nullptr);
     return hipGetLastError();
 }
 

@@ -28,9 +28,8 @@ __global__ __launch_bounds__(64) void k_gauss(BinState bins, int Nx, int Ny, int
     const int64_t p0 = pt_begin + tile * kTile;
     const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
     const double org[3] = {(double)qi * bins.L[0] / Nx, (double)qj * bins.L[1] / Ny, (double)qk * bins.L[2] / Nz};
-    const double lo[3] = {wave_min_d(rx), wave_min_d(ry), wave_min_d(rz)};
-    const double hi[3] = {wave_max_d(rx), wave_max_d(ry), wave_max_d(rz)};
-    const int base = gather_candidates(bins, lo, hi, org, cutoff, cand, kMaxCand, scan_tmp);
+    const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
+    const int base = gather_candidates(bins, boxes, org, cutoff, cand, kMaxCand, scan_tmp);
     if (base > kMaxCand && lane == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     __syncthreads();

@@ -331,7 +331,8 @@ hipError_t launch_ldos_colsum(hipStream_t s, const float* ldos, int64_t n_pts, i
 
 hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
                         double e0, double de, double kT, double n_target, double* dos_out,
-                        double* weights_out, void* result, WindowRec* win, const double* li_coef);
+                        double* weights_out, void* result, WindowRec* win, const double* li_coef,
+                        const int* cap_err = nullptr);   // capacity flags: nonzero -> status MALA_E_CAPACITY
 hipError_t launch_fermi_estimate(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
                                  double e0, double de, double kT, double n_target, WindowRec* win,
                                  const double* li_coef, int w_max, double margin);

@@ -41,24 +41,55 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total)
     return wbase + x - v;
 }
 
-// Candidate atom images of a tile whose bounding box is [lo, hi]: every image
-// in the cells overlapping the box grown by rcut that lies within rcut of the
-// box, in a fixed order (cells in index order, atoms in cell order), stored
-// relative to the origin o as float4 in cand[0 .. cap) (w holds the bits of
-// the atom's index).  Called by the whole
-// block; returns the total count, which exceeds cap when the list overflowed
-// (only the first cap are stored).  scan_tmp holds blockDim/64 ints.
-__device__ __forceinline__ int gather_candidates(const BinState& bins, const double lo[3], const double hi[3],
-                                                 const double o[3], double rcut, float4* cand, int cap,
-                                                 int* scan_tmp) {
+// Bounding boxes of a tile of consecutive flat grid indices (lane = point,
+// p0 the tile's first point): box 0 holds the points in p0's run (its z-row
+// when a row has at least 64 points, else its x-plane), box 1 the others.
+// A tile that crosses a row or a plane would otherwise get one box spanning
+// the cell's whole cross-section, and with it far more candidate images.
+struct TileBoxes {
+    double lo[2][3], hi[2][3];
+    int n;            // 1, or 2 when the tile crosses a run boundary
+};
+
+__device__ __forceinline__ TileBoxes tile_boxes(int64_t p, int64_t p0, int Ny, int Nz, double rx, double ry,
+                                                double rz) {
+    const int64_t run = Nz >= 64 ? (int64_t)Nz : (int64_t)Ny * Nz;
+    const bool first = p / run == p0 / run;
+    const double r[3] = {rx, ry, rz};
+    TileBoxes b;
+    for (int d = 0; d < 3; ++d) {
+        b.lo[0][d] = wave_min_d(first ? r[d] : INFINITY);
+        b.hi[0][d] = wave_max_d(first ? r[d] : -INFINITY);
+        b.lo[1][d] = wave_min_d(first ? INFINITY : r[d]);
+        b.hi[1][d] = wave_max_d(first ? -INFINITY : r[d]);
+    }
+    b.n = wave_max_int(first ? 0 : 1) ? 2 : 1;
+    return b;
+}
+
+__device__ __forceinline__ bool near_box(const double lo[3], const double hi[3], double X, double Y, double Z,
+                                         double rc2) {
+    const double dx = fmax(0.0, fmax(lo[0] - X, X - hi[0]));
+    const double dy = fmax(0.0, fmax(lo[1] - Y, Y - hi[1]));
+    const double dz = fmax(0.0, fmax(lo[2] - Z, Z - hi[2]));
+    return dx * dx + dy * dy + dz * dz < rc2;
+}
+
+// One pass of the candidate gather: every image in the cells overlapping box
+// `k` grown by rcut that lies within rcut of that box (and, for k = 1, not
+// within rcut of box 0, whose pass took it already), appended after `base`
+// in a fixed order (cells in index order, atoms in cell order).
+__device__ __forceinline__ int gather_pass(const BinState& bins, const TileBoxes& tb, int k, const double o[3],
+                                           double rcut, float4* cand, int cap, int* scan_tmp, int base) {
     const double rc2 = rcut * rcut;
+    const double* lo = tb.lo[k];
+    const double* hi = tb.hi[k];
     int c_lo[3], c_n[3];
     for (int d = 0; d < 3; ++d) {
         c_lo[d] = (int)floor((lo[d] - rcut) / bins.cs[d]);
         c_n[d] = (int)floor((hi[d] + rcut) / bins.cs[d]) - c_lo[d] + 1;
     }
     const int ncells = c_n[0] * c_n[1] * c_n[2];
-    int base = 0;
     for (int c0 = 0; c0 < ncells; c0 += blockDim.x) {
         const int c = c0 + threadIdx.x;
         int cnt = 0, b = 0, e = 0;
@@ -78,10 +109,7 @@ __device__ __forceinline__ int gather_candidates(const BinState& bins, const dou
             for (int a = b; a < e; ++a) {
                 const double4 at = bins.atoms[a];
                 const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
-                const double dx = fmax(0.0, fmax(lo[0] - X, X - hi[0]));
-                const double dy = fmax(0.0, fmax(lo[1] - Y, Y - hi[1]));
-                const double dz = fmax(0.0, fmax(lo[2] - Z, Z - hi[2]));
-                cnt += (dx * dx + dy * dy + dz * dz < rc2);
+                cnt += near_box(lo, hi, X, Y, Z, rc2) && !(k == 1 && near_box(tb.lo[0], tb.hi[0], X, Y, Z, rc2));
             }
         }
         int total;
@@ -89,10 +117,7 @@ __device__ __forceinline__ int gather_candidates(const BinState& bins, const dou
         for (int a = b; a < e; ++a) {
             const double4 at = bins.atoms[a];
             const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
-            const double dx = fmax(0.0, fmax(lo[0] - X, X - hi[0]));
-            const double dy = fmax(0.0, fmax(lo[1] - Y, Y - hi[1]));
-            const double dz = fmax(0.0, fmax(lo[2] - Z, Z - hi[2]));
-            if (dx * dx + dy * dy + dz * dz < rc2) {
+            if (near_box(lo, hi, X, Y, Z, rc2) && !(k == 1 && near_box(tb.lo[0], tb.hi[0], X, Y, Z, rc2))) {
                 if (off < cap)
                     cand[off] = make_float4((float)(X - o[0]), (float)(Y - o[1]), (float)(Z - o[2]),
                                             __int_as_float((int)at.w));
@@ -101,6 +126,18 @@ __device__ __forceinline__ int gather_candidates(const BinState& bins, const dou
         }
         base += total;
     }
+    return base;
+}
+
+// Candidate atom images of a tile with boxes `tb`: every image within rcut
+// of one of its boxes, each once, stored relative to the origin o as float4
+// in cand[0 .. cap) (w holds the bits of the atom's index).  Called by the
+// whole block; returns the total count, which exceeds cap when the list
+// overflowed (only the first cap are stored).  scan_tmp holds blockDim/64 ints.
+__device__ __forceinline__ int gather_candidates(const BinState& bins, const TileBoxes& tb, const double o[3],
+                                                 double rcut, float4* cand, int cap, int* scan_tmp) {
+    int base = gather_pass(bins, tb, 0, o, rcut, cand, cap, scan_tmp, 0);
+    if (tb.n == 2) base = gather_pass(bins, tb, 1, o, rcut, cand, cap, scan_tmp, base);
     return base;
 }
 

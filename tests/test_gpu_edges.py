@@ -108,3 +108,43 @@ def test_neighbour_capacity_is_reported(env):
         ctx.check_device_errors()
     assert e.value.status == mala.MALA_E_CAPACITY
     ctx.check_device_errors()                                   # flag cleared
+
+
+def test_predict_status_reports_capacity(env):
+    """The fused call carries the capacity flag into its result record."""
+    mala, ctx, torch = env
+    rng = mala_synth.SplitMix64(5)
+    pos = (rng.uniform(600).reshape(200, 3) - 0.5) * 1.0 + 5.0
+    w = ctx.weights(mala_synth.net_to_blob(mala_synth.small_net()), mala.PREC_FP32)
+    dos, dens, res = ctx.mala_predict(w, pos, [10.0, 10.0, 10.0], [4, 4, 4], 4.67, 8, EG, 298.0, 600.0)
+    r = mala.read_result(res)
+    log("capacity in predict:", r["status"])
+    assert r["status"] == mala.MALA_E_CAPACITY
+    with pytest.raises(mala.MalaError):
+        ctx.check_device_errors()
+    ctx.check_device_errors()
+
+
+@pytest.mark.parametrize("grid", [(60, 103, 121), (120, 200, 37)])
+def test_tiles_crossing_rows_and_planes_of_a_large_cell(env, grid):
+    """The 16,384-atom slab on grids whose planes (and, for 121, rows) hold a
+    number of points that is not a multiple of 64: tiles cross z-rows and
+    x-planes, and each keeps two compact boxes (one box would span the
+    cell's 79 x 92 A cross-section: several thousand candidates)."""
+    mala, ctx, torch = env
+    s = mala_synth.with_grid(mala_synth.slab(), grid)
+    plane = grid[1] * grid[2]
+    assert plane % 64 != 0
+    # a range over several plane boundaries, from a point that is not 64-aligned
+    b = 7 * plane - 1000
+    e = b + 4 * plane + 333
+    B = ctx.mala_descriptors(s.positions, s.L, s.N, s.rcut, s.twojmax, b, e).cpu().double().numpy()
+    ctx.check_device_errors()                          # no candidate overflow
+    seam = [k * plane + d for k in range(8, 11) for d in (-2, -1, 0, 1, 2, 40)]
+    rows = [k * plane + j * grid[2] + d for k in (8, 9) for j in (0, grid[1] // 2, grid[1] - 1) for d in (-1, 0, 1)]
+    pts = np.unique(np.concatenate([np.array(seam + rows, dtype=np.int64),
+                                    b + mala_synth.sample_points(e - b, 120, 61)]))
+    pts = pts[(pts >= b) & (pts < e)]
+    err = rel_rows(B[pts - b], oracle.descriptors(s, pts))
+    log("grid", grid, "crossing tiles: B rel err %.3e over %d points" % (err, len(pts)))
+    assert err <= 1e-5
