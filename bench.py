@@ -137,7 +137,8 @@ def cpu_baseline(snap, net, n_sample):
     return rec, pts, B, ld
 
 
-TRAFFIC_FILES = {"paper_solid": "traffic_k_zb_al256_solid_90c_tj10.txt"}
+TRAFFIC_FILES = {"al256_solid_298K_90c_tj10": "traffic_k_zb_al256_solid_90c_tj10.txt",
+                 "al16384_slab111_fault_298K_tj10": "traffic_k_zb_al16384_slab_tj10.txt"}
 
 
 def kernel_source_hash():
@@ -148,10 +149,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(snapshot):
     """HBM bytes per k_zb launch from the committed, calibrated rocprofv3 counters;
-    None if there are none for this workload or the kernel source changed since."""
-    name = TRAFFIC_FILES.get(workload)
+    None if there are none for this snapshot or the kernel source changed since."""
+    name = TRAFFIC_FILES.get(snapshot)
     path = os.path.join(ROOT, "profiles", name) if name else None
     if not path or not os.path.exists(path):
         return None
@@ -162,11 +163,11 @@ def measured_traffic(workload):
 
 
 TRAFFIC_CMDS = """# commands (repository root = $REPO, output directory $OUT, after cd /tmp && export TMPDIR=/tmp):
-#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
-#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- python $REPO/bench.py --steps 1 --warmup 1 --no-cpu-baseline --serve-requests 0 --no-extras
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- python $REPO/bench.py --workload %(w)s --headline-only --steps 1 --warmup 1 --no-cpu-baseline
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- python $REPO/bench.py --workload %(w)s --headline-only --steps 1 --warmup 1 --no-cpu-baseline
 #   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_cfetch -o run -- python $REPO/bench.py --copy-calibration
 #   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_cwrite -o run -- python $REPO/bench.py --copy-calibration
-#   python bench.py --traffic-summary $OUT/pmc_fetch $OUT/pmc_write $OUT/pmc_cfetch $OUT/pmc_cwrite
+#   python bench.py --workload %(w)s --traffic-summary $OUT/pmc_fetch $OUT/pmc_write $OUT/pmc_cfetch $OUT/pmc_cwrite
 """
 COPY_GIB = 1
 
@@ -218,10 +219,10 @@ def traffic_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload="pape
     alg = n_half * 8 + n_b * 4
     per_launch = float(np.mean(fb) + np.mean(wb))
     per_point = (sum(fb) + sum(wb)) / float(sum(pts))
-    name = TRAFFIC_FILES[workload]
+    name = TRAFFIC_FILES[snap.name]
     with open(os.path.join(ROOT, "profiles", name), "w") as f:
         f.write("# HBM traffic of k_zb<10> (Z/B contraction), %s\n" % snap.name)
-        f.write(TRAFFIC_CMDS)
+        f.write(TRAFFIC_CMDS % {"w": workload})
         f.write("# calibration: the same two counters on a plain %d GiB device-to-device copy (torch copy_ ->\n"
                 "# __amd_rocclr_copyBuffer), %d copies: FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB per copy of %.0f KiB\n"
                 % (COPY_GIB, len(cf), np.mean(cf), np.mean(cw), copy_kib))
@@ -296,6 +297,127 @@ def stats_summary(prof_dir, bench_json, out_name, command):
                   "%s %.3f" % (k, v["ms_per_step"]) for k, v in b["stages"].items()), ""]
     with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
         fo.write("\n".join(lines))
+    print("wrote profiles/%s" % out_name)
+
+
+def probe_kernels():
+    """Each kernel family once after one warm-up call, on the 729,000-point
+    solid: the fused path in FP32 and BF16 (cell list, k_ui, k_zb, k_mlp,
+    k_fermi), grid ACE (k_ace), the network VJP (k_mlp_vjp) and the
+    descriptor VJP (k_yi, k_dedr).  A short program for counter runs."""
+    import torch
+    import paper_2411_19617_amd as mala
+    mala.lib()
+    ctx = mala.Context(0)
+    snap, net = WORKLOADS["paper_solid"][0](), WORKLOADS["paper_solid"][1]()
+    blob = mala_synth.net_to_blob(net)
+    for prec in (mala.PREC_FP32, mala.PREC_BF16):
+        w = ctx.weights(blob, prec)
+        for _ in range(2):
+            ctx.mala_predict(w, snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, mala_synth.EGRID, snap.T,
+                             snap.n_electrons)
+    for _ in range(2):
+        ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, 4, 4)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    B = ctx.mala_descriptors(snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax)
+    v = torch.randn((snap.n_points, 250), generator=gen, device="cuda", dtype=torch.float32)
+    w = ctx.weights(blob, mala.PREC_FP32)
+    for _ in range(2):
+        g = ctx.mala_ldos_vjp(w, B, v)
+    for _ in range(2):
+        ctx.mala_descriptors_vjp(snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax, g)
+    torch.cuda.synchronize()
+    ctx.check_device_errors()
+    ctx.close()
+    print("probe done", flush=True)
+
+
+COUNTER_KERNELS = ["mala::k_ui<", "mala::k_zb<", "mala::k_mlp<0", "mala::k_mlp<1", "mala::k_ace",
+                   "mala::k_mlp_vjp", "mala::k_yi", "mala::k_dedr"]
+
+
+def counter_summary(out_name, command, dirs):
+    """Per-kernel sums of rocprofv3 --pmc counters (one or more runs, one
+    counter set each) and the ratios derived from them: the GPU clock from
+    GRBM_GUI_ACTIVE over the dispatch time, VALU issue use (a wave64 VALU
+    instruction holds its SIMD for 4 cycles), MFMA busy, LDS bank
+    conflicts, FMA share."""
+    import csv
+    import glob
+    import re
+    acc = {}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit("no counter_collection.csv under %s" % d)
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                name = _short_kernel_name(r["Kernel_Name"])
+                key = next((k for k in COUNTER_KERNELS if name.startswith(k)), None)
+                if key is None:
+                    continue
+                a = acc.setdefault(name, {"dispatch": {}, "counters": {}})
+                dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+                a["dispatch"][(d, r["Dispatch_Id"])] = dur
+                c = a["counters"].setdefault(r["Counter_Name"], {})
+                c[(d, r["Dispatch_Id"])] = c.get((d, r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+    lines = ["# rocprofv3 counters per kernel", "", "Commands (repository root = $REPO, output directory $OUT, "
+             "after `cd /tmp && export TMPDIR=/tmp`; one counter set per run):", "", "```"]
+    lines += [command.replace("{DIR}", os.path.basename(os.path.normpath(d)).replace("pmc_", "")) for d in dirs]
+    lines += ["```", "", "Counter sums over the kernel's dispatches of each run; derived ratios use the dispatch "
+              "times of the same runs (counter collection serialises dispatches).  GRBM_GUI_ACTIVE is read as "
+              "the sum over the 8 XCDs (its per-dispatch value divided by 8 x the dispatch time gives the clock).  "
+              "VALU issue = SQ_INSTS_VALU x 4 cycles / (1,024 SIMDs x cycles); MFMA busy = "
+              "SQ_VALU_MFMA_BUSY_CYCLES / (1,024 SIMDs x cycles); LDS conflict = SQ_LDS_BANK_CONFLICT / "
+              "SQ_LDS_IDX_ACTIVE.", ""]
+    names = sorted(acc)
+    counters = sorted({c for n in names for c in acc[n]["counters"]})
+    lines += ["| kernel | dispatches | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
+    derived = []
+    for n in names:
+        a = acc[n]
+        row = ["`%s`" % n, str(max(len(v) for v in a["counters"].values()))]
+        tot = {}
+        for c in counters:
+            v = a["counters"].get(c)
+            tot[c] = sum(v.values()) if v else None
+            row.append("%.4g" % tot[c] if v else "")
+        lines.append("| " + " | ".join(row) + " |")
+        # derived ratios per run that holds the needed counters
+        def per(c):
+            v = a["counters"].get(c)
+            if not v:
+                return None
+            keys = list(v)
+            return sum(v.values()), sum(a["dispatch"][k] for k in keys)
+        g = per("GRBM_GUI_ACTIVE")
+        d = {"kernel": n}
+        if g and g[1] > 0:
+            d["clock_GHz"] = g[0] / 8.0 / g[1] / 1e9
+            d["ms_per_dispatch"] = 1e3 * g[1] / max(len(a["counters"]["GRBM_GUI_ACTIVE"]), 1)
+        cyc_per_s = (d.get("clock_GHz") or 2.4) * 1e9
+        for c, label, scale in (("SQ_INSTS_VALU", "valu_issue", 4.0), ("SQ_VALU_MFMA_BUSY_CYCLES", "mfma_busy", 1.0)):
+            x = per(c)
+            if x and x[1] > 0:
+                d[label] = x[0] * scale / (1024.0 * cyc_per_s * x[1])
+        x, y = per("SQ_INSTS_VALU_FMA_F32"), per("SQ_INSTS_VALU")
+        if x and y and y[0] > 0 and x[1] == y[1]:
+            d["fma_share_of_valu"] = x[0] / y[0]
+        x, y = per("SQ_LDS_BANK_CONFLICT"), per("SQ_LDS_IDX_ACTIVE")
+        if x and y and y[0] > 0:
+            d["lds_conflict_share"] = x[0] / y[0]
+        x, y = per("SQ_INSTS_LDS"), per("SQ_INSTS_VALU")
+        if x and y and y[0] > 0 and x[1] == y[1]:
+            d["lds_per_valu"] = x[0] / y[0]
+        derived.append(d)
+    keys = ["clock_GHz", "ms_per_dispatch", "valu_issue", "fma_share_of_valu", "lds_per_valu", "mfma_busy",
+            "lds_conflict_share"]
+    lines += ["", "| kernel | " + " | ".join(keys) + " |", "|---|" + "---|" * len(keys)]
+    for d in derived:
+        lines.append("| `%s` | " % d["kernel"] + " | ".join("%.3f" % d[k] if k in d else "" for k in keys) + " |")
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
+        fo.write("\n".join(lines) + "\n")
     print("wrote profiles/%s" % out_name)
 
 
@@ -657,6 +779,11 @@ def main():
     ap.add_argument("--traffic-summary", nargs=4, metavar="DIR",
                     help="write the calibrated k_zb traffic profile from four rocprofv3 --pmc output "
                          "directories (kernel FETCH_SIZE, WRITE_SIZE; copy FETCH_SIZE, WRITE_SIZE); no GPU")
+    ap.add_argument("--probe-kernels", action="store_true",
+                    help="run each kernel family once on the 256-atom solid (a short program for counter runs)")
+    ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
+                    help="OUT_NAME COMMAND_TEMPLATE DIR...: write a profiles/ markdown table of rocprofv3 --pmc "
+                         "counters per kernel from one or more output directories; no GPU")
     ap.add_argument("--stats-summary", nargs=4, metavar=("PROF_DIR", "BENCH_LOG", "OUT_NAME", "COMMAND"),
                     help="write a profiles/ markdown table from a rocprofv3 --kernel-trace --stats run; no GPU")
     a = ap.parse_args()
@@ -664,10 +791,16 @@ def main():
         stats_summary(*a.stats_summary)
         return
     if a.traffic_summary:
-        traffic_summary(*a.traffic_summary)
+        traffic_summary(*a.traffic_summary, workload=a.workload)
+        return
+    if a.counter_summary:
+        counter_summary(a.counter_summary[0], a.counter_summary[1], a.counter_summary[2:])
         return
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.probe_kernels:
+        probe_kernels()
         return
     if a.gpus != 1:
         print("bench.py measures one GPU: the path shards by grid slabs with one 2 KB DOS all-reduce, "
