@@ -318,6 +318,8 @@ def probe_kernels():
                              snap.n_electrons)
     for _ in range(2):
         ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, 4, 4)
+    for _ in range(2):
+        ctx.mala_ace4_descriptors(snap.positions, snap.L, snap.N, snap.rcut, 3, 3)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
     B = ctx.mala_descriptors(snap.positions, snap.L, snap.N, snap.rcut, snap.twojmax)
@@ -333,7 +335,7 @@ def probe_kernels():
     print("probe done", flush=True)
 
 
-COUNTER_KERNELS = ["mala::k_ui<", "mala::k_zb<", "mala::k_mlp<0", "mala::k_mlp<1", "mala::k_ace",
+COUNTER_KERNELS = ["mala::k_ui<", "mala::k_zb<", "mala::k_mlp<0", "mala::k_mlp<1", "mala::k_ace4", "mala::k_ace",
                    "mala::k_mlp_vjp", "mala::k_yi", "mala::k_dedr"]
 
 
@@ -596,6 +598,46 @@ def ace_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax=4, lmax=4):
     return {"nmax": nmax, "lmax": lmax, "descriptors": mala.ace_count(nmax, lmax), "rank3_terms": terms,
             "ms_per_grid": ms, "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl,
             "tflops": tf, "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS}
+
+
+def ace4_flops(mala, nmax4, lmax4, mean_nbr):
+    """Work of the rank-4 grid ACE descriptors per point: the projection
+    (4 flop per (n < 4, l <= 4, m >= 0) and neighbour), 10 flop per term of
+    the coupled pairs P_a(M) = sum <l1 m1 l2 m2|L M> A A (M >= 0; terms where
+    both m lie in range, the structural count) and 4 flop per M of every
+    descriptor's inner product."""
+    nl = lmax4 + 1
+    pairs, desc = set(), 0.0
+    for p1, p2, p3, p4, L in mala.ace4_list(nmax4, lmax4):
+        pairs.add((p1, p2, L))
+        pairs.add((p3, p4, L))
+        desc += 4.0 * (L + 1)
+    terms = 0
+    for p1, p2, L in pairs:
+        l1, l2 = p1 % nl, p2 % nl
+        terms += sum(1 for M in range(L + 1) for m1 in range(-l1, l1 + 1) if abs(M - m1) <= l2)
+    proj = 4.0 * 4 * 15 * mean_nbr
+    return proj + 10.0 * terms + desc, terms
+
+
+def ace4_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax4=3, lmax4=3):
+    """Rank-4 grid ACE descriptors (nmax4 = lmax4 = 3) over the whole grid,
+    outside the metric's step."""
+    out = ctx.mala_ace4_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax4, lmax4)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_ace4_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax4, lmax4, out=out)
+    ms = ctx.profile_read()["ace4"][0] / reps
+    ctx.profile_enable(False)
+    ctx.check_device_errors()
+    fl, terms = ace4_flops(mala, nmax4, lmax4, mean_nbr)
+    tf = fl * snap.n_points / (ms * 1e-3) / 1e12
+    n4 = mala.ace4_count(nmax4, lmax4)
+    del out
+    return {"nmax4": nmax4, "lmax4": lmax4, "descriptors": n4, "pair_terms": terms, "ms_per_grid": ms,
+            "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl, "tflops": tf,
+            "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS,
+            "write_GB_s": 4.0 * n4 * snap.n_points / (ms * 1e-3) / 1e9}
 
 
 def serving_bench(mala, prec, reqs, n_main, n_side=200, slots=4, budget_gb=64, loads=(0.5, 0.7, 0.9), seed=5,
@@ -874,6 +916,7 @@ def main():
         out["network_vjp"] = network_vjp_bench(ctx, mala, es, WORKLOADS["paper_solid"][1](), torch)
         out["descriptor_vjp"] = descriptor_adjoint_bench(ctx, es, torch)
         out["ace_descriptors"] = ace_bench(ctx, mala, es, efl["mean_neighbours"], torch)
+        out["ace4_descriptors"] = ace4_bench(ctx, mala, es, efl["mean_neighbours"], torch)
         print("extras done", file=sys.stderr, flush=True)
     if a.serve_requests > 0:
         sv = {}

@@ -178,6 +178,29 @@ mala_status mala_ace_descriptors(mala_ctx* ctx, const double* positions, int32_t
                                  const mala_cell_grid* cg, double rcut, int32_t nmax, int32_t lmax,
                                  int64_t pt_begin, int64_t pt_end, float* out);
 
+/* Grid ACE descriptors of rank 4 (Sec. 3.2.3, Eq. ace_grid with four
+ * factors and one intermediate coupling L, the generalized Clebsch-Gordan
+ * coefficient of the coupling tree ((l1 l2) L, (l3 l4) L) -> 0):
+ *   B = sum_m <l1 m1 l2 m2|L M> <l3 m3 l4 m4|L -M> (-1)^(L-M)/sqrt(2L+1)
+ *       A_{n1 l1 m1} A_{n2 l2 m2} A_{n3 l3 m3} A_{n4 l4 m4},  M = m1 + m2,
+ * with A, the radial basis and the self term as for mala_ace_descriptors.
+ * The set: for keys p = n (lmax4+1) + l (n < nmax4, l <= lmax4), every
+ * multiset p1 <= p2 <= p3 <= p4 with an even l-sum and, for it, the
+ * couplings L in increasing order whose coefficients (summed over the
+ * permutations that exchange equal keys) are linearly independent of those
+ * kept before: the non-redundant rank-4 descriptors the paper requires.
+ *  nmax4 in 1..3, lmax4 in 0..3 (MALA_E_UNSUPPORTED otherwise);
+ *  out: device float32 [pt_end - pt_begin][mala_ace4_count(nmax4, lmax4)],
+ *  in the order of mala_ace4_list.
+ * mala_ace4_list writes (p1, p2, p3, p4, L) per descriptor into out[5 n]
+ * (host int32, cap entries of five) and returns the count, or < 0 if the
+ * sizes are unsupported or cap is too small.  Empty ranges are a no-op.    */
+int32_t mala_ace4_count(int32_t nmax4, int32_t lmax4);
+int32_t mala_ace4_list(int32_t nmax4, int32_t lmax4, int32_t* out, int32_t cap);
+mala_status mala_ace4_descriptors(mala_ctx* ctx, const double* positions, int32_t n_atoms,
+                                  const mala_cell_grid* cg, double rcut, int32_t nmax4, int32_t lmax4,
+                                  int64_t pt_begin, int64_t pt_end, float* out);
+
 /* Gaussian descriptors of grid points [pt_begin, pt_end): the Gaussian
  * representation of the ionic positions behind the structure factor
  * (Eq. structurefactor_gaussian), a Gaussian of width sigma normalised to
@@ -351,7 +374,8 @@ mala_status mala_server_destroy(mala_server* s);
 #define MALA_STAGE_ADJ_Y 12       /* descriptor adjoint: dL/du               */
 #define MALA_STAGE_ADJ_DEDR 13    /* descriptor adjoint: dL/dR               */
 #define MALA_STAGE_ACE 14         /* grid ACE descriptors                    */
-#define MALA_N_STAGES 15
+#define MALA_STAGE_ACE4 15        /* grid ACE descriptors of rank 4          */
+#define MALA_N_STAGES 16
 mala_status mala_profile_enable(mala_ctx* ctx, int32_t on);
 mala_status mala_profile_read(mala_ctx* ctx, double* ms, int64_t* launches, int64_t* points);
 

@@ -26,7 +26,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 RESULT_BYTES = 64
 STAGES = ["bin", "ui", "zb", "mlp_ldos", "mlp_dos", "fermi", "mlp_density", "integrate", "estimate",
-          "density_window", "gauss", "mlp_vjp", "adj_y", "adj_dedr", "ace"]
+          "density_window", "gauss", "mlp_vjp", "adj_y", "adj_dedr", "ace", "ace4"]
 DENSITY_WINDOW = 0
 DENSITY_RECOMPUTE = 1
 
@@ -86,6 +86,9 @@ def lib():
             ("mala_descriptors_vjp", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p, p]),
             ("mala_ace_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, p]),
             ("mala_ace_count", [i32, i32]),
+            ("mala_ace4_count", [i32, i32]),
+            ("mala_ace4_list", [i32, i32, p, i32]),
+            ("mala_ace4_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, p]),
             ("mala_gaussian_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, d, i64, i64, p]),
             ("mala_ldos_infer", [p, p, p, i64, p]),
             ("mala_ldos_vjp", [p, p, p, p, i64, p]),
@@ -123,6 +126,24 @@ def ace_count(nmax, lmax):
     if n < 0:
         raise MalaError(n, "grid ACE: nmax must be 1..4 and lmax 0..4")
     return n
+
+
+def ace4_count(nmax4, lmax4):
+    """Rank-4 grid ACE descriptors per point for (nmax4, lmax4); raises if unsupported."""
+    n = int(lib().mala_ace4_count(int(nmax4), int(lmax4)))
+    if n < 0:
+        raise MalaError(n, "rank-4 grid ACE: nmax4 must be 1..3 and lmax4 0..3")
+    return n
+
+
+def ace4_list(nmax4, lmax4):
+    """The library's rank-4 descriptor set: [(p1, p2, p3, p4, L), ...] in output order."""
+    n = ace4_count(nmax4, lmax4)
+    buf = (ctypes.c_int32 * (5 * max(n, 1)))()
+    got = int(lib().mala_ace4_list(int(nmax4), int(lmax4), buf, n))
+    if got != n:
+        raise MalaError(got, "mala_ace4_list")
+    return [tuple(buf[5 * k:5 * k + 5]) for k in range(n)]
 
 
 def _check(st):
@@ -276,6 +297,21 @@ class Context:
         cg = _cell_grid(L, N)
         _check(lib().mala_descriptors_vjp(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(twojmax),
                                           int(pt_begin), int(pt_end), _ptr(gB), _ptr(out)))
+        return out
+
+    def mala_ace4_descriptors(self, positions, L, N, rcut, nmax4=3, lmax4=3, pt_begin=0, pt_end=None, out=None):
+        """Rank-4 grid ACE descriptors [pt_end - pt_begin][ace4_count(nmax4, lmax4)] (device float32)."""
+        import torch
+        self._sync_stream()
+        pos, pp, n_at = _positions(positions)
+        ntot = int(N[0]) * int(N[1]) * int(N[2])
+        pt_end = ntot if pt_end is None else int(pt_end)
+        nd = ace4_count(nmax4, lmax4)
+        if out is None:
+            out = torch.empty((max(pt_end - pt_begin, 0), nd), dtype=torch.float32, device=self.torch_device)
+        cg = _cell_grid(L, N)
+        _check(lib().mala_ace4_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(nmax4),
+                                           int(lmax4), int(pt_begin), int(pt_end), _ptr(out)))
         return out
 
     def mala_ace_descriptors(self, positions, L, N, rcut, nmax=4, lmax=4, pt_begin=0, pt_end=None, out=None):

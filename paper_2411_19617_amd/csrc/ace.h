@@ -12,6 +12,17 @@ constexpr int kAceMaxL = 4;      // angular momentum
 inline int ace_count_ranks12(int nmax, int lmax) { return nmax + (lmax + 1) * nmax * (nmax + 1) / 2; }
 int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<int>& term_idx,
                      std::vector<float>& term_coef, std::vector<int>& outputs);
+// rank 4: descriptor set (p1, p2, p3, p4, L per entry) and its evaluation tables
+constexpr int kAce4MaxN = 3;
+constexpr int kAce4MaxL = 3;
+constexpr size_t kAce4LdsBudget = 96 * 1024;     // dynamic LDS of the pair vectors of one L
+int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc);
+int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
+                      std::vector<int>& term_idx, std::vector<float>& term_coef, std::vector<int>& l_descs,
+                      std::vector<int4>& descs, int& max_slots);
+hipError_t launch_ace4(hipStream_t s, const BinState& bins, const int N[3], double rcut, int lmax4, int64_t pt_begin,
+                       int64_t n_pts, const int* l_units, const int4* units, const int2* terms, const int* l_descs,
+                       const int4* descs, int max_slots, int n4, float* out, int* err);
 hipError_t launch_ace(hipStream_t s, const BinState& bins, const int N[3], double rcut, int nmax, int lmax,
                       int64_t pt_begin, int64_t n_pts, const int* groups, int n_groups, const int2* terms,
                       const int* outputs, int n_desc, float* out, int* err);

@@ -19,6 +19,8 @@
 // packed terms (storage indices, conjugation flags, 3j symbol with signs,
 // sorted by m3) read with wave-uniform loads, then B = sum_m3 P(m3) A_{n3 l3 m3}
 // for every n3 of the group.  Bound: LDS reads and the table loads.
+#include <mutex>
+
 #include "ace.h"
 #include "tile_gather.h"
 
@@ -45,21 +47,23 @@ __host__ __device__ constexpr float ace_norm(int l, int m) {
     return (float)ace_sqrt((2 * l + 1) / (4.0 * 3.14159265358979323846) * ace_fact(l - m) / ace_fact(l + m));
 }
 
-__global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
-                                            int64_t pt_begin, int64_t n_pts, const int* __restrict__ groups,
-                                            int n_groups, const int2* __restrict__ terms,
-                                            const int* __restrict__ outputs, int n_desc, float* __restrict__ out,
-                                            int* __restrict__ err) {
-    __shared__ float4 cand[kMaxCand];
-    __shared__ float2 sA[kAceN * kAceLm][kTile];
-    __shared__ int scan_tmp[16];
+// The tile's own point (lane = point) relative to the tile origin, and its
+// candidate atom images gathered into cand (whole block).
+struct AceTile {
+    int64_t idx;      // point index within the launch range
+    bool valid;
+    float px, py, pz;
+    int ncand;
+};
 
+__device__ __forceinline__ AceTile ace_tile(const BinState& bins, int Nx, int Ny, int Nz, double rcut, int64_t pt_begin,
+                                            int64_t n_pts, float4* cand, int* scan_tmp, int* err) {
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tile = blockIdx.x;
-    const int64_t idx = tile * kTile + lane;
-    const bool valid = idx < n_pts;
-    const int64_t p = pt_begin + (valid ? idx : tile * kTile);
+    AceTile t;
+    t.idx = tile * kTile + lane;
+    t.valid = t.idx < n_pts;
+    const int64_t p = pt_begin + (t.valid ? t.idx : tile * kTile);
     const int64_t pk = p % Nz, pj = (p / Nz) % Ny, pi = p / ((int64_t)Ny * Nz);
     const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
                  rz = (double)pk * bins.L[2] / Nz;
@@ -71,12 +75,20 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
     const double org[3] = {ox, oy, oz};
     const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
-    const int ncand = base < kMaxCand ? base : kMaxCand;
-    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)
-        sA[e / kTile][e % kTile] = make_float2(0.f, 0.f);
-    __syncthreads();
+    t.ncand = base < kMaxCand ? base : kMaxCand;
+    t.px = (float)(rx - ox);
+    t.py = (float)(ry - oy);
+    t.pz = (float)(rz - oz);
+    return t;
+}
 
-    const float px = (float)(rx - ox), py = (float)(ry - oy), pz = (float)(rz - oz);
+// Adds the lane's A_nlm (n < 4, l <= 4, m >= 0) into sA (zeroed by the
+// caller): wave w of nw visits candidates w, w + nw, ...; wave 0 adds the
+// grid point's own delta.
+__device__ __forceinline__ void ace_project(const float4* cand, const AceTile& tl, double rcut, int wave, int nw,
+                                            int lane, float2 (*sA)[kTile]) {
+    const int ncand = tl.ncand;
+    const float px = tl.px, py = tl.py, pz = tl.pz;
     const float rcf = (float)rcut, rc2 = rcf * rcf;
     constexpr float kpi = 3.14159265358979323846f;
     float ar[kAceN][kAceLm], ai[kAceN][kAceLm];
@@ -89,7 +101,7 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
 #pragma unroll
         for (int n = 0; n < kAceN; ++n) ar[n][0] = (n & 1) ? -y00 : y00;  // the grid point's own delta
     }
-    for (int c = wave; c < ncand; c += kAceWaves) {
+    for (int c = wave; c < ncand; c += nw) {
         const float4 q = cand[c];
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -155,6 +167,26 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
             atomicAdd(&sA[n * kAceLm + e][lane].x, ar[n][e]);
             atomicAdd(&sA[n * kAceLm + e][lane].y, ai[n][e]);
         }
+}
+
+__global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
+                                            int64_t pt_begin, int64_t n_pts, const int* __restrict__ groups,
+                                            int n_groups, const int2* __restrict__ terms,
+                                            const int* __restrict__ outputs, int n_desc, float* __restrict__ out,
+                                            int* __restrict__ err) {
+    __shared__ float4 cand[kMaxCand];
+    __shared__ float2 sA[kAceN * kAceLm][kTile];
+    __shared__ int scan_tmp[16];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const AceTile tl = ace_tile(bins, Nx, Ny, Nz, rcut, pt_begin, n_pts, cand, scan_tmp, err);
+    const int64_t idx = tl.idx;
+    const bool valid = tl.valid;
+    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)
+        sA[e / kTile][e % kTile] = make_float2(0.f, 0.f);
+    __syncthreads();
+    ace_project(cand, tl, rcut, wave, kAceWaves, lane, sA);
     __syncthreads();
 
     float* o = out + (valid ? idx : 0) * n_desc;
@@ -249,6 +281,119 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
             if (valid) o[n12 + (ok >> 7)] = v;
         }
     }
+}
+
+// Rank 4 (one intermediate coupling L).  Eight waves per 64-point tile:
+// after the projection, for every L the coupled pairs
+// P_a(M) = sum_m1 <l1 m1 l2 m2|L M> A_p1 A_p2 (M = 0..L) the descriptors of
+// that L need are formed into LDS (every wave takes every eighth unit
+// (a, M)), then every wave evaluates a contiguous share of that L's
+// descriptors, B = f (Re P_a(0) conj P_b(0) + 2 sum_{M>0} Re P_a(M) conj P_b(M))
+// (f = (-1)^(l3+l4) / sqrt(2L+1)), keeping P_a in registers while consecutive
+// descriptors share it.  Terms and descriptors come from wave-uniform loads.
+constexpr int kAce4Waves = 8;
+
+__global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(BinState bins, int Nx, int Ny, int Nz, double rcut,
+                                                          int lmax4, int64_t pt_begin, int64_t n_pts,
+                                                          const int* __restrict__ l_units,
+                                                          const int4* __restrict__ units,
+                                                          const int2* __restrict__ terms,
+                                                          const int* __restrict__ l_descs,
+                                                          const int4* __restrict__ descs, int n4,
+                                                          float* __restrict__ out, int* __restrict__ err) {
+    __shared__ float4 cand[kMaxCand];
+    __shared__ float2 sA[kAceN * kAceLm][kTile];
+    __shared__ int scan_tmp[16];
+    extern __shared__ float2 sP[];          // [slots][kTile]
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const AceTile tl = ace_tile(bins, Nx, Ny, Nz, rcut, pt_begin, n_pts, cand, scan_tmp, err);
+    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)
+        sA[e / kTile][e % kTile] = make_float2(0.f, 0.f);
+    __syncthreads();
+    ace_project(cand, tl, rcut, wave, kAce4Waves, lane, sA);
+    __syncthreads();
+
+    float* o = out + (tl.valid ? tl.idx : 0) * n4;
+    for (int L = 0; L <= 2 * lmax4; ++L) {
+        // coupled pairs of this L into sP
+        const int u0 = l_units[L], u1 = l_units[L + 1];
+        for (int u = u0 + wave; u < u1; u += kAce4Waves) {
+            const int4 h = units[u];
+            int t = __builtin_amdgcn_readfirstlane(h.x);
+            const int cnt = __builtin_amdgcn_readfirstlane(h.y), slot = __builtin_amdgcn_readfirstlane(h.z);
+            float xr = 0.f, xi = 0.f;
+            auto term = [&](int2 e) {
+                const int pk2 = __builtin_amdgcn_readfirstlane(e.x);
+                const float cf = __int_as_float(__builtin_amdgcn_readfirstlane(e.y));
+                const float2 a = sA[pk2 & 127][lane], b = sA[(pk2 >> 7) & 127][lane];
+                const float ay = (pk2 & (1 << 14)) ? -a.y : a.y;
+                const float by = (pk2 & (1 << 15)) ? -b.y : b.y;
+                xr = fmaf(cf, a.x * b.x - ay * by, xr);
+                xi = fmaf(cf, a.x * by + ay * b.x, xi);
+            };
+            int k = 0;
+            for (; k + 4 <= cnt; k += 4, t += 4) {
+                int2 e[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) e[j] = terms[t + j];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) term(e[j]);
+            }
+            for (; k < cnt; ++k) term(terms[t++]);
+            sP[slot * kTile + lane] = make_float2(xr, xi);
+        }
+        __syncthreads();
+        // this L's descriptors, a contiguous share per wave
+        const int d0 = l_descs[L], nd = l_descs[L + 1] - d0;
+        const int db = d0 + nd * wave / kAce4Waves, de = d0 + nd * (wave + 1) / kAce4Waves;
+        int cached = -1;
+        float2 pa[2 * kAce4MaxL + 1];
+        for (int d = db; d < de; ++d) {
+            const int4 q = descs[d];
+            const int sa = __builtin_amdgcn_readfirstlane(q.x), sb = __builtin_amdgcn_readfirstlane(q.y);
+            const int ok = __builtin_amdgcn_readfirstlane(q.z);
+            const float f = __int_as_float(__builtin_amdgcn_readfirstlane(q.w));
+            if (sa != cached) {
+#pragma unroll
+                for (int M = 0; M <= 2 * kAce4MaxL; ++M)
+                    if (M <= L) pa[M] = sP[(sa + M) * kTile + lane];
+                cached = sa;
+            }
+            const float2 b0 = sP[sb * kTile + lane];
+            float acc = 0.f;
+#pragma unroll
+            for (int M = 1; M <= 2 * kAce4MaxL; ++M)
+                if (M <= L) {
+                    const float2 b = sP[(sb + M) * kTile + lane];
+                    acc = fmaf(pa[M].x, b.x, fmaf(pa[M].y, b.y, acc));
+                }
+            const float v = f * fmaf(2.f, acc, pa[0].x * b0.x + pa[0].y * b0.y);
+            if (tl.valid) o[ok] = v;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_ace4(hipStream_t s, const BinState& bins, const int N[3], double rcut, int lmax4, int64_t pt_begin,
+                       int64_t n_pts, const int* l_units, const int4* units, const int2* terms, const int* l_descs,
+                       const int4* descs, int max_slots, int n4, float* out, int* err) {
+    if (n_pts <= 0 || n4 <= 0) return hipSuccess;
+    if (lmax4 < 0 || lmax4 > kAce4MaxL) return hipErrorInvalidValue;
+    const size_t lds = sizeof(float2) * (size_t)max_slots * kTile;
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [] {
+        attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ace4),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAce4LdsBudget);
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    if (lds > kAce4LdsBudget) return hipErrorInvalidValue;
+    const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, bins, N[0], N[1], N[2], rcut,
+                       lmax4, pt_begin, n_pts, l_units, units, terms, l_descs, descs, n4, out, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_ace(hipStream_t s, const BinState& bins, const int N[3], double rcut, int nmax, int lmax,

@@ -88,6 +88,16 @@ struct TjTables {
 constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
 constexpr double kWindowMargin = 0.3;     // eV around the E_F estimate kept in the stored LDOS window
 
+struct Ace4Tables {
+    bool ready = false;
+    int n4 = 0, max_slots = 0;
+    int* l_units = nullptr;
+    int4* units = nullptr;
+    int2* terms = nullptr;
+    int* l_descs = nullptr;
+    int4* descs = nullptr;
+};
+
 struct AceTables {
     bool ready = false;
     int n3 = 0, n_groups = 0;
@@ -121,6 +131,7 @@ struct mala_ctx {
     uint64_t n_allocs = 0;               // device/pinned allocations made by this context
     TjTables tj[kMaxTwojmax + 1];
     AceTables ace[kAceMaxN + 1][kAceMaxL + 1];
+    Ace4Tables ace4[kAce4MaxN + 1][kAce4MaxL + 1];
     // stage timing
     bool prof_on = false;
     struct Rec {
@@ -557,6 +568,14 @@ mala_status mala_destroy(mala_ctx* c) {
             if (a.terms) (void)hipFree(a.terms);
             if (a.outputs) (void)hipFree(a.outputs);
         }
+    for (auto& row : c->ace4)
+        for (auto& a : row) {
+            if (a.l_units) (void)hipFree(a.l_units);
+            if (a.units) (void)hipFree(a.units);
+            if (a.terms) (void)hipFree(a.terms);
+            if (a.l_descs) (void)hipFree(a.l_descs);
+            if (a.descs) (void)hipFree(a.descs);
+        }
     for (auto& t : c->tj) {
         if (t.cg) (void)hipFree(t.cg);
         if (t.cg_off) (void)hipFree(t.cg_off);
@@ -909,6 +928,71 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
     HIP_TRY(staged(c, MALA_STAGE_ACE, pt_end - pt_begin, [&] {
         return launch_ace(c->stream, bs, cg->N, rcut, nmax, lmax, pt_begin, pt_end - pt_begin, t.groups, t.n_groups,
                           t.terms, t.outputs, n_desc, out, c->err);
+    }));
+    return MALA_OK;
+}
+
+int32_t mala_ace4_count(int32_t nmax4, int32_t lmax4) {
+    if (nmax4 < 1 || nmax4 > kAce4MaxN || lmax4 < 0 || lmax4 > kAce4MaxL) return MALA_E_UNSUPPORTED;
+    std::vector<int> set;
+    return ace4_descriptor_set(nmax4, lmax4, set);
+}
+
+int32_t mala_ace4_list(int32_t nmax4, int32_t lmax4, int32_t* out, int32_t cap) {
+    if (nmax4 < 1 || nmax4 > kAce4MaxN || lmax4 < 0 || lmax4 > kAce4MaxL) return MALA_E_UNSUPPORTED;
+    std::vector<int> set;
+    const int n = ace4_descriptor_set(nmax4, lmax4, set);
+    if (!out || cap < n) return MALA_E_INVALID_ARG;
+    for (size_t i = 0; i < set.size(); ++i) out[i] = set[i];
+    return n;
+}
+
+mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
+                                  double rcut, int32_t nmax4, int32_t lmax4, int64_t pt_begin, int64_t pt_end,
+                                  float* out) {
+    if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
+    if (nmax4 < 1 || nmax4 > kAce4MaxN || lmax4 < 0 || lmax4 > kAce4MaxL)
+        return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: nmax4 must be 1..3 and lmax4 0..3");
+    mala_status st = check_geometry(positions, n_atoms, cg, rcut, 2);
+    if (st) return st;
+    const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
+    if (pt_begin < 0 || pt_end < pt_begin || pt_end > ntot) return fail(MALA_E_INVALID_ARG, "bad point range");
+    if (pt_end == pt_begin) return MALA_OK;
+    if (!out) return fail(MALA_E_INVALID_ARG, "out is NULL");
+    DeviceGuard g(c->device);
+    Ace4Tables& t = c->ace4[nmax4][lmax4];
+    if (!t.ready) {
+        std::vector<int> l_units, term_idx, l_descs;
+        std::vector<int4> units, descs;
+        std::vector<float> coef;
+        t.n4 = build_ace4_tables(nmax4, lmax4, l_units, units, term_idx, coef, l_descs, descs, t.max_slots);
+        if ((size_t)t.max_slots * kTile * sizeof(float2) > kAce4LdsBudget)
+            return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: pair vectors exceed the LDS budget");
+        std::vector<int2> terms(term_idx.size());
+        for (size_t i = 0; i < term_idx.size(); ++i) {
+            int cb;
+            memcpy(&cb, &coef[i], 4);
+            terms[i] = make_int2(term_idx[i], cb);
+        }
+        c->n_allocs += 5;
+        HIP_TRY(hipMalloc(&t.l_units, sizeof(int) * l_units.size()));
+        HIP_TRY(hipMalloc(&t.units, sizeof(int4) * (units.size() ? units.size() : 1)));
+        HIP_TRY(hipMalloc(&t.terms, sizeof(int2) * (terms.size() ? terms.size() : 1)));
+        HIP_TRY(hipMalloc(&t.l_descs, sizeof(int) * l_descs.size()));
+        HIP_TRY(hipMalloc(&t.descs, sizeof(int4) * (descs.size() ? descs.size() : 1)));
+        HIP_TRY(hipMemcpy(t.l_units, l_units.data(), sizeof(int) * l_units.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.units, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.terms, terms.data(), sizeof(int2) * terms.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.l_descs, l_descs.data(), sizeof(int) * l_descs.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.descs, descs.data(), sizeof(int4) * descs.size(), hipMemcpyHostToDevice));
+        t.ready = true;
+    }
+    if ((st = upload_positions(c, positions, n_atoms))) return st;
+    BinState bs{};
+    if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
+    HIP_TRY(staged(c, MALA_STAGE_ACE4, pt_end - pt_begin, [&] {
+        return launch_ace4(c->stream, bs, cg->N, rcut, lmax4, pt_begin, pt_end - pt_begin, t.l_units, t.units,
+                           t.terms, t.l_descs, t.descs, t.max_slots, t.n4, out, c->err);
     }));
     return MALA_OK;
 }

@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <vector>
 
 #include "ace.h"
@@ -279,6 +280,182 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<i
                 for (int o : outs) outputs.push_back(o);
             }
     return nd;
+}
+
+// Rank-4 grid ACE (Eq. ace_grid with four factors, one intermediate
+// coupling L): for keys p = n (lmax4+1) + l,
+//   B(p1 p2 p3 p4; L) = sum over m of <l1 m1 l2 m2 | L M> <l3 m3 l4 m4 | L -M>
+//                       (-1)^(L-M)/sqrt(2L+1) A_p1 A_p2 A_p3 A_p4.
+// The set: multisets p1 <= p2 <= p3 <= p4 with an even l-sum; for each, the
+// couplings L (in increasing order) whose coefficients, summed over the
+// permutations that exchange equal keys, are linearly independent of those
+// kept before (Gram-Schmidt on the coefficient tensors).
+// Evaluation: with the coupled pairs P_a(M) = sum_m1 <l1 m1 l2 m2|L M>
+// A_p1,m1 A_p2,m2 (a = (p1 p2), m2 = M - m1) and A_{l,-m} = (-1)^m conj A_{l,m},
+// P_a(-M) = (-1)^(l1+l2-L+M) conj P_a(M); for an even l-sum the descriptor is
+//   B = (-1)^(l3+l4-L) (-1)^L / sqrt(2L+1)
+//       [Re P_a(0) conj P_b(0) + 2 sum_{M>=1} Re P_a(M) conj P_b(M)],
+// so only M >= 0 of every pair is formed.  Tables per L: pair units (first
+// term, term count, LDS slot of P_a(M)), terms packed as in rank 3, and
+// descriptors (slot of P_a(0), slot of P_b(0), output position, factor).
+namespace {
+
+struct Ace4Cg {
+    std::vector<Coupling> cache = std::vector<Coupling>(25 * 25);
+    std::vector<bool> have = std::vector<bool>(25 * 25, false);
+    // <l1 m1 l2 m2 | L M> from the coupled states of couple()
+    double operator()(int l1, int m1, int l2, int m2, int L, int M) {
+        if (m1 + m2 != M || abs(m1) > l1 || abs(m2) > l2 || abs(M) > L || L < abs(l1 - l2) || L > l1 + l2)
+            return 0.0;
+        const int key = 2 * l1 * 25 + 2 * l2;
+        if (!have[key]) {
+            cache[key] = couple(2 * l1, 2 * l2);
+            have[key] = true;
+        }
+        return cache[key].vec[l1 + l2 - L][L + M][pidx(2 * l2, l1 + m1, l2 + m2)];
+    }
+};
+
+}  // namespace
+
+int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc) {
+    desc.clear();
+    Ace4Cg cg;
+    const int nl = lmax4 + 1, np = nmax4 * nl;
+    for (int p1 = 0; p1 < np; ++p1)
+        for (int p2 = p1; p2 < np; ++p2)
+            for (int p3 = p2; p3 < np; ++p3)
+                for (int p4 = p3; p4 < np; ++p4) {
+                    const int ps[4] = {p1, p2, p3, p4};
+                    const int l[4] = {p1 % nl, p2 % nl, p3 % nl, p4 % nl};
+                    if ((l[0] + l[1] + l[2] + l[3]) % 2) continue;
+                    const int d1 = 2 * l[1] + 1, d2 = 2 * l[2] + 1, d3 = 2 * l[3] + 1;
+                    const int dim = (2 * l[0] + 1) * d1 * d2 * d3;
+                    // permutations of the four slots that map every key onto an equal key
+                    std::vector<std::array<int, 4>> perms;
+                    std::array<int, 4> q = {0, 1, 2, 3};
+                    do {
+                        bool ok = true;
+                        for (int i = 0; i < 4; ++i) ok = ok && ps[q[i]] == ps[i];
+                        if (ok) perms.push_back(q);
+                    } while (std::next_permutation(q.begin(), q.end()));
+                    std::vector<std::vector<double>> kept;
+                    const int Llo = std::max(abs(l[0] - l[1]), abs(l[2] - l[3]));
+                    const int Lhi = std::min(l[0] + l[1], l[2] + l[3]);
+                    for (int L = Llo; L <= Lhi; ++L) {
+                        std::vector<double> T(dim, 0.0);
+                        auto at = [&](const int (&m)[4]) {
+                            return (((m[0] + l[0]) * d1 + m[1] + l[1]) * d2 + m[2] + l[2]) * d3 + m[3] + l[3];
+                        };
+                        for (int m1 = -l[0]; m1 <= l[0]; ++m1)
+                            for (int m2 = -l[1]; m2 <= l[1]; ++m2)
+                                for (int m3 = -l[2]; m3 <= l[2]; ++m3) {
+                                    const int m4 = -m1 - m2 - m3, M = m1 + m2;
+                                    if (abs(m4) > l[3] || abs(M) > L) continue;
+                                    const double c = cg(l[0], m1, l[1], m2, L, M) * cg(l[2], m3, l[3], m4, L, -M) *
+                                                     (((L - M) & 1) ? -1.0 : 1.0) / sqrt(2.0 * L + 1.0);
+                                    if (c == 0.0) continue;
+                                    const int m[4] = {m1, m2, m3, m4};
+                                    // symmetrised: the coefficient lands on every slot order
+                                    // that exchanges equal keys
+                                    for (const auto& pr : perms) {
+                                        int mp[4];
+                                        for (int i = 0; i < 4; ++i) mp[pr[i]] = m[i];
+                                        T[at(mp)] += c / (double)perms.size();
+                                    }
+                                }
+                        double n0 = 0.0;
+                        for (double x : T) n0 += x * x;
+                        for (const auto& k : kept) {            // Gram-Schmidt against the kept ones
+                            double dot = 0.0;
+                            for (int i = 0; i < dim; ++i) dot += k[i] * T[i];
+                            for (int i = 0; i < dim; ++i) T[i] -= dot * k[i];
+                        }
+                        double n1 = 0.0;
+                        for (double x : T) n1 += x * x;
+                        if (n0 > 0.0 && n1 > 1e-18 * std::max(1.0, n0)) {
+                            const double inv = 1.0 / sqrt(n1);
+                            for (double& x : T) x *= inv;
+                            kept.push_back(T);
+                            for (int i = 0; i < 4; ++i) desc.push_back(ps[i]);
+                            desc.push_back(L);
+                        }
+                    }
+                }
+    return (int)(desc.size() / 5);
+}
+
+int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
+                      std::vector<int>& term_idx, std::vector<float>& term_coef, std::vector<int>& l_descs,
+                      std::vector<int4>& descs, int& max_slots) {
+    std::vector<int> set;
+    const int n4 = ace4_descriptor_set(nmax4, lmax4, set);
+    Ace4Cg cg;
+    const int nl = lmax4 + 1;
+    l_units.assign(1, 0);
+    l_descs.assign(1, 0);
+    units.clear();
+    term_idx.clear();
+    term_coef.clear();
+    descs.clear();
+    max_slots = 0;
+    for (int L = 0; L <= 2 * lmax4; ++L) {
+        // the pairs this L needs, in first-use order, each with L+1 slots
+        std::vector<std::pair<int, int>> pairs;
+        auto slot_of = [&](int pa, int pb) {
+            for (size_t i = 0; i < pairs.size(); ++i)
+                if (pairs[i].first == pa && pairs[i].second == pb) return (int)i * (L + 1);
+            pairs.push_back({pa, pb});
+            return (int)(pairs.size() - 1) * (L + 1);
+        };
+        std::vector<std::array<int, 4>> dl;
+        for (int k = 0; k < n4; ++k) {
+            const int* d = &set[5 * k];
+            if (d[4] != L) continue;
+            dl.push_back({slot_of(d[0], d[1]), slot_of(d[2], d[3]), k, (d[2] % nl + d[3] % nl)});
+        }
+        // descriptors sharing their first pair next to each other
+        std::stable_sort(dl.begin(), dl.end(), [](const std::array<int, 4>& x, const std::array<int, 4>& y) {
+            return x[0] < y[0];
+        });
+        for (const auto& x : dl) {
+            const double f = ((x[3] & 1) ? -1.0 : 1.0) / sqrt(2.0 * L + 1.0);     // (-1)^(l3+l4-L) (-1)^L
+            float ff = (float)f;
+            int fb;
+            memcpy(&fb, &ff, 4);
+            descs.push_back(make_int4(x[0], x[1], x[2], fb));
+        }
+        for (size_t i = 0; i < pairs.size(); ++i) {
+            const int pa = pairs[i].first, pb = pairs[i].second;
+            const int n1 = pa / nl, l1 = pa % nl, n2 = pb / nl, l2 = pb % nl;
+            for (int M = 0; M <= L; ++M) {
+                const int t0 = (int)term_idx.size();
+                for (int m1 = -l1; m1 <= l1; ++m1) {
+                    const int m2 = M - m1;
+                    if (abs(m2) > l2) continue;
+                    double coef = cg(l1, m1, l2, m2, L, M);
+                    if (coef == 0.0) continue;
+                    const int m[2] = {m1, m2}, n[2] = {n1, n2}, ll[2] = {l1, l2};
+                    int packed = 0;
+                    for (int j = 0; j < 2; ++j) {
+                        const int am = abs(m[j]);
+                        packed |= (n[j] * 15 + ll[j] * (ll[j] + 1) / 2 + am) << (7 * j);
+                        if (m[j] < 0) {
+                            packed |= 1 << (14 + j);
+                            if (am & 1) coef = -coef;
+                        }
+                    }
+                    term_idx.push_back(packed);
+                    term_coef.push_back((float)coef);
+                }
+                units.push_back(make_int4(t0, (int)term_idx.size() - t0, (int)i * (L + 1) + M, 0));
+            }
+        }
+        max_slots = std::max(max_slots, (int)pairs.size() * (L + 1));
+        l_units.push_back((int)units.size());
+        l_descs.push_back((int)descs.size());
+    }
+    return n4;
 }
 
 // Longest-processing-time assignment of triples to the waves of a block.

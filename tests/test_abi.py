@@ -69,3 +69,21 @@ def test_result_record_layout():
     assert mala.RESULT_BYTES == 64
     assert ctypes.sizeof(mala.Result) == 64
     assert mala.Result.entropy.offset == 48 and mala.Result.e_entropy.offset == 56
+
+
+@pytest.mark.parametrize("nmax4,lmax4", [(1, 1), (1, 2), (2, 2), (3, 2), (2, 3), (3, 3)])
+def test_ace4_set_matches_oracle(lib, nmax4, lmax4):
+    """The library chooses its non-redundant rank-4 set by Gram-Schmidt on
+    the symmetrised coupling coefficients of its own Clebsch-Gordan table;
+    the oracle by the rank of the same coefficients from the Racah formula.
+    Both must give the same (p1, p2, p3, p4, L) list in the same order."""
+    import oracle
+    n = lib.mala_ace4_count(nmax4, lmax4)
+    buf = (ctypes.c_int32 * (5 * n))()
+    assert lib.mala_ace4_list(nmax4, lmax4, buf, n) == n
+    got = [tuple(buf[5 * k:5 * k + 5]) for k in range(n)]
+    assert got == [tuple(int(x) for x in d) for d in oracle.ace4_set(nmax4, lmax4)]
+
+
+def test_ace4_unsupported_sizes(lib):
+    assert lib.mala_ace4_count(4, 2) < 0 and lib.mala_ace4_count(2, 4) < 0 and lib.mala_ace4_count(0, 1) < 0

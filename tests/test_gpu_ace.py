@@ -1,7 +1,7 @@
 """GPU parity of the grid ACE descriptors (Sec. 3.2.3) through the C ABI
-against the FP64 oracle: whole small grid, a range of the 256-atom cell,
-several (nmax, lmax), sampled rows of the full 729,000-point grid, and the
-empty / unsupported cases."""
+against the FP64 oracle, ranks 1-3 and rank 4: whole small grid, a range of
+the 256-atom cell, several basis sizes, sampled rows of the full
+729,000-point grid, and the empty / unsupported cases."""
 import sys
 
 import numpy as np
@@ -89,3 +89,61 @@ def test_ace_empty_and_unsupported(env):
     e = torch.empty((4, 602), dtype=torch.float32, device="cuda")
     with pytest.raises(mala.MalaError):
         ctx.mala_ace_descriptors(s.positions, s.L, s.N, s.rcut, 4, 5, 0, 4, out=e)
+
+
+# ---------------------------------------------------------------- rank 4
+
+def compare4(env, s, rcut, nmax4, lmax4, pt_begin, pt_end):
+    mala, ctx, torch = env
+    log("ace4", s.name, "nmax4", nmax4, "lmax4", lmax4, "points", pt_begin, pt_end)
+    g = ctx.mala_ace4_descriptors(s.positions, s.L, s.N, rcut, nmax4, lmax4, pt_begin, pt_end).cpu().double().numpy()
+    ctx.check_device_errors()
+    ref = oracle.ace4(s, rcut, nmax4, lmax4, np.arange(pt_begin, pt_end, dtype=np.int64), nthreads=16)
+    assert g.shape == ref.shape
+    err = rel_rows(g, ref)
+    log("  rel err %.3e" % err)
+    assert np.all(np.isfinite(g))
+    assert err <= TOL
+
+
+def test_ace4_small_cell_whole_grid(env):
+    s = mala_synth.small()
+    compare4(env, s, s.rcut, 3, 3, 0, s.n_points)
+
+
+def test_ace4_paper_cell_range(env):
+    s = mala_synth.paper_liquid()
+    compare4(env, s, s.rcut, 3, 3, 310000, 310000 + 1024 + 77)
+
+
+@pytest.mark.parametrize("nmax4,lmax4", [(1, 0), (1, 2), (2, 2), (3, 2), (2, 3)])
+def test_ace4_parameters(env, nmax4, lmax4):
+    s = mala_synth.small()
+    compare4(env, s, s.rcut, nmax4, lmax4, 2000, 2000 + 257)
+
+
+def test_ace4_full_grid_sampled(env):
+    """729,000 points in one launch; 192 seeded rows against the oracle."""
+    mala, ctx, torch = env
+    s = mala_synth.paper_solid()
+    g = ctx.mala_ace4_descriptors(s.positions, s.L, s.N, s.rcut, 3, 3)
+    ctx.check_device_errors()
+    rows = mala_synth.sample_points(s.n_points, 192, 43)
+    gs = g[torch.as_tensor(rows, device="cuda")].cpu().double().numpy()
+    err = rel_rows(gs, oracle.ace4(s, s.rcut, 3, 3, rows, nthreads=16))
+    log("ace4 full grid sampled rel err %.3e" % err)
+    assert err <= TOL
+    assert bool(torch.isfinite(g).all())
+
+
+def test_ace4_empty_and_unsupported(env):
+    mala, ctx, torch = env
+    s = mala_synth.small()
+    n = mala.ace4_count(3, 3)
+    out = ctx.mala_ace4_descriptors(s.positions, s.L, s.N, s.rcut, 3, 3, 7, 7)
+    assert out.shape == (0, n)
+    with pytest.raises(mala.MalaError):
+        mala.ace4_count(4, 3)
+    e = torch.empty((4, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(mala.MalaError):
+        ctx.mala_ace4_descriptors(s.positions, s.L, s.N, s.rcut, 3, 4, 0, 4, out=e)
