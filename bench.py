@@ -137,8 +137,7 @@ def cpu_baseline(snap, net, n_sample):
     return rec, pts, B, ld
 
 
-TRAFFIC_FILES = {"al256_solid_298K_90c_tj10": "traffic_k_zb_al256_solid_90c_tj10.txt",
-                 "al16384_slab111_fault_298K_tj10": "traffic_k_zb_al16384_slab_tj10.txt"}
+TRAFFIC_FILES = {"al16384_slab111_fault_298K_tj10": "traffic_k_zb_al16384_slab_tj10.txt"}
 
 
 def kernel_source_hash():
@@ -264,16 +263,17 @@ def stats_summary(prof_dir, bench_json, out_name, command):
         raise SystemExit("no kernel_stats.csv under %s" % prof_dir)
     rows = list(csv.DictReader(open(f[0])))
     b = None
-    for line in open(bench_json).read().split("\n"):    # the profiler may log after the bench line
+    for line in (open(bench_json).read().split("\n") if bench_json != "-" else []):  # the profiler may log after it
         if line.startswith("{"):
             try:
                 b = json.loads(line)
             except ValueError:
                 pass
-    if b is None:
+    if b is None and bench_json != "-":
         raise SystemExit("no bench JSON line in %s" % bench_json)
-    cfg, rf = b["config"], b["roofline"]
-    lines = ["# rocprofv3 kernel stats: %s, %s network" % (cfg["workload"], cfg["network_precision"]), "",
+    title = ("%s, %s network" % (b["config"]["workload"], b["config"]["network_precision"]) if b else
+             "bench.py --probe-kernels (each kernel family once on the 729,000-point 256-atom solid)")
+    lines = ["# rocprofv3 kernel stats: " + title, "",
              "Command (repository root = $REPO, output directory $OUT):", "", "```",
              "cd /tmp && export TMPDIR=/tmp && " + command, "```", "",
              "| kernel | calls | avg ms | min ms | max ms | total ms | share |", "|---|---|---|---|---|---|---|"]
@@ -286,8 +286,14 @@ def stats_summary(prof_dir, bench_json, out_name, command):
         if name.startswith("mala::k_zb<"):
             zb = float(r["AverageNs"]) / 1e6
     lines += ["", "The metric's step runs the cell list, `k_ui`, `k_zb`, `k_mlp` and `k_fermi` "
-              "(and `k_density_window`); `k_gauss`, `k_mlp_vjp`, `k_yi`, `k_dedr` and `k_ace` come from the "
-              "lines outside the metric (Gaussian descriptors, both VJPs, grid ACE) when they are run."]
+              "(and `k_density_window`); `k_gauss`, `k_mlp_vjp`, `k_yi`, `k_dedr`, `k_ace` and `k_ace4` come "
+              "from the lines outside the metric (Gaussian descriptors, both VJPs, grid ACE) when they are run."]
+    if b is None:
+        with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
+            fo.write("\n".join(lines) + "\n")
+        print("wrote profiles/%s" % out_name)
+        return
+    rf = b["roofline"]
     lines += ["", "Dominant kernel `k_zb`: rocprof average %.4f ms per launch; bench.py (same build, "
               "HIP events on the library stream) %.4f ms per launch over %.0f points: achieved %.1f %s = "
               "%.3f of the %.1f %s peak (%.1f kflop/point)."
