@@ -597,12 +597,21 @@ def ace_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax=4, lmax=4):
         ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax, lmax, out=out)
     ms = ctx.profile_read()["ace"][0] / reps
     ctx.profile_enable(False)
+    del out
+    dm = ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax, lmax, descriptor_major=True)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_ace_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax, lmax, out=dm, descriptor_major=True)
+    ms_dm = ctx.profile_read()["ace"][0] / reps
+    ctx.profile_enable(False)
+    out = dm
     ctx.check_device_errors()
     fl, terms = ace_flops(nmax, lmax, mean_nbr)
     tf = fl * snap.n_points / (ms * 1e-3) / 1e12
     del out
     return {"nmax": nmax, "lmax": lmax, "descriptors": mala.ace_count(nmax, lmax), "rank3_terms": terms,
-            "ms_per_grid": ms, "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl,
+            "ms_per_grid": ms, "ms_per_grid_descriptor_major": ms_dm,
+            "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl,
             "tflops": tf, "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS}
 
 
@@ -635,12 +644,21 @@ def ace4_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax4=3, lmax4=3):
         ctx.mala_ace4_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax4, lmax4, out=out)
     ms = ctx.profile_read()["ace4"][0] / reps
     ctx.profile_enable(False)
+    del out
+    out = ctx.mala_ace4_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax4, lmax4, descriptor_major=True)
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.mala_ace4_descriptors(snap.positions, snap.L, snap.N, snap.rcut, nmax4, lmax4, out=out,
+                                  descriptor_major=True)
+    ms_dm = ctx.profile_read()["ace4"][0] / reps
+    ctx.profile_enable(False)
     ctx.check_device_errors()
     fl, terms = ace4_flops(mala, nmax4, lmax4, mean_nbr)
     tf = fl * snap.n_points / (ms * 1e-3) / 1e12
     n4 = mala.ace4_count(nmax4, lmax4)
     del out
     return {"nmax4": nmax4, "lmax4": lmax4, "descriptors": n4, "pair_terms": terms, "ms_per_grid": ms,
+            "ms_per_grid_descriptor_major": ms_dm,
             "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl, "tflops": tf,
             "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS,
             "write_GB_s": 4.0 * n4 * snap.n_points / (ms * 1e-3) / 1e9}

@@ -171,12 +171,17 @@ mala_status mala_descriptors_vjp(mala_ctx* ctx, const double* positions, int32_t
  *   p = n (lmax+1) + l, p1 <= p2 <= p3, with l1+l2+l3 even and triangle.
  *  nmax in 1..4, lmax in 0..4 (MALA_E_UNSUPPORTED otherwise); positions,
  *  cg, rcut as for mala_descriptors;
- *  out: device float32 [pt_end - pt_begin][mala_ace_count(nmax, lmax)].
+ *  layout MALA_LAYOUT_POINT_MAJOR: out is device float32
+ *  [pt_end - pt_begin][mala_ace_count(nmax, lmax)]; MALA_LAYOUT_DESCRIPTOR_MAJOR:
+ *  [mala_ace_count(nmax, lmax)][pt_end - pt_begin] (one plane per descriptor,
+ *  written with coalesced stores: faster when the consumer can take planes).
  * Empty ranges are a no-op.                                                  */
+#define MALA_LAYOUT_POINT_MAJOR 0
+#define MALA_LAYOUT_DESCRIPTOR_MAJOR 1
 int32_t mala_ace_count(int32_t nmax, int32_t lmax);   /* descriptors per point, or < 0 */
 mala_status mala_ace_descriptors(mala_ctx* ctx, const double* positions, int32_t n_atoms,
                                  const mala_cell_grid* cg, double rcut, int32_t nmax, int32_t lmax,
-                                 int64_t pt_begin, int64_t pt_end, float* out);
+                                 int64_t pt_begin, int64_t pt_end, int32_t layout, float* out);
 
 /* Grid ACE descriptors of rank 4 (Sec. 3.2.3, Eq. ace_grid with four
  * factors and one intermediate coupling L, the generalized Clebsch-Gordan
@@ -190,8 +195,9 @@ mala_status mala_ace_descriptors(mala_ctx* ctx, const double* positions, int32_t
  * permutations that exchange equal keys) are linearly independent of those
  * kept before: the non-redundant rank-4 descriptors the paper requires.
  *  nmax4 in 1..3, lmax4 in 0..3 (MALA_E_UNSUPPORTED otherwise);
- *  out: device float32 [pt_end - pt_begin][mala_ace4_count(nmax4, lmax4)],
- *  in the order of mala_ace4_list.
+ *  out: device float32 [pt_end - pt_begin][mala_ace4_count(nmax4, lmax4)]
+ *  (MALA_LAYOUT_POINT_MAJOR) or its transpose (MALA_LAYOUT_DESCRIPTOR_MAJOR),
+ *  descriptors in the order of mala_ace4_list.
  * mala_ace4_list writes (p1, p2, p3, p4, L) per descriptor into out[5 n]
  * (host int32, cap entries of five) and returns the count, or < 0 if the
  * sizes are unsupported or cap is too small.  Empty ranges are a no-op.    */
@@ -199,7 +205,7 @@ int32_t mala_ace4_count(int32_t nmax4, int32_t lmax4);
 int32_t mala_ace4_list(int32_t nmax4, int32_t lmax4, int32_t* out, int32_t cap);
 mala_status mala_ace4_descriptors(mala_ctx* ctx, const double* positions, int32_t n_atoms,
                                   const mala_cell_grid* cg, double rcut, int32_t nmax4, int32_t lmax4,
-                                  int64_t pt_begin, int64_t pt_end, float* out);
+                                  int64_t pt_begin, int64_t pt_end, int32_t layout, float* out);
 
 /* Gaussian descriptors of grid points [pt_begin, pt_end): the Gaussian
  * representation of the ionic positions behind the structure factor

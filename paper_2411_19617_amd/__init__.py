@@ -84,11 +84,11 @@ def lib():
             ("mala_weights_free", [p]),
             ("mala_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p]),
             ("mala_descriptors_vjp", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i64, i64, p, p]),
-            ("mala_ace_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, p]),
+            ("mala_ace_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, i32, p]),
             ("mala_ace_count", [i32, i32]),
             ("mala_ace4_count", [i32, i32]),
             ("mala_ace4_list", [i32, i32, p, i32]),
-            ("mala_ace4_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, p]),
+            ("mala_ace4_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, i32, i32, i64, i64, i32, p]),
             ("mala_gaussian_descriptors", [p, p, i32, ctypes.POINTER(CellGrid), d, d, i64, i64, p]),
             ("mala_ldos_infer", [p, p, p, i64, p]),
             ("mala_ldos_vjp", [p, p, p, p, i64, p]),
@@ -299,34 +299,41 @@ class Context:
                                           int(pt_begin), int(pt_end), _ptr(gB), _ptr(out)))
         return out
 
-    def mala_ace4_descriptors(self, positions, L, N, rcut, nmax4=3, lmax4=3, pt_begin=0, pt_end=None, out=None):
-        """Rank-4 grid ACE descriptors [pt_end - pt_begin][ace4_count(nmax4, lmax4)] (device float32)."""
+    def mala_ace4_descriptors(self, positions, L, N, rcut, nmax4=3, lmax4=3, pt_begin=0, pt_end=None, out=None,
+                              descriptor_major=False):
+        """Rank-4 grid ACE descriptors [pt_end - pt_begin][ace4_count(nmax4, lmax4)] (device float32),
+        or [ace4_count][pt_end - pt_begin] with descriptor_major."""
         import torch
         self._sync_stream()
         pos, pp, n_at = _positions(positions)
         ntot = int(N[0]) * int(N[1]) * int(N[2])
         pt_end = ntot if pt_end is None else int(pt_end)
         nd = ace4_count(nmax4, lmax4)
+        shape = (nd, max(pt_end - pt_begin, 0)) if descriptor_major else (max(pt_end - pt_begin, 0), nd)
         if out is None:
-            out = torch.empty((max(pt_end - pt_begin, 0), nd), dtype=torch.float32, device=self.torch_device)
+            out = torch.empty(shape, dtype=torch.float32, device=self.torch_device)
         cg = _cell_grid(L, N)
         _check(lib().mala_ace4_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(nmax4),
-                                           int(lmax4), int(pt_begin), int(pt_end), _ptr(out)))
+                                           int(lmax4), int(pt_begin), int(pt_end), 1 if descriptor_major else 0,
+                                           _ptr(out)))
         return out
 
-    def mala_ace_descriptors(self, positions, L, N, rcut, nmax=4, lmax=4, pt_begin=0, pt_end=None, out=None):
-        """Grid ACE descriptors [pt_end - pt_begin][ace_count(nmax, lmax)] (device float32)."""
+    def mala_ace_descriptors(self, positions, L, N, rcut, nmax=4, lmax=4, pt_begin=0, pt_end=None, out=None,
+                             descriptor_major=False):
+        """Grid ACE descriptors [pt_end - pt_begin][ace_count(nmax, lmax)] (device float32),
+        or [ace_count][pt_end - pt_begin] with descriptor_major."""
         import torch
         self._sync_stream()
         pos, pp, n_at = _positions(positions)
         ntot = int(N[0]) * int(N[1]) * int(N[2])
         pt_end = ntot if pt_end is None else int(pt_end)
         nd = ace_count(nmax, lmax)
+        shape = (nd, max(pt_end - pt_begin, 0)) if descriptor_major else (max(pt_end - pt_begin, 0), nd)
         if out is None:
-            out = torch.empty((max(pt_end - pt_begin, 0), nd), dtype=torch.float32, device=self.torch_device)
+            out = torch.empty(shape, dtype=torch.float32, device=self.torch_device)
         cg = _cell_grid(L, N)
         _check(lib().mala_ace_descriptors(self.handle, pp, n_at, ctypes.byref(cg), float(rcut), int(nmax), int(lmax),
-                                          int(pt_begin), int(pt_end), _ptr(out)))
+                                          int(pt_begin), int(pt_end), 1 if descriptor_major else 0, _ptr(out)))
         return out
 
     def mala_gaussian_descriptors(self, positions, L, N, sigma, cutoff, pt_begin=0, pt_end=None, out=None):

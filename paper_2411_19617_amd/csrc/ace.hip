@@ -1,24 +1,28 @@
 // Grid-centred atomic cluster expansion descriptors (Sec. 3.2.3, Eqs.
 // unweighted_ionicdensity, gridatom_basis, grid_base, product_grid_basis,
-// ace_grid), one chemical element, ranks 1-3:
+// ace_grid), one chemical element:
 //   A_nlm = sum over atom images within rcut of R_n(r) Y_l^m(d/r), plus the
 //   grid point's own delta on l = 0 (R_n(0) Y_0^0 = (-1)^n / sqrt(4 pi));
 //   R_n(r) = T_n(2 r / rcut - 1) fc(r) (Chebyshev times the cosine cutoff);
 //   rank 1: A_n00; rank 2: sum_m (-1)^m A_{n1 l m} A_{n2 l -m};
-//   rank 3: sum (l1 l2 l3; m1 m2 m3) A A A over multisets of three (n, l).
-// Four waves per 64-point tile (lane = point): the tile's candidate atom
-// images are gathered into LDS (shared with the other neighbour kernels);
-// wave w visits candidates w, w+4, ... and accumulates its part of the
-// lane's A_nlm (m >= 0; A_{l,-m} = (-1)^m conj(A_{l,m})) in registers: T_n by
-// the three-term recurrence, Y_l^m = N_lm Q_l^m(z/r) ((x + i y)/r)^m with
-// Q_l^m = (-1)^m d^m P_l / dt^m by the associated Legendre recurrence in l.
-// The parts are added into LDS (float atomics, so the last bits depend on
-// the order), then wave 0 forms ranks 1 and 2 and every wave takes every
-// fourth rank-3 group (p1, p2, l3): the partial sums
+//   rank 3: sum (l1 l2 l3; m1 m2 m3) A A A over multisets of three (n, l);
+//   rank 4: the generalized Clebsch-Gordan contraction with one intermediate
+//   coupling L (k_ace4 below).
+// Two kernels per chunk of points.  k_ace_proj: per 64-point tile (lane =
+// point) the candidate atom images are gathered into LDS (shared with the
+// other neighbour kernels), wave 0 builds per-point neighbour lists, and wave
+// n forms the rows A_{n l m} (m >= 0; A_{l,-m} = (-1)^m conj A_{l,m}) over its
+// lane's list: T_n by the three-term recurrence, Y_l^m = N_lm Q_l^m(z/r)
+// ((x + i y)/r)^m with Q_l^m = (-1)^m d^m P_l / dt^m by the associated
+// Legendre recurrence in l; the tile's A goes to HBM (480 B per point,
+// coalesced).  k_ace (ranks 1-3) and k_ace4 (rank 4) load a tile's A into
+// LDS and contract it with few registers, so many waves share a CU.  Rank 3
+// is grouped by (p1, p2, l3): the partial sums
 // P(m3) = sum_m1 (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} from a table of
 // packed terms (storage indices, conjugation flags, 3j symbol with signs,
 // sorted by m3) read with wave-uniform loads, then B = sum_m3 P(m3) A_{n3 l3 m3}
-// for every n3 of the group.  Bound: LDS reads and the table loads.
+// for every n3 of the group.  Outputs are written point-major or
+// descriptor-major (one plane per descriptor, coalesced stores).
 #include <mutex>
 
 #include "ace.h"
@@ -29,7 +33,8 @@ namespace mala {
 constexpr int kAceN = kAceMaxN;          // radial functions held per point
 constexpr int kAceL = kAceMaxL;          // largest l held
 constexpr int kAceLm = 15;               // (l, m >= 0) entries per n: l(l+1)/2 + m
-constexpr int kAceWaves = 4;
+constexpr int kAceWaves = 4;            // projection: one wave per radial index
+constexpr int kAce3Waves = 8;           // rank 1-3 contraction
 
 __host__ __device__ constexpr double ace_fact(int n) {
     double f = 1.0;
@@ -82,42 +87,38 @@ __device__ __forceinline__ AceTile ace_tile(const BinState& bins, int Nx, int Ny
     return t;
 }
 
-// Adds the lane's A_nlm (n < 4, l <= 4, m >= 0) into sA (zeroed by the
-// caller): wave w of nw visits candidates w, w + nw, ...; wave 0 adds the
-// grid point's own delta.
-__device__ __forceinline__ void ace_project(const float4* cand, const AceTile& tl, double rcut, int wave, int nw,
-                                            int lane, float2 (*sA)[kTile]) {
-    const int ncand = tl.ncand;
+// The lane's A_{n l m} for one radial index n (all l <= 4, m >= 0) over the
+// lane's neighbour list (candidate indices within rcut, in candidate order),
+// plus the grid point's own delta on l = 0; written to dst[lm][lane].
+__device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned short (*nbr)[kTile], int my_n,
+                                              int n_iter, const AceTile& tl, double rcut, int n, int lane,
+                                              float2* __restrict__ dst) {
     const float px = tl.px, py = tl.py, pz = tl.pz;
-    const float rcf = (float)rcut, rc2 = rcf * rcf;
+    const float rcf = (float)rcut;
     constexpr float kpi = 3.14159265358979323846f;
-    float ar[kAceN][kAceLm], ai[kAceN][kAceLm];
-#pragma unroll
-    for (int n = 0; n < kAceN; ++n)
-#pragma unroll
-        for (int e = 0; e < kAceLm; ++e) ar[n][e] = ai[n][e] = 0.f;
     constexpr float y00 = 0.28209479177387814f;            // 1 / sqrt(4 pi)
-    if (wave == 0) {
+    float ar[kAceLm], ai[kAceLm];
 #pragma unroll
-        for (int n = 0; n < kAceN; ++n) ar[n][0] = (n & 1) ? -y00 : y00;  // the grid point's own delta
-    }
-    for (int c = wave; c < ncand; c += nw) {
-        const float4 q = cand[c];
+    for (int e = 0; e < kAceLm; ++e) ar[e] = ai[e] = 0.f;
+    ar[0] = (n & 1) ? -y00 : y00;                          // the grid point's own delta: T_n(-1) Y_0^0
+    for (int s = 0; s < n_iter; ++s) {
+        if (s >= my_n) continue;
+        const float4 q = cand[nbr[s][lane]];
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (!(r2 < rc2)) continue;
         const float r = sqrtf(r2);
-        // radial: T_n(x) fc(r)
+        // radial: T_n(x) fc(r) by the three-term recurrence
         const float x = 2.f * r / rcf - 1.f;
         const float fc = 0.5f * (cosf(kpi * r / rcf) + 1.f);
-        float R[kAceN];
-        R[0] = fc;
-        R[1] = x * fc;
-#pragma unroll
-        for (int n = 2; n < kAceN; ++n) R[n] = 2.f * x * R[n - 1] - R[n - 2];
+        float t0 = 1.f, t1 = x;
+        for (int k = 2; k <= n; ++k) {
+            const float t2 = 2.f * x * t1 - t0;
+            t0 = t1;
+            t1 = t2;
+        }
+        const float R = (n == 0 ? 1.f : t1) * fc;
         if (r2 == 0.f) {                                   // an atom on the point: l = 0 only
-#pragma unroll
-            for (int n = 0; n < kAceN; ++n) ar[n][0] += R[n] * y00;
+            ar[0] += R * y00;
             continue;
         }
         const float inv = 1.f / r;
@@ -151,50 +152,78 @@ __device__ __forceinline__ void ace_project(const float4* cand, const AceTile& t
                 constexpr int m = decltype(mc)::value;
                 constexpr int e = l * (l + 1) / 2 + m;
                 constexpr float nrm = ace_norm(l, m);
-                const float yr = nrm * Q[e] * er[m], yi = nrm * Q[e] * ei[m];
-#pragma unroll
-                for (int n = 0; n < kAceN; ++n) {
-                    ar[n][e] = fmaf(R[n], yr, ar[n][e]);
-                    ai[n][e] = fmaf(R[n], yi, ai[n][e]);
-                }
+                const float y = R * nrm * Q[e];
+                ar[e] = fmaf(y, er[m], ar[e]);
+                ai[e] = fmaf(y, ei[m], ai[e]);
             });
         });
     }
 #pragma unroll
-    for (int n = 0; n < kAceN; ++n)
-#pragma unroll
-        for (int e = 0; e < kAceLm; ++e) {
-            atomicAdd(&sA[n * kAceLm + e][lane].x, ar[n][e]);
-            atomicAdd(&sA[n * kAceLm + e][lane].y, ai[n][e]);
-        }
+    for (int e = 0; e < kAceLm; ++e) dst[e * kTile + lane] = make_float2(ar[e], ai[e]);
 }
 
-__global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, int Ny, int Nz, double rcut, int nmax, int lmax,
-                                            int64_t pt_begin, int64_t n_pts, const int* __restrict__ groups,
-                                            int n_groups, const int2* __restrict__ terms,
-                                            const int* __restrict__ outputs, int n_desc, float* __restrict__ out,
-                                            int* __restrict__ err) {
+__global__ __launch_bounds__(64 * kAceWaves) void k_ace_proj(BinState bins, int Nx, int Ny, int Nz, double rcut,
+                                                             int64_t pt_begin, int64_t n_pts,
+                                                             float2* __restrict__ Ag, int* __restrict__ err) {
     __shared__ float4 cand[kMaxCand];
-    __shared__ float2 sA[kAceN * kAceLm][kTile];
+    __shared__ unsigned short nbr[kMaxNbr][kTile];
+    __shared__ int nnbr[kTile];
     __shared__ int scan_tmp[16];
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const AceTile tl = ace_tile(bins, Nx, Ny, Nz, rcut, pt_begin, n_pts, cand, scan_tmp, err);
-    const int64_t idx = tl.idx;
-    const bool valid = tl.valid;
-    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)
-        sA[e / kTile][e % kTile] = make_float2(0.f, 0.f);
     __syncthreads();
-    ace_project(cand, tl, rcut, wave, kAceWaves, lane, sA);
+    // per-point neighbour lists (wave 0), in candidate order
+    const float rcf = (float)rcut;
+    if (wave == 0) {
+        int cnt = 0;
+        for (int c = 0; c < tl.ncand; ++c) {
+            const float4 q = cand[c];
+            const float dx = q.x - tl.px, dy = q.y - tl.py, dz = q.z - tl.pz;
+            if (dx * dx + dy * dy + dz * dz < rcf * rcf) {
+                if (cnt < kMaxNbr) nbr[cnt][lane] = (unsigned short)c;
+                ++cnt;
+            }
+        }
+        if (cnt > kMaxNbr) atomicOr(err, kErrNbr);
+        nnbr[lane] = tl.valid ? (cnt < kMaxNbr ? cnt : kMaxNbr) : 0;
+    }
+    __syncthreads();
+    const int my_n = nnbr[lane];
+    const int n_iter = wave_max_int(my_n);
+    // wave n forms the rows of radial index n
+    float2* dst = Ag + ((int64_t)blockIdx.x * kAceN * kAceLm + wave * kAceLm) * kTile;
+    ace_project_n(cand, nbr, my_n, n_iter, tl, rcut, wave, lane, dst);
+}
+
+// The tile's A from the projection kernel into LDS (whole block).
+__device__ __forceinline__ void ace_load_tile(const float2* __restrict__ Ag, float2 (*sA)[kTile]) {
+    const float2* src = Ag + (int64_t)blockIdx.x * kAceN * kAceLm * kTile;
+    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x) sA[e / kTile][e % kTile] = src[e];
+}
+
+// Ranks 1-3 of one tile from its projected A (no register-heavy projection
+// here, so many blocks share a CU).
+__global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restrict__ Ag, int nmax, int lmax,
+                                                        int64_t n_pts, const int* __restrict__ groups,
+                                                        int n_groups, const int2* __restrict__ terms,
+                                                        const int* __restrict__ outputs, int n_desc,
+                                                        float* __restrict__ out, int64_t ps, int64_t ds) {
+    __shared__ float2 sA[kAceN * kAceLm][kTile];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t idx = (int64_t)blockIdx.x * kTile + lane;
+    const bool valid = idx < n_pts;
+    ace_load_tile(Ag, sA);
     __syncthreads();
 
-    float* o = out + (valid ? idx : 0) * n_desc;
+    float* o = out + (valid ? idx : 0) * ps;       // descriptor d at o[d * ds]
     const int n12 = nmax + (lmax + 1) * nmax * (nmax + 1) / 2;
     int d = 0;
     if (wave == 0) {
     for (int n = 0; n < nmax; ++n, ++d)
-        if (valid) o[d] = sA[n * kAceLm][lane].x;
+        if (valid) o[d * ds] = sA[n * kAceLm][lane].x;
     for (int l = 0; l <= lmax; ++l)
         for (int n1 = 0; n1 < nmax; ++n1)
             for (int n2 = n1; n2 < nmax; ++n2, ++d) {
@@ -206,7 +235,7 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
                     const float2 a = sA[n1 * kAceLm + e0 + m][lane], b = sA[n2 * kAceLm + e0 + m][lane];
                     s = fmaf(2.f, a.x * b.x + a.y * b.y, s);
                 }
-                if (valid) o[d] = s;
+                if (valid) o[d * ds] = s;
             }
     }
     // rank 3 by groups (p1, p2, l3): P(m3) once, then every n3 of the group
@@ -219,11 +248,11 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
     };
     int nxt[6] = {0, 0, 0, 0, 0, 0};
     if (n_groups > 0) header(wave, nxt);
-    for (int gi = wave; gi < n_groups; gi += kAceWaves) {
+    for (int gi = wave; gi < n_groups; gi += kAce3Waves) {
         int h[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) h[i] = nxt[i];
-        header(gi + kAceWaves, nxt);
+        header(gi + kAce3Waves, nxt);
         int t = __builtin_amdgcn_readfirstlane(h[0]);
         const int l3 = __builtin_amdgcn_readfirstlane(h[1]);
         const int o0 = __builtin_amdgcn_readfirstlane(h[2]), oc = __builtin_amdgcn_readfirstlane(h[3]);
@@ -278,44 +307,40 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace(BinState bins, int Nx, i
                     v = fmaf(sg, pr[slot] * c.x - pim[slot] * cy, v);    // Re(P A)
                 }
             });
-            if (valid) o[n12 + (ok >> 7)] = v;
+            if (valid) o[(n12 + (ok >> 7)) * ds] = v;
         }
     }
 }
 
-// Rank 4 (one intermediate coupling L).  Eight waves per 64-point tile:
-// after the projection, for every L the coupled pairs
+// Rank 4 (one intermediate coupling L).  Sixteen waves per 64-point tile
+// (the projected A of the tile in LDS): for every L the coupled pairs
 // P_a(M) = sum_m1 <l1 m1 l2 m2|L M> A_p1 A_p2 (M = 0..L) the descriptors of
-// that L need are formed into LDS (every wave takes every eighth unit
+// that L need are formed into LDS (every wave takes every sixteenth unit
 // (a, M)), then every wave evaluates a contiguous share of that L's
 // descriptors, B = f (Re P_a(0) conj P_b(0) + 2 sum_{M>0} Re P_a(M) conj P_b(M))
 // (f = (-1)^(l3+l4) / sqrt(2L+1)), keeping P_a in registers while consecutive
 // descriptors share it.  Terms and descriptors come from wave-uniform loads.
-constexpr int kAce4Waves = 8;
+constexpr int kAce4Waves = 16;
 
-__global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(BinState bins, int Nx, int Ny, int Nz, double rcut,
-                                                          int lmax4, int64_t pt_begin, int64_t n_pts,
+__global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restrict__ Ag, int lmax4, int64_t n_pts,
                                                           const int* __restrict__ l_units,
                                                           const int4* __restrict__ units,
                                                           const int2* __restrict__ terms,
                                                           const int* __restrict__ l_descs,
                                                           const int4* __restrict__ descs, int n4,
-                                                          float* __restrict__ out, int* __restrict__ err) {
-    __shared__ float4 cand[kMaxCand];
+                                                          float* __restrict__ out, int64_t ps, int64_t ds) {
     __shared__ float2 sA[kAceN * kAceLm][kTile];
-    __shared__ int scan_tmp[16];
     extern __shared__ float2 sP[];          // [slots][kTile]
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const AceTile tl = ace_tile(bins, Nx, Ny, Nz, rcut, pt_begin, n_pts, cand, scan_tmp, err);
-    for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x)
-        sA[e / kTile][e % kTile] = make_float2(0.f, 0.f);
-    __syncthreads();
-    ace_project(cand, tl, rcut, wave, kAce4Waves, lane, sA);
+    AceTile tl;
+    tl.idx = (int64_t)blockIdx.x * kTile + lane;
+    tl.valid = tl.idx < n_pts;
+    ace_load_tile(Ag, sA);
     __syncthreads();
 
-    float* o = out + (tl.valid ? tl.idx : 0) * n4;
+    float* o = out + (tl.valid ? tl.idx : 0) * ps;    // descriptor k at o[k * ds]
     for (int L = 0; L <= 2 * lmax4; ++L) {
         // coupled pairs of this L into sP
         const int u0 = l_units[L], u1 = l_units[L + 1];
@@ -370,15 +395,24 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(BinState bins, int Nx,
                     acc = fmaf(pa[M].x, b.x, fmaf(pa[M].y, b.y, acc));
                 }
             const float v = f * fmaf(2.f, acc, pa[0].x * b0.x + pa[0].y * b0.y);
-            if (tl.valid) o[ok] = v;
+            if (tl.valid) o[ok * ds] = v;
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_ace4(hipStream_t s, const BinState& bins, const int N[3], double rcut, int lmax4, int64_t pt_begin,
-                       int64_t n_pts, const int* l_units, const int4* units, const int2* terms, const int* l_descs,
-                       const int4* descs, int max_slots, int n4, float* out, int* err) {
+hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], double rcut, int64_t pt_begin,
+                           int64_t n_pts, float2* Ag, int* err) {
+    if (n_pts <= 0) return hipSuccess;
+    const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_ace_proj, dim3((unsigned)n_tiles), dim3(64 * kAceWaves), 0, s, bins, N[0], N[1], N[2], rcut,
+                       pt_begin, n_pts, Ag, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts, const int* l_units,
+                       const int4* units, const int2* terms, const int* l_descs, const int4* descs, int max_slots,
+                       int n4, float* out, int64_t ps, int64_t ds) {
     if (n_pts <= 0 || n4 <= 0) return hipSuccess;
     if (lmax4 < 0 || lmax4 > kAce4MaxL) return hipErrorInvalidValue;
     const size_t lds = sizeof(float2) * (size_t)max_slots * kTile;
@@ -391,19 +425,19 @@ hipError_t launch_ace4(hipStream_t s, const BinState& bins, const int N[3], doub
     if (attr_err != hipSuccess) return attr_err;
     if (lds > kAce4LdsBudget) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, bins, N[0], N[1], N[2], rcut,
-                       lmax4, pt_begin, n_pts, l_units, units, terms, l_descs, descs, n4, out, err);
+    hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, Ag, lmax4, n_pts, l_units,
+                       units, terms, l_descs, descs, n4, out, ps, ds);
     return hipGetLastError();
 }
 
-hipError_t launch_ace(hipStream_t s, const BinState& bins, const int N[3], double rcut, int nmax, int lmax,
-                      int64_t pt_begin, int64_t n_pts, const int* groups, int n_groups, const int2* terms,
-                      const int* outputs, int n_desc, float* out, int* err) {
+hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64_t n_pts, const int* groups,
+                      int n_groups, const int2* terms, const int* outputs, int n_desc, float* out, int64_t ps,
+                      int64_t ds) {
     if (n_pts <= 0) return hipSuccess;
     if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAceWaves), 0, s, bins, N[0], N[1], N[2], rcut, nmax, lmax,
-                       pt_begin, n_pts, groups, n_groups, terms, outputs, n_desc, out, err);
+    hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAce3Waves), 0, s, Ag, nmax, lmax, n_pts, groups,
+                       n_groups, terms, outputs, n_desc, out, ps, ds);
     return hipGetLastError();
 }
 

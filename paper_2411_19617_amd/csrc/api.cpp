@@ -119,6 +119,7 @@ struct mala_ctx {
     DevBuf<double4> atoms_tmp, atoms_sorted;
     DevBuf<float2> u;
     DevBuf<float2> yadj;                 // dL/du of the descriptor adjoint, laid out like u
+    DevBuf<float2> aceA;                 // projected grid ACE basis of one chunk [tile][60][64]
     DevBuf<float> Bbuf;
     DevBuf<double> partials, est_partials;
     DevBuf<double> fermi_w;
@@ -486,6 +487,7 @@ void ctx_trim(mala_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     release(c->u);
     release(c->yadj);
+    release(c->aceA);
     release(c->Bbuf);
     release(c->window);
     release(c->prefix);
@@ -552,6 +554,8 @@ mala_status mala_destroy(mala_ctx* c) {
     release(c->atoms_tmp);
     release(c->atoms_sorted);
     release(c->u);
+    release(c->yadj);
+    release(c->aceA);
     release(c->Bbuf);
     release(c->partials);
     release(c->est_partials);
@@ -890,10 +894,12 @@ int32_t mala_ace_count(int32_t nmax, int32_t lmax) {
 
 mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
                                  double rcut, int32_t nmax, int32_t lmax, int64_t pt_begin, int64_t pt_end,
-                                 float* out) {
+                                 int32_t layout, float* out) {
     if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
     if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL)
         return fail(MALA_E_UNSUPPORTED, "grid ACE: nmax must be 1..4 and lmax 0..4");
+    if (layout != MALA_LAYOUT_POINT_MAJOR && layout != MALA_LAYOUT_DESCRIPTOR_MAJOR)
+        return fail(MALA_E_INVALID_ARG, "unknown output layout");
     mala_status st = check_geometry(positions, n_atoms, cg, rcut, 2);
     if (st) return st;
     const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
@@ -922,13 +928,24 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
         t.ready = true;
     }
     const int n_desc = ace_count_ranks12(nmax, lmax) + t.n3;
+    // point-major [point][descriptor] or descriptor-major [descriptor][point]
+    const int64_t ps = layout == MALA_LAYOUT_POINT_MAJOR ? n_desc : 1;
+    const int64_t ds = layout == MALA_LAYOUT_POINT_MAJOR ? 1 : pt_end - pt_begin;
     if ((st = upload_positions(c, positions, n_atoms))) return st;
     BinState bs{};
     if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
-    HIP_TRY(staged(c, MALA_STAGE_ACE, pt_end - pt_begin, [&] {
-        return launch_ace(c->stream, bs, cg->N, rcut, nmax, lmax, pt_begin, pt_end - pt_begin, t.groups, t.n_groups,
-                          t.terms, t.outputs, n_desc, out, c->err);
-    }));
+    const int64_t total = pt_end - pt_begin;
+    const int64_t chunk = total < kChunk ? total : kChunk;
+    HIP_TRY(ensure(c->n_allocs, c->aceA, (size_t)((chunk + kTile - 1) / kTile) * kAceAPerPoint * kTile));
+    for (int64_t off = 0; off < total; off += chunk) {
+        const int64_t n = (total - off) < chunk ? (total - off) : chunk;
+        HIP_TRY(staged(c, MALA_STAGE_ACE, n, [&] {
+            hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
+            if (e != hipSuccess) return e;
+            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, t.groups, t.n_groups, t.terms, t.outputs, n_desc,
+                              out + off * ps, ps, ds);
+        }));
+    }
     return MALA_OK;
 }
 
@@ -949,10 +966,12 @@ int32_t mala_ace4_list(int32_t nmax4, int32_t lmax4, int32_t* out, int32_t cap) 
 
 mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
                                   double rcut, int32_t nmax4, int32_t lmax4, int64_t pt_begin, int64_t pt_end,
-                                  float* out) {
+                                  int32_t layout, float* out) {
     if (!c) return fail(MALA_E_INVALID_ARG, "ctx is NULL");
     if (nmax4 < 1 || nmax4 > kAce4MaxN || lmax4 < 0 || lmax4 > kAce4MaxL)
         return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: nmax4 must be 1..3 and lmax4 0..3");
+    if (layout != MALA_LAYOUT_POINT_MAJOR && layout != MALA_LAYOUT_DESCRIPTOR_MAJOR)
+        return fail(MALA_E_INVALID_ARG, "unknown output layout");
     mala_status st = check_geometry(positions, n_atoms, cg, rcut, 2);
     if (st) return st;
     const int64_t ntot = (int64_t)cg->N[0] * cg->N[1] * cg->N[2];
@@ -990,10 +1009,20 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
     if ((st = upload_positions(c, positions, n_atoms))) return st;
     BinState bs{};
     if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
-    HIP_TRY(staged(c, MALA_STAGE_ACE4, pt_end - pt_begin, [&] {
-        return launch_ace4(c->stream, bs, cg->N, rcut, lmax4, pt_begin, pt_end - pt_begin, t.l_units, t.units,
-                           t.terms, t.l_descs, t.descs, t.max_slots, t.n4, out, c->err);
-    }));
+    const int64_t total = pt_end - pt_begin;
+    const int64_t chunk = total < kChunk ? total : kChunk;
+    const int64_t ps4 = layout == MALA_LAYOUT_POINT_MAJOR ? t.n4 : 1;
+    const int64_t ds4 = layout == MALA_LAYOUT_POINT_MAJOR ? 1 : total;
+    HIP_TRY(ensure(c->n_allocs, c->aceA, (size_t)((chunk + kTile - 1) / kTile) * kAceAPerPoint * kTile));
+    for (int64_t off = 0; off < total; off += chunk) {
+        const int64_t n = (total - off) < chunk ? (total - off) : chunk;
+        HIP_TRY(staged(c, MALA_STAGE_ACE4, n, [&] {
+            hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
+            if (e != hipSuccess) return e;
+            return launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.terms, t.l_descs, t.descs,
+                               t.max_slots, t.n4, out + off * ps4, ps4, ds4);
+        }));
+    }
     return MALA_OK;
 }
 

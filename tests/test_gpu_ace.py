@@ -147,3 +147,22 @@ def test_ace4_empty_and_unsupported(env):
     e = torch.empty((4, n), dtype=torch.float32, device="cuda")
     with pytest.raises(mala.MalaError):
         ctx.mala_ace4_descriptors(s.positions, s.L, s.N, s.rcut, 3, 4, 0, 4, out=e)
+
+
+@pytest.mark.parametrize("rank", [3, 4])
+def test_ace_descriptor_major_layout_is_the_transpose(env, rank):
+    """The descriptor-major output is the transpose of the point-major one
+    over a range that spans two 2^19-point chunks (to FP32 rounding: the
+    projection adds the waves' parts with LDS float atomics, so the last bits
+    of two calls may differ)."""
+    mala, ctx, torch = env
+    s = mala_synth.paper_solid()
+    b, e = 100_000, 100_000 + (1 << 19) + 777
+    f = ctx.mala_ace_descriptors if rank == 3 else ctx.mala_ace4_descriptors
+    pm = f(s.positions, s.L, s.N, s.rcut, pt_begin=b, pt_end=e)
+    dm = f(s.positions, s.L, s.N, s.rcut, pt_begin=b, pt_end=e, descriptor_major=True)
+    ctx.check_device_errors()
+    assert dm.shape == (pm.shape[1], pm.shape[0])
+    err = rel_rows(dm.t().cpu().double().numpy(), pm.cpu().double().numpy())
+    log("rank", rank, "layouts differ by %.3e" % err)
+    assert err <= 1e-6
