@@ -612,7 +612,8 @@ def ace_bench(ctx, mala, snap, mean_nbr, torch, reps=3, nmax=4, lmax=4):
     return {"nmax": nmax, "lmax": lmax, "descriptors": mala.ace_count(nmax, lmax), "rank3_terms": terms,
             "ms_per_grid": ms, "ms_per_grid_descriptor_major": ms_dm,
             "points_per_s": snap.n_points / (ms * 1e-3), "flops_per_point": fl,
-            "tflops": tf, "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS}
+            "tflops": tf, "peak": PEAK_FP32_VALU_TFLOPS, "frac": tf / PEAK_FP32_VALU_TFLOPS,
+            "frac_descriptor_major": fl * snap.n_points / (ms_dm * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS}
 
 
 def ace4_flops(mala, nmax4, lmax4, mean_nbr):

@@ -203,11 +203,64 @@ __device__ __forceinline__ void ace_load_tile(const float2* __restrict__ Ag, flo
     for (int e = threadIdx.x; e < kAceN * kAceLm * kTile; e += blockDim.x) sA[e / kTile][e % kTile] = src[e];
 }
 
+// Position of the structural term (m3, m1) in the coefficient block of a
+// rank-3 combination (l1, l2, l3): m3 = -l3..l3, m1 = -l1..l1 with
+// |m1 + m3| <= l2 (the host builds the block in the same order).
+__host__ __device__ constexpr int ace3_k(int L1, int L2, int L3, int m3, int m1) {
+    int k = 0;
+    for (int a = -L3; a <= L3; ++a)
+        for (int b = -L1; b <= L1; ++b) {
+            if (a == m3 && b == m1) return k;
+            if (-b - a >= -L2 && -b - a <= L2) ++k;
+        }
+    return k;
+}
+
+// P(m3) = sum_m1 (l1 l2 l3; m1, m2 = -m1-m3, m3) A1(m1) A2(m2) of one group,
+// code specialised for (L1, L2, L3): the group's A values are read from LDS
+// once into registers (L1 + 1 and L2 + 1 of them, m >= 0), and every index,
+// conjugation and sign of A_{l,-m} = (-1)^m conj A_{l,m} is resolved at
+// compile time; the 3j symbols come from the combination's coefficient block.
+template <int L1, int L2, int L3>
+__device__ __forceinline__ void ace3_group(const float2 (*sA)[kTile], int b1, int b2, int lane,
+                                           const float* __restrict__ cf, float (&pr)[9], float (&pim)[9]) {
+    float2 a1[L1 + 1], a2[L2 + 1];
+    static_for<0, L1 + 1>([&](auto mc) { a1[decltype(mc)::value] = sA[b1 + decltype(mc)::value][lane]; });
+    static_for<0, L2 + 1>([&](auto mc) { a2[decltype(mc)::value] = sA[b2 + decltype(mc)::value][lane]; });
+    static_for<0, 2 * L3 + 1>([&](auto ic) {
+        constexpr int m3 = decltype(ic)::value - L3;
+        // one slot's coefficients at a time (hoisting all of a group's loads
+        // ahead would hold up to 81 of them in registers)
+        __builtin_amdgcn_sched_barrier(0);
+        float xr = 0.f, xi = 0.f;
+        static_for<0, 2 * L1 + 1>([&](auto jc) {
+            constexpr int m1 = decltype(jc)::value - L1, m2 = -m1 - m3;
+            if constexpr (m2 >= -L2 && m2 <= L2) {
+                constexpr int k = ace3_k(L1, L2, L3, m3, m1);
+                constexpr int am1 = m1 < 0 ? -m1 : m1, am2 = m2 < 0 ? -m2 : m2;
+                constexpr bool neg = ((m1 < 0 && (am1 & 1)) != (m2 < 0 && (am2 & 1)));
+                const float c = neg ? -cf[k] : cf[k];
+                const float ax = a1[am1].x, ay = m1 < 0 ? -a1[am1].y : a1[am1].y;
+                const float bx = a2[am2].x, by = m2 < 0 ? -a2[am2].y : a2[am2].y;
+                xr = fmaf(c, ax * bx - ay * by, xr);
+                xi = fmaf(c, ax * by + ay * bx, xi);
+            }
+        });
+        pr[m3 + 4] = xr;
+        pim[m3 + 4] = xi;
+    });
+}
+
+__host__ __device__ constexpr bool ace3_combo_valid(int c) {
+    const int l1 = c / 25, l2 = (c / 5) % 5, l3 = c % 5;
+    return l3 >= (l1 > l2 ? l1 - l2 : l2 - l1) && l3 <= l1 + l2 && (l1 + l2 + l3) % 2 == 0;
+}
+
 // Ranks 1-3 of one tile from its projected A (no register-heavy projection
 // here, so many blocks share a CU).
 __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restrict__ Ag, int nmax, int lmax,
                                                         int64_t n_pts, const int* __restrict__ groups,
-                                                        int n_groups, const int2* __restrict__ terms,
+                                                        int n_groups, const float* __restrict__ coef,
                                                         const int* __restrict__ outputs, int n_desc,
                                                         float* __restrict__ out, int64_t ps, int64_t ds) {
     __shared__ float2 sA[kAceN * kAceLm][kTile];
@@ -241,56 +294,29 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
     // rank 3 by groups (p1, p2, l3): P(m3) once, then every n3 of the group
     // the next group's header is loaded while the current group is formed
     // (a wave past the last group re-reads group 0, unused)
-    auto header = [&](int gi, int (&h)[6]) {
+    auto header = [&](int gi, int (&h)[8]) {
         const int* gr = groups + 8 * (gi < n_groups ? gi : 0);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) h[i] = gr[i];
+        for (int i = 0; i < 8; ++i) h[i] = gr[i];
     };
-    int nxt[6] = {0, 0, 0, 0, 0, 0};
+    int nxt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (n_groups > 0) header(wave, nxt);
     for (int gi = wave; gi < n_groups; gi += kAce3Waves) {
-        int h[6];
+        int h[8];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) h[i] = nxt[i];
+        for (int i = 0; i < 8; ++i) h[i] = nxt[i];
         header(gi + kAce3Waves, nxt);
-        int t = __builtin_amdgcn_readfirstlane(h[0]);
+        const float* cf = coef + __builtin_amdgcn_readfirstlane(h[0]);
         const int l3 = __builtin_amdgcn_readfirstlane(h[1]);
         const int o0 = __builtin_amdgcn_readfirstlane(h[2]), oc = __builtin_amdgcn_readfirstlane(h[3]);
-        const int cnt8 = __builtin_amdgcn_readfirstlane(h[4]), c8 = __builtin_amdgcn_readfirstlane(h[5]);
+        const int combo = __builtin_amdgcn_readfirstlane(h[4]);
+        const int b1 = __builtin_amdgcn_readfirstlane(h[5]), b2 = __builtin_amdgcn_readfirstlane(h[6]);
         float pr[9], pim[9];
-        static_for<0, 9>([&](auto sc) {
-            constexpr int slot = decltype(sc)::value;
-            const int cnt = slot < 8 ? (cnt8 >> (4 * slot)) & 15 : c8;
-            float xr = 0.f, xi = 0.f;
-            auto term = [&](int2 e) {
-                const int pk2 = __builtin_amdgcn_readfirstlane(e.x);
-                const float cf = __int_as_float(__builtin_amdgcn_readfirstlane(e.y));
-                const float2 a = sA[pk2 & 127][lane], b = sA[(pk2 >> 7) & 127][lane];
-                const float ay = (pk2 & (1 << 14)) ? -a.y : a.y;
-                const float by = (pk2 & (1 << 15)) ? -b.y : b.y;
-                xr = fmaf(cf, a.x * b.x - ay * by, xr);
-                xi = fmaf(cf, a.x * by + ay * b.x, xi);
-            };
-            // four terms per step: their table loads and LDS reads are issued
-            // together, so a step waits once instead of once per term
-            int k = 0;
-            for (; k + 4 <= cnt; k += 4, t += 4) {
-                int2 e[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) e[j] = terms[t + j];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) term(e[j]);
+        static_for<0, 125>([&](auto cc) {
+            constexpr int C = decltype(cc)::value;
+            if constexpr (ace3_combo_valid(C)) {
+                if (combo == C) ace3_group<C / 25, (C / 5) % 5, C % 5>(sA, b1, b2, lane, cf, pr, pim);
             }
-            if (k + 2 <= cnt) {
-                const int2 e0 = terms[t], e1 = terms[t + 1];
-                term(e0);
-                term(e1);
-                k += 2;
-                t += 2;
-            }
-            if (k < cnt) term(terms[t++]);
-            pr[slot] = xr;
-            pim[slot] = xi;
         });
         for (int k = 0; k < oc; ++k) {
             const int ok = __builtin_amdgcn_readfirstlane(outputs[o0 + k]);
@@ -431,13 +457,13 @@ hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts
 }
 
 hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64_t n_pts, const int* groups,
-                      int n_groups, const int2* terms, const int* outputs, int n_desc, float* out, int64_t ps,
+                      int n_groups, const float* coef, const int* outputs, int n_desc, float* out, int64_t ps,
                       int64_t ds) {
     if (n_pts <= 0) return hipSuccess;
     if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAce3Waves), 0, s, Ag, nmax, lmax, n_pts, groups,
-                       n_groups, terms, outputs, n_desc, out, ps, ds);
+                       n_groups, coef, outputs, n_desc, out, ps, ds);
     return hipGetLastError();
 }
 

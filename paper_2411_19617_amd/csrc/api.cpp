@@ -102,7 +102,7 @@ struct AceTables {
     bool ready = false;
     int n3 = 0, n_groups = 0;
     int* groups = nullptr;
-    int2* terms = nullptr;
+    float* coef = nullptr;
     int* outputs = nullptr;
 };
 
@@ -569,7 +569,7 @@ mala_status mala_destroy(mala_ctx* c) {
     for (auto& row : c->ace)
         for (auto& a : row) {
             if (a.groups) (void)hipFree(a.groups);
-            if (a.terms) (void)hipFree(a.terms);
+            if (a.coef) (void)hipFree(a.coef);
             if (a.outputs) (void)hipFree(a.outputs);
         }
     for (auto& row : c->ace4)
@@ -887,9 +887,9 @@ mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n
 
 int32_t mala_ace_count(int32_t nmax, int32_t lmax) {
     if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL) return MALA_E_UNSUPPORTED;
-    std::vector<int> groups, idx, outs;
+    std::vector<int> groups, outs;
     std::vector<float> coef;
-    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, groups, idx, coef, outs);
+    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, groups, coef, outs);
 }
 
 mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
@@ -909,21 +909,16 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
     DeviceGuard g(c->device);
     AceTables& t = c->ace[nmax][lmax];
     if (!t.ready) {
-        std::vector<int> groups, idx, outs;
+        std::vector<int> groups, outs;
         std::vector<float> coef;
-        t.n3 = build_ace_tables(nmax, lmax, groups, idx, coef, outs);
+        t.n3 = build_ace_tables(nmax, lmax, groups, coef, outs);
         t.n_groups = (int)(groups.size() / 8);
-        std::vector<int2> terms(idx.size());
-        for (size_t i = 0; i < idx.size(); ++i) {
-            int cb;
-            memcpy(&cb, &coef[i], 4);
-            terms[i] = make_int2(idx[i], cb);
-        }
+        c->n_allocs += 3;
         HIP_TRY(hipMalloc(&t.groups, sizeof(int) * (groups.size() ? groups.size() : 1)));
-        HIP_TRY(hipMalloc(&t.terms, sizeof(int2) * (terms.size() ? terms.size() : 1)));
+        HIP_TRY(hipMalloc(&t.coef, sizeof(float) * (coef.size() ? coef.size() : 1)));
         HIP_TRY(hipMalloc(&t.outputs, sizeof(int) * (outs.size() ? outs.size() : 1)));
         HIP_TRY(hipMemcpy(t.groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(t.terms, terms.data(), sizeof(int2) * terms.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t.outputs, outs.data(), sizeof(int) * outs.size(), hipMemcpyHostToDevice));
         t.ready = true;
     }
@@ -942,7 +937,7 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
         HIP_TRY(staged(c, MALA_STAGE_ACE, n, [&] {
             hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
             if (e != hipSuccess) return e;
-            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, t.groups, t.n_groups, t.terms, t.outputs, n_desc,
+            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, t.groups, t.n_groups, t.coef, t.outputs, n_desc,
                               out + off * ps, ps, ds);
         }));
     }

@@ -196,19 +196,20 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
 // are formed once and every descriptor of the group is
 //   B = sum_m3 P(m3) A_{n3 l3 m3}.
 // A is stored for m >= 0 only (A_{l,-m} = (-1)^m conj(A_{l,m})) at n*15 +
-// l(l+1)/2 + |m|.  Per group: groups[8g..8g+7] = {first term, l3, first
-// output, output count, terms per m3 slot packed 4 bits x 8 (slots 0..7),
-// count of slot 8, 0, 0}; terms are sorted by slot m3 + 4 and pack the two
-// storage indices (7 bits each) and two conjugation flags (bits 14, 15),
-// the coefficient carrying the 3j symbol and the signs; outputs pack the
-// storage base n3*15 + l3(l3+1)/2 (bits 0-6) and the descriptor's rank-3
-// position (bits 7 and up).  The 3j symbol comes from the coupled states of
-// couple(): (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3) <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
-int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<int>& term_idx,
-                     std::vector<float>& term_coef, std::vector<int>& outputs) {
+// l(l+1)/2 + |m|.  The kernel evaluates a group with code specialised for
+// its (l1, l2, l3), so the 3j symbols of each such combination form one block
+// of coefficients shared by all groups of that combination, in the order
+// m3 = -l3..l3, m1 = -l1..l1 with |m1 + m3| <= l2 (zeros included).  Per group:
+// groups[8g..8g+7] = {offset of its coefficient block, l3, first output,
+// output count, l1*25 + l2*5 + l3, storage base of (n1, l1), of (n2, l2), 0};
+// outputs pack the storage base n3*15 + l3(l3+1)/2 (bits 0-6) and the
+// descriptor's rank-3 position (bits 7 and up).  The 3j symbol comes from the
+// coupled states of couple(): (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3)
+// <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
+int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef,
+                     std::vector<int>& outputs) {
     groups.clear();
-    term_idx.clear();
-    term_coef.clear();
+    coef.clear();
     outputs.clear();
     std::vector<Coupling> cache(25 * 25);
     std::vector<bool> have(cache.size(), false);
@@ -237,6 +238,7 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<i
                 if (l3 < abs(l1 - l2) || l3 > l1 + l2 || (l1 + l2 + l3) % 2) continue;
                 pos_of[(p1 * np + p2) * np + p3] = nd++;
             }
+    std::vector<int> block_of(125, -1);
     for (int p1 = 0; p1 < np; ++p1)
         for (int p2 = p1; p2 < np; ++p2)
             for (int l3 = 0; l3 <= lmax; ++l3) {
@@ -249,33 +251,18 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<i
                     outs.push_back((n3 * 15 + l3 * (l3 + 1) / 2) | (pos_of[(p1 * np + p2) * np + p3] << 7));
                 }
                 if (outs.empty()) continue;
-                int g[8] = {(int)term_idx.size(), l3, (int)outputs.size(), (int)outs.size(), 0, 0, 0, 0};
-                for (int slot = 0; slot < 9; ++slot) {
-                    const int m3 = slot - 4;
-                    int cnt = 0;
-                    if (abs(m3) <= l3)
+                const int combo = l1 * 25 + l2 * 5 + l3;
+                if (block_of[combo] < 0) {
+                    block_of[combo] = (int)coef.size();
+                    for (int m3 = -l3; m3 <= l3; ++m3)
                         for (int m1 = -l1; m1 <= l1; ++m1) {
                             const int m2 = -m1 - m3;
                             if (abs(m2) > l2) continue;
-                            double coef = three_j(l1, l2, l3, m1, m2, m3);
-                            if (coef == 0.0) continue;
-                            const int m[2] = {m1, m2}, n[2] = {n1, n2}, l[2] = {l1, l2};
-                            int packed = 0;
-                            for (int i = 0; i < 2; ++i) {
-                                const int am = abs(m[i]);
-                                packed |= (n[i] * 15 + l[i] * (l[i] + 1) / 2 + am) << (7 * i);
-                                if (m[i] < 0) {
-                                    packed |= 1 << (14 + i);
-                                    if (am & 1) coef = -coef;
-                                }
-                            }
-                            term_idx.push_back(packed);
-                            term_coef.push_back((float)coef);
-                            ++cnt;
+                            coef.push_back((float)three_j(l1, l2, l3, m1, m2, m3));
                         }
-                    if (slot < 8) g[4] |= cnt << (4 * slot);
-                    else g[5] = cnt;
                 }
+                const int g[8] = {block_of[combo], l3, (int)outputs.size(), (int)outs.size(), combo,
+                                  n1 * 15 + l1 * (l1 + 1) / 2, n2 * 15 + l2 * (l2 + 1) / 2, 0};
                 for (int i = 0; i < 8; ++i) groups.push_back(g[i]);
                 for (int o : outs) outputs.push_back(o);
             }
