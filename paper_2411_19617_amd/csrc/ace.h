@@ -18,8 +18,8 @@ constexpr int kAce4MaxL = 3;
 constexpr size_t kAce4LdsBudget = 96 * 1024;     // dynamic LDS of the pair vectors of one L
 int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc);
 int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
-                      std::vector<int>& term_idx, std::vector<float>& term_coef, std::vector<int>& l_descs,
-                      std::vector<int4>& descs, int& max_slots);
+                      std::vector<float>& coef, std::vector<int>& l_descs, std::vector<int4>& descs,
+                      int& max_slots);
 // A of every point of a chunk (n < 4, l <= 4, m >= 0: 60 complex per point),
 // laid out [tile][60][64 lanes], written by the projection kernel and read by
 // the contraction kernels.
@@ -27,7 +27,7 @@ constexpr int kAceAPerPoint = kAceMaxN * 15;
 hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], double rcut, int64_t pt_begin,
                            int64_t n_pts, float2* Ag, int* err);
 hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts, const int* l_units,
-                       const int4* units, const int2* terms, const int* l_descs, const int4* descs, int max_slots,
+                       const int4* units, const float* coef, const int* l_descs, const int4* descs, int max_slots,
                        int n4, float* out, int64_t ps, int64_t ds);   // descriptor k of point p at out[p ps + k ds]
 hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64_t n_pts, const int* groups,
                       int n_groups, const float* coef, const int* outputs, int n_desc, float* out, int64_t ps,

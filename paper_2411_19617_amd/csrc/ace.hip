@@ -338,11 +338,59 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
     }
 }
 
+// Position of the term (M, m1) in the Clebsch-Gordan block of a rank-4
+// pair combination (l1, l2, L): M = 0..L, m1 = -l1..l1 with |M - m1| <= l2
+// (the host builds the block in the same order).
+__host__ __device__ constexpr int ace4_k(int L1, int L2, int M, int m1) {
+    int k = 0;
+    for (int a = 0; a <= M; ++a)
+        for (int b = -L1; b <= L1; ++b) {
+            if (a == M && b == m1) return k;
+            if (a - b >= -L2 && a - b <= L2) ++k;
+        }
+    return k;
+}
+
+// P_a(M) = sum_m1 <l1 m1 l2 m2|L M> A1(m1) A2(m2), m2 = M - m1, for M = 0..L,
+// code specialised for (L1, L2, LL): the pair's A values in registers,
+// indices, conjugations and signs at compile time; written to dst[M][lane].
+template <int L1, int L2, int LL>
+__device__ __forceinline__ void ace4_pair(const float2 (*sA)[kTile], int b1, int b2, int lane,
+                                          const float* __restrict__ cf, float2* __restrict__ dst) {
+    float2 a1[L1 + 1], a2[L2 + 1];
+    static_for<0, L1 + 1>([&](auto mc) { a1[decltype(mc)::value] = sA[b1 + decltype(mc)::value][lane]; });
+    static_for<0, L2 + 1>([&](auto mc) { a2[decltype(mc)::value] = sA[b2 + decltype(mc)::value][lane]; });
+    static_for<0, LL + 1>([&](auto ic) {
+        constexpr int M = decltype(ic)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        float xr = 0.f, xi = 0.f;
+        static_for<0, 2 * L1 + 1>([&](auto jc) {
+            constexpr int m1 = decltype(jc)::value - L1, m2 = M - m1;
+            if constexpr (m2 >= -L2 && m2 <= L2) {
+                constexpr int k = ace4_k(L1, L2, M, m1);
+                constexpr int am1 = m1 < 0 ? -m1 : m1, am2 = m2 < 0 ? -m2 : m2;
+                constexpr bool neg = ((m1 < 0 && (am1 & 1)) != (m2 < 0 && (am2 & 1)));
+                const float c = neg ? -cf[k] : cf[k];
+                const float ax = a1[am1].x, ay = m1 < 0 ? -a1[am1].y : a1[am1].y;
+                const float bx = a2[am2].x, by = m2 < 0 ? -a2[am2].y : a2[am2].y;
+                xr = fmaf(c, ax * bx - ay * by, xr);
+                xi = fmaf(c, ax * by + ay * bx, xi);
+            }
+        });
+        dst[M * kTile + lane] = make_float2(xr, xi);
+    });
+}
+
+__host__ __device__ constexpr bool ace4_combo_valid(int c) {
+    const int l1 = c / 28, l2 = (c / 7) % 4, L = c % 7;
+    return L >= (l1 > l2 ? l1 - l2 : l2 - l1) && L <= l1 + l2;
+}
+
 // Rank 4 (one intermediate coupling L).  Sixteen waves per 64-point tile
 // (the projected A of the tile in LDS): for every L the coupled pairs
 // P_a(M) = sum_m1 <l1 m1 l2 m2|L M> A_p1 A_p2 (M = 0..L) the descriptors of
-// that L need are formed into LDS (every wave takes every sixteenth unit
-// (a, M)), then every wave evaluates a contiguous share of that L's
+// that L need are formed into LDS (every wave takes every sixteenth pair, all
+// its M by code specialised for (l1, l2, L)), then every wave evaluates a contiguous share of that L's
 // descriptors, B = f (Re P_a(0) conj P_b(0) + 2 sum_{M>0} Re P_a(M) conj P_b(M))
 // (f = (-1)^(l3+l4) / sqrt(2L+1)), keeping P_a in registers while consecutive
 // descriptors share it.  Terms and descriptors come from wave-uniform loads.
@@ -351,7 +399,7 @@ constexpr int kAce4Waves = 16;
 __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restrict__ Ag, int lmax4, int64_t n_pts,
                                                           const int* __restrict__ l_units,
                                                           const int4* __restrict__ units,
-                                                          const int2* __restrict__ terms,
+                                                          const float* __restrict__ coef,
                                                           const int* __restrict__ l_descs,
                                                           const int4* __restrict__ descs, int n4,
                                                           float* __restrict__ out, int64_t ps, int64_t ds) {
@@ -372,28 +420,16 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
         const int u0 = l_units[L], u1 = l_units[L + 1];
         for (int u = u0 + wave; u < u1; u += kAce4Waves) {
             const int4 h = units[u];
-            int t = __builtin_amdgcn_readfirstlane(h.x);
-            const int cnt = __builtin_amdgcn_readfirstlane(h.y), slot = __builtin_amdgcn_readfirstlane(h.z);
-            float xr = 0.f, xi = 0.f;
-            auto term = [&](int2 e) {
-                const int pk2 = __builtin_amdgcn_readfirstlane(e.x);
-                const float cf = __int_as_float(__builtin_amdgcn_readfirstlane(e.y));
-                const float2 a = sA[pk2 & 127][lane], b = sA[(pk2 >> 7) & 127][lane];
-                const float ay = (pk2 & (1 << 14)) ? -a.y : a.y;
-                const float by = (pk2 & (1 << 15)) ? -b.y : b.y;
-                xr = fmaf(cf, a.x * b.x - ay * by, xr);
-                xi = fmaf(cf, a.x * by + ay * b.x, xi);
-            };
-            int k = 0;
-            for (; k + 4 <= cnt; k += 4, t += 4) {
-                int2 e[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) e[j] = terms[t + j];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) term(e[j]);
-            }
-            for (; k < cnt; ++k) term(terms[t++]);
-            sP[slot * kTile + lane] = make_float2(xr, xi);
+            const float* cf = coef + __builtin_amdgcn_readfirstlane(h.x);
+            const int combo = __builtin_amdgcn_readfirstlane(h.y), slot = __builtin_amdgcn_readfirstlane(h.z);
+            const int bb = __builtin_amdgcn_readfirstlane(h.w);
+            const int b1 = bb & 255, b2 = bb >> 8;
+            static_for<0, 4 * 4 * 7>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                if constexpr (ace4_combo_valid(C)) {
+                    if (combo == C) ace4_pair<C / 28, (C / 7) % 4, C % 7>(sA, b1, b2, lane, cf, sP + slot * kTile);
+                }
+            });
         }
         __syncthreads();
         // this L's descriptors, a contiguous share per wave
@@ -437,7 +473,7 @@ hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], 
 }
 
 hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts, const int* l_units,
-                       const int4* units, const int2* terms, const int* l_descs, const int4* descs, int max_slots,
+                       const int4* units, const float* coef, const int* l_descs, const int4* descs, int max_slots,
                        int n4, float* out, int64_t ps, int64_t ds) {
     if (n_pts <= 0 || n4 <= 0) return hipSuccess;
     if (lmax4 < 0 || lmax4 > kAce4MaxL) return hipErrorInvalidValue;
@@ -452,7 +488,7 @@ hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts
     if (lds > kAce4LdsBudget) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, Ag, lmax4, n_pts, l_units,
-                       units, terms, l_descs, descs, n4, out, ps, ds);
+                       units, coef, l_descs, descs, n4, out, ps, ds);
     return hipGetLastError();
 }
 

@@ -93,7 +93,7 @@ struct Ace4Tables {
     int n4 = 0, max_slots = 0;
     int* l_units = nullptr;
     int4* units = nullptr;
-    int2* terms = nullptr;
+    float* coef = nullptr;
     int* l_descs = nullptr;
     int4* descs = nullptr;
 };
@@ -576,7 +576,7 @@ mala_status mala_destroy(mala_ctx* c) {
         for (auto& a : row) {
             if (a.l_units) (void)hipFree(a.l_units);
             if (a.units) (void)hipFree(a.units);
-            if (a.terms) (void)hipFree(a.terms);
+            if (a.coef) (void)hipFree(a.coef);
             if (a.l_descs) (void)hipFree(a.l_descs);
             if (a.descs) (void)hipFree(a.descs);
         }
@@ -976,27 +976,21 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
     DeviceGuard g(c->device);
     Ace4Tables& t = c->ace4[nmax4][lmax4];
     if (!t.ready) {
-        std::vector<int> l_units, term_idx, l_descs;
+        std::vector<int> l_units, l_descs;
         std::vector<int4> units, descs;
         std::vector<float> coef;
-        t.n4 = build_ace4_tables(nmax4, lmax4, l_units, units, term_idx, coef, l_descs, descs, t.max_slots);
+        t.n4 = build_ace4_tables(nmax4, lmax4, l_units, units, coef, l_descs, descs, t.max_slots);
         if ((size_t)t.max_slots * kTile * sizeof(float2) > kAce4LdsBudget)
             return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: pair vectors exceed the LDS budget");
-        std::vector<int2> terms(term_idx.size());
-        for (size_t i = 0; i < term_idx.size(); ++i) {
-            int cb;
-            memcpy(&cb, &coef[i], 4);
-            terms[i] = make_int2(term_idx[i], cb);
-        }
         c->n_allocs += 5;
         HIP_TRY(hipMalloc(&t.l_units, sizeof(int) * l_units.size()));
         HIP_TRY(hipMalloc(&t.units, sizeof(int4) * (units.size() ? units.size() : 1)));
-        HIP_TRY(hipMalloc(&t.terms, sizeof(int2) * (terms.size() ? terms.size() : 1)));
+        HIP_TRY(hipMalloc(&t.coef, sizeof(float) * (coef.size() ? coef.size() : 1)));
         HIP_TRY(hipMalloc(&t.l_descs, sizeof(int) * l_descs.size()));
         HIP_TRY(hipMalloc(&t.descs, sizeof(int4) * (descs.size() ? descs.size() : 1)));
         HIP_TRY(hipMemcpy(t.l_units, l_units.data(), sizeof(int) * l_units.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t.units, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(t.terms, terms.data(), sizeof(int2) * terms.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t.l_descs, l_descs.data(), sizeof(int) * l_descs.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t.descs, descs.data(), sizeof(int4) * descs.size(), hipMemcpyHostToDevice));
         t.ready = true;
@@ -1014,7 +1008,7 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
         HIP_TRY(staged(c, MALA_STAGE_ACE4, n, [&] {
             hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
             if (e != hipSuccess) return e;
-            return launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.terms, t.l_descs, t.descs,
+            return launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
                                t.max_slots, t.n4, out + off * ps4, ps4, ds4);
         }));
     }

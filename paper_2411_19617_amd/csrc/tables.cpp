@@ -282,8 +282,9 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<f
 // P_a(-M) = (-1)^(l1+l2-L+M) conj P_a(M); for an even l-sum the descriptor is
 //   B = (-1)^(l3+l4-L) (-1)^L / sqrt(2L+1)
 //       [Re P_a(0) conj P_b(0) + 2 sum_{M>=1} Re P_a(M) conj P_b(M)],
-// so only M >= 0 of every pair is formed.  Tables per L: pair units (first
-// term, term count, LDS slot of P_a(M)), terms packed as in rank 3, and
+// so only M >= 0 of every pair is formed.  Tables per L: pair units
+// (coefficient block, (l1, l2, L) combination, LDS slot of P_a(0), storage
+// bases of the two keys), one Clebsch-Gordan block per combination, and
 // descriptors (slot of P_a(0), slot of P_b(0), output position, factor).
 namespace {
 
@@ -373,8 +374,8 @@ int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc) {
 }
 
 int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
-                      std::vector<int>& term_idx, std::vector<float>& term_coef, std::vector<int>& l_descs,
-                      std::vector<int4>& descs, int& max_slots) {
+                      std::vector<float>& coef, std::vector<int>& l_descs, std::vector<int4>& descs,
+                      int& max_slots) {
     std::vector<int> set;
     const int n4 = ace4_descriptor_set(nmax4, lmax4, set);
     Ace4Cg cg;
@@ -382,10 +383,10 @@ int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vect
     l_units.assign(1, 0);
     l_descs.assign(1, 0);
     units.clear();
-    term_idx.clear();
-    term_coef.clear();
+    coef.clear();
     descs.clear();
     max_slots = 0;
+    std::vector<int> block_of(4 * 4 * 7, -1);        // (l1, l2, L) with l <= 3, L <= 6
     for (int L = 0; L <= 2 * lmax4; ++L) {
         // the pairs this L needs, in first-use order, each with L+1 slots
         std::vector<std::pair<int, int>> pairs;
@@ -412,31 +413,25 @@ int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vect
             memcpy(&fb, &ff, 4);
             descs.push_back(make_int4(x[0], x[1], x[2], fb));
         }
+        // one unit per pair: P_a(M) for M = 0..L by code specialised for
+        // (l1, l2, L), with the Clebsch-Gordan coefficients of that
+        // combination in one block, ordered M = 0..L, m1 = -l1..l1 with
+        // |M - m1| <= l2 (zeros included)
         for (size_t i = 0; i < pairs.size(); ++i) {
             const int pa = pairs[i].first, pb = pairs[i].second;
             const int n1 = pa / nl, l1 = pa % nl, n2 = pb / nl, l2 = pb % nl;
-            for (int M = 0; M <= L; ++M) {
-                const int t0 = (int)term_idx.size();
-                for (int m1 = -l1; m1 <= l1; ++m1) {
-                    const int m2 = M - m1;
-                    if (abs(m2) > l2) continue;
-                    double coef = cg(l1, m1, l2, m2, L, M);
-                    if (coef == 0.0) continue;
-                    const int m[2] = {m1, m2}, n[2] = {n1, n2}, ll[2] = {l1, l2};
-                    int packed = 0;
-                    for (int j = 0; j < 2; ++j) {
-                        const int am = abs(m[j]);
-                        packed |= (n[j] * 15 + ll[j] * (ll[j] + 1) / 2 + am) << (7 * j);
-                        if (m[j] < 0) {
-                            packed |= 1 << (14 + j);
-                            if (am & 1) coef = -coef;
-                        }
+            const int combo = (l1 * 4 + l2) * 7 + L;
+            if (block_of[combo] < 0) {
+                block_of[combo] = (int)coef.size();
+                for (int M = 0; M <= L; ++M)
+                    for (int m1 = -l1; m1 <= l1; ++m1) {
+                        const int m2 = M - m1;
+                        if (abs(m2) > l2) continue;
+                        coef.push_back((float)cg(l1, m1, l2, m2, L, M));
                     }
-                    term_idx.push_back(packed);
-                    term_coef.push_back((float)coef);
-                }
-                units.push_back(make_int4(t0, (int)term_idx.size() - t0, (int)i * (L + 1) + M, 0));
             }
+            const int base1 = n1 * 15 + l1 * (l1 + 1) / 2, base2 = n2 * 15 + l2 * (l2 + 1) / 2;
+            units.push_back(make_int4(block_of[combo], combo, (int)i * (L + 1), base1 | (base2 << 8)));
         }
         max_slots = std::max(max_slots, (int)pairs.size() * (L + 1));
         l_units.push_back((int)units.size());
