@@ -52,12 +52,12 @@ __host__ __device__ constexpr float ace_norm(int l, int m) {
     return (float)ace_sqrt((2 * l + 1) / (4.0 * 3.14159265358979323846) * ace_fact(l - m) / ace_fact(l + m));
 }
 
-// The tile's own point (lane = point) relative to the tile origin, and its
-// candidate atom images gathered into cand (whole block).
+// The tile's own point (lane = point) relative to the origins of its
+// candidate atom images, gathered into cand (whole block).
 struct AceTile {
     int64_t idx;      // point index within the launch range
     bool valid;
-    float px, py, pz;
+    PointFrame frame;
     int ncand;
 };
 
@@ -73,17 +73,12 @@ __device__ __forceinline__ AceTile ace_tile(const BinState& bins, int Nx, int Ny
     const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
                  rz = (double)pk * bins.L[2] / Nz;
     const int64_t p0 = pt_begin + tile * kTile;
-    const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
-    const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
-                 oz = (double)qk * bins.L[2] / Nz;
     const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
-    const double org[3] = {ox, oy, oz};
-    const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
+    int n0;
+    const int base = gather_candidates(bins, boxes, rcut, cand, kMaxCand, scan_tmp, &n0);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     t.ncand = base < kMaxCand ? base : kMaxCand;
-    t.px = (float)(rx - ox);
-    t.py = (float)(ry - oy);
-    t.pz = (float)(rz - oz);
+    t.frame = point_frame(boxes, n0, rx, ry, rz);
     return t;
 }
 
@@ -93,7 +88,6 @@ __device__ __forceinline__ AceTile ace_tile(const BinState& bins, int Nx, int Ny
 __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned short (*nbr)[kTile], int my_n,
                                               int n_iter, const AceTile& tl, double rcut, int n, int lane,
                                               float2* __restrict__ dst) {
-    const float px = tl.px, py = tl.py, pz = tl.pz;
     const float rcf = (float)rcut;
     constexpr float kpi = 3.14159265358979323846f;
     constexpr float y00 = 0.28209479177387814f;            // 1 / sqrt(4 pi)
@@ -103,8 +97,10 @@ __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned
     ar[0] = (n & 1) ? -y00 : y00;                          // the grid point's own delta: T_n(-1) Y_0^0
     for (int s = 0; s < n_iter; ++s) {
         if (s >= my_n) continue;
-        const float4 q = cand[nbr[s][lane]];
-        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+        const int c = nbr[s][lane];
+        const float4 q = cand[c];
+        const float3 o = tl.frame.at(c);
+        const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float r = sqrtf(r2);
         // radial: T_n(x) fc(r) by the three-term recurrence
@@ -175,20 +171,7 @@ __global__ __launch_bounds__(64 * kAceWaves) void k_ace_proj(BinState bins, int 
     const AceTile tl = ace_tile(bins, Nx, Ny, Nz, rcut, pt_begin, n_pts, cand, scan_tmp, err);
     __syncthreads();
     // per-point neighbour lists (wave 0), in candidate order
-    const float rcf = (float)rcut;
-    if (wave == 0) {
-        int cnt = 0;
-        for (int c = 0; c < tl.ncand; ++c) {
-            const float4 q = cand[c];
-            const float dx = q.x - tl.px, dy = q.y - tl.py, dz = q.z - tl.pz;
-            if (dx * dx + dy * dy + dz * dz < rcf * rcf) {
-                if (cnt < kMaxNbr) nbr[cnt][lane] = (unsigned short)c;
-                ++cnt;
-            }
-        }
-        if (cnt > kMaxNbr) atomicOr(err, kErrNbr);
-        nnbr[lane] = tl.valid ? (cnt < kMaxNbr ? cnt : kMaxNbr) : 0;
-    }
+    if (wave == 0) build_neighbour_lists(cand, tl.ncand, tl.frame, (float)rcut, tl.valid, lane, nbr, nnbr, err);
     __syncthreads();
     const int my_n = nnbr[lane];
     const int n_iter = wave_max_int(my_n);

@@ -185,33 +185,18 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
     const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
                  rz = (double)pk * bins.L[2] / Nz;
     const int64_t p0 = pt_begin + tile * kTile;
-    const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
-    const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
-                 oz = (double)qk * bins.L[2] / Nz;
     const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
-    const double org[3] = {ox, oy, oz};
 
-    const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
+    int n0;
+    const int base = gather_candidates(bins, boxes, rcut, cand, kMaxCand, scan_tmp, &n0);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     for (int c = threadIdx.x; c < ncand; c += blockDim.x) cgrad[c][0] = cgrad[c][1] = cgrad[c][2] = 0.f;
     __syncthreads();
 
-    const float px = (float)(rx - ox), py = (float)(ry - oy), pz = (float)(rz - oz);
+    const PointFrame frame = point_frame(boxes, n0, rx, ry, rz);
     const float rcf = (float)rcut;
-    if (wave == 0) {
-        int cnt = 0;
-        for (int c = 0; c < ncand; ++c) {
-            const float4 q = cand[c];
-            const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
-            if (dx * dx + dy * dy + dz * dz < rcf * rcf) {
-                if (cnt < kMaxNbr) nbr[cnt][lane] = (unsigned short)c;
-                ++cnt;
-            }
-        }
-        if (cnt > kMaxNbr) atomicOr(err, kErrNbr);
-        nnbr[lane] = valid ? (cnt < kMaxNbr ? cnt : kMaxNbr) : 0;
-    }
+    if (wave == 0) build_neighbour_lists(cand, ncand, frame, rcf, valid, lane, nbr, nnbr, err);
     __syncthreads();
 
     const float2* yt = y_in + tile * NH * kTile + lane;
@@ -229,7 +214,8 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
             const bool act = s < nn;
             const int c = act ? nbr[s][lane] : 0;
             const float4 q = cand[c];
-            const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+            const float3 o = frame.at(c);
+            const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const bool on = act && r2 > 0.f;       // an atom on the point has no derivative: left out
             const float r = on ? sqrtf(r2) : 1.f;

@@ -167,35 +167,20 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
     const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
                  rz = (double)pk * bins.L[2] / Nz;
     const int64_t p0 = pt_begin + tile * kTile;
-    const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
-    const double ox = (double)qi * bins.L[0] / Nx, oy = (double)qj * bins.L[1] / Ny,
-                 oz = (double)qk * bins.L[2] / Nz;
-    // bounding box of the tile's points
+    // bounding boxes of the tile's points
     const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
-    const double org[3] = {ox, oy, oz};
 
-    // ---- candidate atom images within rcut of the box, in a fixed order
-    const int base = gather_candidates(bins, boxes, org, rcut, cand, kMaxCand, scan_tmp);
+    // ---- candidate atom images within rcut of the boxes, in a fixed order
+    int n0;
+    const int base = gather_candidates(bins, boxes, rcut, cand, kMaxCand, scan_tmp, &n0);
     if (base > kMaxCand && threadIdx.x == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     __syncthreads();
 
     // ---- per-point neighbour lists (wave 0), in candidate order
-    const float px = (float)(rx - ox), py = (float)(ry - oy), pz = (float)(rz - oz);
+    const PointFrame frame = point_frame(boxes, n0, rx, ry, rz);
     const float rcf = (float)rcut;
-    if (wave == 0) {
-        int cnt = 0;
-        for (int c = 0; c < ncand; ++c) {
-            const float4 q = cand[c];
-            const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
-            if (dx * dx + dy * dy + dz * dz < rcf * rcf) {
-                if (cnt < kMaxNbr) nbr[cnt][lane] = (unsigned short)c;
-                ++cnt;
-            }
-        }
-        if (cnt > kMaxNbr) atomicOr(err, kErrNbr);
-        nnbr[lane] = valid ? (cnt < kMaxNbr ? cnt : kMaxNbr) : 0;
-    }
+    if (wave == 0) build_neighbour_lists(cand, ncand, frame, rcf, valid, lane, nbr, nnbr, err);
     __syncthreads();
 
     // ---- expansion coefficients, this wave's chain group
@@ -214,8 +199,10 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
         for (int s = 0; s < n_iter; ++s) {
             float ar = 1.f, ai = 0.f, br = 0.f, bi = 0.f, fc = 0.f;
             if (s < my_n) {
-                const float4 q = cand[nbr[s][lane]];
-                const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+                const int c = nbr[s][lane];
+                const float4 q = cand[c];
+                const float3 o = frame.at(c);
+                const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
                 const float r = sqrtf(dx * dx + dy * dy + dz * dz);
                 const float inv = r > 0.f ? 1.f / r : 0.f;
                 float sn, cs;

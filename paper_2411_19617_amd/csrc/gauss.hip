@@ -26,23 +26,27 @@ __global__ __launch_bounds__(64) void k_gauss(BinState bins, int Nx, int Ny, int
     const double rx = (double)pi * bins.L[0] / Nx, ry = (double)pj * bins.L[1] / Ny,
                  rz = (double)pk * bins.L[2] / Nz;
     const int64_t p0 = pt_begin + tile * kTile;
-    const int64_t qk = p0 % Nz, qj = (p0 / Nz) % Ny, qi = p0 / ((int64_t)Ny * Nz);
-    const double org[3] = {(double)qi * bins.L[0] / Nx, (double)qj * bins.L[1] / Ny, (double)qk * bins.L[2] / Nz};
     const TileBoxes boxes = tile_boxes(p, p0, Ny, Nz, rx, ry, rz);
-    const int base = gather_candidates(bins, boxes, org, cutoff, cand, kMaxCand, scan_tmp);
+    int n0;
+    const int base = gather_candidates(bins, boxes, cutoff, cand, kMaxCand, scan_tmp, &n0);
     if (base > kMaxCand && lane == 0) atomicOr(err, kErrCand);
     const int ncand = base < kMaxCand ? base : kMaxCand;
     __syncthreads();
 
-    const float px = (float)(rx - org[0]), py = (float)(ry - org[1]), pz = (float)(rz - org[2]);
+    const PointFrame frame = point_frame(boxes, n0, rx, ry, rz);
     const float rc2 = (float)(cutoff * cutoff);
     float acc = 0.f;
-    for (int c = 0; c < ncand; ++c) {
-        const float4 q = cand[c];
-        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
-        const float d2 = dx * dx + dy * dy + dz * dz;
-        if (d2 < rc2) acc += expf(-a * d2);
-    }
+    auto scan = [&](int c0, int c1, float3 o) {
+        for (int c = c0; c < c1; ++c) {
+            const float4 q = cand[c];
+            const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
+            const float d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < rc2) acc += expf(-a * d2);
+        }
+    };
+    const int split = n0 < ncand ? n0 : ncand;
+    scan(0, split, frame.p0);
+    scan(split, ncand, frame.p1);
     if (valid) out[idx] = (float)(norm * (double)acc);
 }
 

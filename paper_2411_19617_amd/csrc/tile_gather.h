@@ -78,9 +78,10 @@ __device__ __forceinline__ bool near_box(const double lo[3], const double hi[3],
 // One pass of the candidate gather: every image in the cells overlapping box
 // `k` grown by rcut that lies within rcut of that box (and, for k = 1, not
 // within rcut of box 0, whose pass took it already), appended after `base`
-// in a fixed order (cells in index order, atoms in cell order).
-__device__ __forceinline__ int gather_pass(const BinState& bins, const TileBoxes& tb, int k, const double o[3],
-                                           double rcut, float4* cand, int cap, int* scan_tmp, int base) {
+// in a fixed order (cells in index order, atoms in cell order), relative to
+// the box's lower corner.
+__device__ __forceinline__ int gather_pass(const BinState& bins, const TileBoxes& tb, int k, double rcut,
+                                           float4* cand, int cap, int* scan_tmp, int base) {
     const double rc2 = rcut * rcut;
     const double* lo = tb.lo[k];
     const double* hi = tb.hi[k];
@@ -119,7 +120,7 @@ __device__ __forceinline__ int gather_pass(const BinState& bins, const TileBoxes
             const double X = at.x + sx, Y = at.y + sy, Z = at.z + sz;
             if (near_box(lo, hi, X, Y, Z, rc2) && !(k == 1 && near_box(tb.lo[0], tb.hi[0], X, Y, Z, rc2))) {
                 if (off < cap)
-                    cand[off] = make_float4((float)(X - o[0]), (float)(Y - o[1]), (float)(Z - o[2]),
+                    cand[off] = make_float4((float)(X - lo[0]), (float)(Y - lo[1]), (float)(Z - lo[2]),
                                             __int_as_float((int)at.w));
                 ++off;
             }
@@ -130,15 +131,60 @@ __device__ __forceinline__ int gather_pass(const BinState& bins, const TileBoxes
 }
 
 // Candidate atom images of a tile with boxes `tb`: every image within rcut
-// of one of its boxes, each once, stored relative to the origin o as float4
-// in cand[0 .. cap) (w holds the bits of the atom's index).  Called by the
-// whole block; returns the total count, which exceeds cap when the list
-// overflowed (only the first cap are stored).  scan_tmp holds blockDim/64 ints.
-__device__ __forceinline__ int gather_candidates(const BinState& bins, const TileBoxes& tb, const double o[3],
-                                                 double rcut, float4* cand, int cap, int* scan_tmp) {
-    int base = gather_pass(bins, tb, 0, o, rcut, cand, cap, scan_tmp, 0);
-    if (tb.n == 2) base = gather_pass(bins, tb, 1, o, rcut, cand, cap, scan_tmp, base);
+// of one of its boxes, each once, as float4 in cand[0 .. cap) (w holds the
+// bits of the atom's index).  Box 0's pass comes first and is stored
+// relative to box 0's lower corner; box 1's pass, from index *n0 on, relative
+// to box 1's, so that offsets stay as small as the boxes (a tile crossing a
+// row spans the cell).  Called by the whole block; returns the total count,
+// which exceeds cap when the list overflowed (only the first cap are
+// stored).  scan_tmp holds blockDim/64 ints.
+__device__ __forceinline__ int gather_candidates(const BinState& bins, const TileBoxes& tb, double rcut,
+                                                 float4* cand, int cap, int* scan_tmp, int* n0) {
+    int base = gather_pass(bins, tb, 0, rcut, cand, cap, scan_tmp, 0);
+    *n0 = base;
+    if (tb.n == 2) base = gather_pass(bins, tb, 1, rcut, cand, cap, scan_tmp, base);
     return base;
+}
+
+// A lane's point relative to the two origins its candidates are stored
+// against: candidate c is compared with at(c).
+struct PointFrame {
+    float3 p0, p1;
+    int n0;
+    __device__ __forceinline__ float3 at(int c) const { return c < n0 ? p0 : p1; }
+};
+
+__device__ __forceinline__ PointFrame point_frame(const TileBoxes& tb, int n0, double rx, double ry, double rz) {
+    PointFrame f;
+    f.p0 = make_float3((float)(rx - tb.lo[0][0]), (float)(ry - tb.lo[0][1]), (float)(rz - tb.lo[0][2]));
+    f.p1 = tb.n == 2 ? make_float3((float)(rx - tb.lo[1][0]), (float)(ry - tb.lo[1][1]), (float)(rz - tb.lo[1][2]))
+                     : f.p0;
+    f.n0 = n0;
+    return f;
+}
+
+// Wave 0's per-point neighbour lists: the indices of the candidates within
+// rc of the lane's point, in candidate order, at most kMaxNbr (more sets
+// kErrNbr in *err); invalid lanes get empty lists.
+__device__ __forceinline__ void build_neighbour_lists(const float4* cand, int ncand, const PointFrame& f, float rc,
+                                                      bool valid, int lane, unsigned short (*nbr)[kTile],
+                                                      int* nnbr, int* err) {
+    int cnt = 0;
+    const int split = f.n0 < ncand ? f.n0 : ncand;
+    auto scan = [&](int c0, int c1, float3 p) {
+        for (int c = c0; c < c1; ++c) {
+            const float4 q = cand[c];
+            const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+            if (dx * dx + dy * dy + dz * dz < rc * rc) {
+                if (cnt < kMaxNbr) nbr[cnt][lane] = (unsigned short)c;
+                ++cnt;
+            }
+        }
+    };
+    scan(0, split, f.p0);
+    scan(split, ncand, f.p1);
+    if (cnt > kMaxNbr) atomicOr(err, kErrNbr);
+    nnbr[lane] = valid ? (cnt < kMaxNbr ? cnt : kMaxNbr) : 0;
 }
 
 }  // namespace mala
