@@ -13,7 +13,7 @@
 // column = 4 units per lane group) and the result writes conflict-free,
 // where a stride of 4, 12, 16 or 36 (mod 64) costs 4 extra cycles per read
 // (measured with the SQ_LDS_BANK_CONFLICT counter).  Layer 2 is
-// produced eight M-tiles at a time and consumed by layer 3 at once.
+// produced a chunk of M-tiles at a time and consumed by layer 3 at once.
 //
 // Epilogues:
 //   LDOS       d = out_scale*y + out_shift stored as float32 [n][n_e]
@@ -28,6 +28,19 @@
 #include "mlp_core.h"
 
 namespace mala {
+
+// M-tiles a wave computes at once (each LDS activation operand then feeds MB
+// MFMAs): BF16 reads four times more LDS bytes per MFMA flop than FP32 (a
+// 16x16x32 operand is 16 B per lane against 4 B for 16x16x4 at twice the
+// flops), so it takes two; FP32 stays at one, which measured faster there.
+template <int PREC>
+constexpr int mlp_mb() { return PREC == 1 ? 2 : 1; }
+// M-tiles of layer 2 held in LDS at once: BF16 keeps the whole layer (half
+// the bytes of FP32), so layer 3 runs once after it with no accumulators
+// live during layer 2; FP32 produces it kWaves M-tiles at a time, each chunk
+// consumed by layer 3 at once.
+template <int PREC>
+inline __host__ __device__ int mlp_h2_chunk(const MlpArgs& a) { return PREC == 1 ? a.h2_tiles : kWaves; }
 
 template <int PREC, int MODE, int NT>
 __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __restrict__ B, int64_t n_pts,
@@ -50,9 +63,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
         lo = o.win->lo;
         W = o.win->valid ? o.win->hi - o.win->lo + 1 : 0;
     }
-    const int xs = P::stride(a.in_pad), hs = P::stride(a.h1_tiles * 16), cs = P::stride(128);
+    constexpr int MB = mlp_mb<PREC>();
+    const int CH = mlp_h2_chunk<PREC>(a);
+    const int xs = P::stride(a.in_pad), hs = P::stride(a.h1_tiles * 16), cs = P::stride(16 * CH);
     T* H1 = reinterpret_cast<T*>(smem);
-    T* X0 = H1 + NP * hs;          // layer-1 input, later the layer-2 chunk
+    T* X0 = H1 + NP * hs;          // layer-1 input, later layer 2 (or its chunk)
     T* H2 = X0;
 
     if constexpr (MODE == kModeDensity || MODE == kModeDosWindow) {
@@ -114,32 +129,71 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
             }
         }
         __syncthreads();
-        layer<PREC, NT>(a.W1, a.b1, a.h1_tiles, 0, KS1, X0, xs, H1, hs, a.slope, wave, lane);
+        layer<PREC, NT, MB>(a.W1, a.b1, a.h1_tiles, 0, KS1, X0, xs, H1, hs, a.slope, wave, lane);
         __syncthreads();
 
-        // layer 2 in chunks of 8 M-tiles, each consumed by layer 3 at once
         f4 acc3[2][NT];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int ot = wave + kWaves * i;
-            const f4 b = ot < a.out_tiles ? bias4(a.b3, 16 * ot + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int n = 0; n < NT; ++n) acc3[i][n] = b;
-        }
-        for (int c0 = 0; c0 < a.h2_tiles; c0 += 8) {
-            const int ct = (a.h2_tiles - c0) < 8 ? (a.h2_tiles - c0) : 8;
-            layer<PREC, NT>(a.W2, a.b2, ct, c0, KS2, H1, hs, H2, cs, a.slope, wave, lane);
+        if constexpr (PREC == 1) {
+            // the whole of layer 2, then layer 3 in one pass: each wave's two
+            // output tiles share every LDS operand when both exist
+            layer<PREC, NT, MB>(a.W2, a.b2, a.h2_tiles, 0, KS2, H1, hs, H2, cs, a.slope, wave, lane);
             __syncthreads();
-            const int ks0 = c0 * 16 / P::K, ksn = ct * 16 / P::K;
-            const T* rows[NT];
+            auto init3 = [&]() {
 #pragma unroll
-            for (int n = 0; n < NT; ++n) rows[n] = H2 + (16 * n + j) * cs;
+                for (int i = 0; i < 2; ++i) {
+                    const int ot = wave + kWaves * i;
+                    const f4 b = ot < a.out_tiles ? bias4(a.b3, 16 * ot + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) acc3[i][n] = b;
+                }
+            };
+            auto layer3 = [&](int ks0, int ksn) {
+                const T* rows[NT];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) rows[n] = H2 + (16 * n + j) * cs;
+                bool both = false;
+                if (wave + kWaves < a.out_tiles) {
+                    const size_t bases[2] = {((size_t)wave * KS3 + ks0) * 64 + lane,
+                                             ((size_t)(wave + kWaves) * KS3 + ks0) * 64 + lane};
+                    kloop_mn<PREC, 2, NT>(a.W3, bases, ksn, rows, g, acc3);
+                    both = true;
+                }
+                if (!both) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int ot = wave + kWaves * i;
+                        if (ot < a.out_tiles)
+                            kloop<PREC, NT>(a.W3, ((size_t)ot * KS3 + ks0) * 64 + lane, ksn, rows, g, acc3[i]);
+                    }
+                }
+            };
+            init3();
+            layer3(0, KS3);
+            __syncthreads();
+        } else {
+            // layer 2 in chunks of CH M-tiles, each consumed by layer 3 at once
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int ot = wave + kWaves * i;
-                if (ot < a.out_tiles) kloop<PREC, NT>(a.W3, ((size_t)ot * KS3 + ks0) * 64 + lane, ksn, rows, g, acc3[i]);
+                const f4 b = ot < a.out_tiles ? bias4(a.b3, 16 * ot + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc3[i][n] = b;
             }
-            __syncthreads();
+            for (int c0 = 0; c0 < a.h2_tiles; c0 += CH) {
+                const int ct = (a.h2_tiles - c0) < CH ? (a.h2_tiles - c0) : CH;
+                layer<PREC, NT, MB>(a.W2, a.b2, ct, c0, KS2, H1, hs, H2, cs, a.slope, wave, lane);
+                __syncthreads();
+                const int ks0 = c0 * 16 / P::K, ksn = ct * 16 / P::K;
+                const T* rows[NT];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) rows[n] = H2 + (16 * n + j) * cs;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int ot = wave + kWaves * i;
+                    if (ot < a.out_tiles) kloop<PREC, NT>(a.W3, ((size_t)ot * KS3 + ks0) * 64 + lane, ksn, rows, g, acc3[i]);
+                }
+                __syncthreads();
+            }
         }
 
         // ---- epilogue
@@ -226,7 +280,7 @@ template <int PREC, int NT>
 static size_t lds_bytes(const MlpArgs& a) {
     using P = Prec<PREC>;
     const size_t el = PREC == 0 ? 4 : 2;
-    const size_t x = (size_t)std::max(P::stride(a.in_pad), P::stride(128));
+    const size_t x = (size_t)std::max(P::stride(a.in_pad), P::stride(16 * mlp_h2_chunk<PREC>(a)));
     return el * 16 * NT * ((size_t)P::stride(a.h1_tiles * 16) + x);
 }
 

@@ -88,33 +88,44 @@ struct Prec<1> {
     __device__ static T cvt(float x) { return (__bf16)x; }
 };
 
-// acc[n] += sum over K-steps s < KS of A(s) B_n(s), in batches of PF K-steps
-// (KS is a multiple of PF).  Weights (from L2) are fetched DA batches ahead
-// into a ring of DA+1 register sets, LDS operands one batch ahead into a
-// ring of two; the loop is unrolled by a multiple of both ring sizes so the
-// sets rotate by name: no register copies and no wait on a load issued in
-// the same batch.  Within a batch the MFMAs go K-step by K-step over the NA
-// independent accumulators.
-template <int PREC, int NA>
-__device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const typename Prec<PREC>::T* const (&rows)[NA],
-                                      int g, f4 (&acc)[NA]) {
+// acc[m][n] += sum over K-steps s < KS of A_m(s) B_n(s), in batches of PF
+// K-steps (KS is a multiple of PF): MB weight tiles (A_m at base[m]) against
+// NA point tiles, so every weight operand feeds NA MFMAs and every LDS
+// operand MB.  Weights (from L2) are fetched DA batches ahead into a ring of
+// DA+1 register sets, LDS operands one batch ahead into a ring of two; the
+// loop is unrolled by a multiple of both ring sizes so the sets rotate by
+// name: no register copies and no wait on a load issued in the same batch.
+// Within a batch the MFMAs go K-step by K-step over the MB x NA independent
+// accumulators.  An MB-fold batch is MB times longer, so fewer batches ahead
+// cover the same L2 latency.
+template <int PREC, int MB, int NA>
+__device__ __forceinline__ void kloop_mn(const void* A, const size_t (&base)[MB], int KS,
+                                         const typename Prec<PREC>::T* const (&rows)[NA], int g,
+                                         f4 (&acc)[MB][NA]) {
     using P = Prec<PREC>;
     using BA = typename P::BatchA;
     using BB = typename P::BatchB;
-    constexpr int RA = P::DA + 1;
+    constexpr int DA = (P::DA + MB - 1) / MB;
+    constexpr int RA = DA + 1;
     constexpr int U = RA % 2 == 0 ? RA : 2 * RA;
     const int NQ = KS / P::PF;
-    BA a[RA];
+    BA a[RA][MB];
     BB b[2][NA];
+    auto fetchA = [&](int q, BA (&ad)[MB]) {
+#pragma unroll
+        for (int m = 0; m < MB; ++m) P::loadA(ad[m], A, base[m], q);
+    };
     auto fetchB = [&](int q, BB (&bd)[NA]) {
 #pragma unroll
         for (int n = 0; n < NA; ++n) P::loadB(bd[n], rows[n], q, g);
     };
-    auto mma = [&](const BA& as, const BB (&bs)[NA]) {
+    auto mma = [&](const BA (&as)[MB], const BB (&bs)[NA]) {
         static_for<0, P::PF>([&](auto sc) {
             constexpr int S = decltype(sc)::value;
 #pragma unroll
-            for (int n = 0; n < NA; ++n) acc[n] = P::template mma_step<S>(as, bs[n], acc[n]);
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int n = 0; n < NA; ++n) acc[m][n] = P::template mma_step<S>(as[m], bs[n], acc[m][n]);
         });
     };
     // batch q + u (u < U) lives in a[u % RA] and b[u % 2].  Prefetches past
@@ -122,16 +133,16 @@ __device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const 
     // unconditional, so the waits count exactly the loads still needed.
     auto step = [&](int q, auto uc) {
         constexpr int u = decltype(uc)::value;
-        const int qa = q + u + P::DA < NQ ? q + u + P::DA : NQ - 1;
+        const int qa = q + u + DA < NQ ? q + u + DA : NQ - 1;
         const int qb = q + u + 1 < NQ ? q + u + 1 : NQ - 1;
-        P::loadA(a[(u + P::DA) % RA], A, base, qa);
+        fetchA(qa, a[(u + DA) % RA]);
         fetchB(qb, b[(u + 1) % 2]);
         mma(a[u % RA], b[u % 2]);
     };
     if (NQ <= 0) return;
-    static_for<0, P::DA>([&](auto ic) {
+    static_for<0, DA>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        P::loadA(a[i], A, base, i < NQ ? i : NQ - 1);
+        fetchA(i < NQ ? i : NQ - 1, a[i]);
     });
     fetchB(0, b[0]);
     int q = 0;
@@ -141,18 +152,61 @@ __device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const 
     });
 }
 
-// One dense layer on the waves of the block: out[p][16 mt + u] = act(W x + b).
-// in: LDS rows (stride is), out: LDS rows (stride os) at column offset out_col
-// for tile mt (out_col(mt) = 16 * (mt - tile_base)).
-template <int PREC, int NT>
+// One weight tile against NA point tiles.
+template <int PREC, int NA>
+__device__ __forceinline__ void kloop(const void* A, size_t base, int KS, const typename Prec<PREC>::T* const (&rows)[NA],
+                                      int g, f4 (&acc)[NA]) {
+    const size_t bases[1] = {base};
+    f4 acc1[1][NA];
+#pragma unroll
+    for (int n = 0; n < NA; ++n) acc1[0][n] = acc[n];
+    kloop_mn<PREC, 1, NA>(A, bases, KS, rows, g, acc1);
+#pragma unroll
+    for (int n = 0; n < NA; ++n) acc[n] = acc1[0][n];
+}
+
+// One dense layer on the waves of the block: out[p][16 mt + u] = act(W x + b)
+// for the M-tiles tile_base + mt, mt < tiles.  in: LDS rows (stride is), out:
+// LDS rows (stride os), column 16 mt.  With MB > 1 the waves first take MB
+// M-tiles each as long as every wave has a full set, then one each, then
+// the (M-tile, point-tile) items left over, so the waves stay balanced.
+template <int PREC, int NT, int MB = 1>
 __device__ __forceinline__ void layer(const void* W, const float* bias, int tiles, int tile_base, int KS,
                                       const typename Prec<PREC>::T* in, int is, typename Prec<PREC>::T* out,
                                       int os, float slope, int wave, int lane) {
     using P = Prec<PREC>;
     using T = typename P::T;
     const int j = lane & 15, g = lane >> 4;
-    const int full = (tiles / kWaves) * kWaves;
-    for (int mt = wave; mt < full; mt += kWaves) {
+    int done = 0;
+    if constexpr (MB > 1) {
+        const int fullm = (tiles / (kWaves * MB)) * kWaves * MB;
+        for (int r0 = 0; r0 < fullm; r0 += kWaves * MB) {
+            f4 acc[MB][NT];
+            size_t bases[MB];
+            const T* rows[NT];
+#pragma unroll
+            for (int n = 0; n < NT; ++n) rows[n] = in + (16 * n + j) * is;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const int mt = r0 + MB * wave + m;
+                const f4 b = bias4(bias, 16 * (tile_base + mt) + 4 * g);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[m][n] = b;
+                bases[m] = (size_t)(tile_base + mt) * KS * 64 + lane;
+            }
+            kloop_mn<PREC, MB, NT>(W, bases, KS, rows, g, acc);
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const int mt = r0 + MB * wave + m;
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    P::store4(out + (16 * n + j) * os + 16 * mt + 4 * g, act4(acc[m][n], slope));
+            }
+        }
+        done = fullm;
+    }
+    const int full = done + ((tiles - done) / kWaves) * kWaves;
+    for (int mt = done + wave; mt < full; mt += kWaves) {
         f4 acc[NT];
         const f4 b = bias4(bias, 16 * (tile_base + mt) + 4 * g);
         const T* rows[NT];
