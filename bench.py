@@ -355,12 +355,16 @@ def counter_summary(out_name, command, dirs):
     import glob
     import re
     acc = {}
+    pmc = {}                                            # counters of each run, in the order they appear
     for d in dirs:
         files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
         if not files:
             raise SystemExit("no counter_collection.csv under %s" % d)
         for f in files:
             for r in csv.DictReader(open(f)):
+                names = pmc.setdefault(d, [])
+                if r["Counter_Name"] not in names:
+                    names.append(r["Counter_Name"])
                 name = _short_kernel_name(r["Kernel_Name"])
                 key = next((k for k in COUNTER_KERNELS if name.startswith(k)), None)
                 if key is None:
@@ -372,13 +376,17 @@ def counter_summary(out_name, command, dirs):
                 c[(d, r["Dispatch_Id"])] = c.get((d, r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
     lines = ["# rocprofv3 counters per kernel", "", "Commands (repository root = $REPO, output directory $OUT, "
              "after `cd /tmp && export TMPDIR=/tmp`; one counter set per run):", "", "```"]
-    lines += [command.replace("{DIR}", os.path.basename(os.path.normpath(d)).replace("pmc_", "")) for d in dirs]
+    lines += [command.replace("{DIR}", os.path.basename(os.path.normpath(d)).replace("pmc_", ""))
+              .replace("{PMC}", " ".join(pmc.get(d, []))) for d in dirs]
     lines += ["```", "", "Counter sums over the kernel's dispatches of each run; derived ratios use the dispatch "
               "times of the same runs (counter collection serialises dispatches).  GRBM_GUI_ACTIVE is read as "
               "the sum over the 8 XCDs (its per-dispatch value divided by 8 x the dispatch time gives the clock).  "
               "VALU issue = SQ_INSTS_VALU x 4 cycles / (1,024 SIMDs x cycles); MFMA busy = "
               "SQ_VALU_MFMA_BUSY_CYCLES / (1,024 SIMDs x cycles); LDS conflict = SQ_LDS_BANK_CONFLICT / "
-              "SQ_LDS_IDX_ACTIVE.", ""]
+              "SQ_LDS_IDX_ACTIVE; wait share = SQ_WAIT_ANY / SQ_WAVE_CYCLES (wave cycles spent in a wait); "
+              "L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS).  SQ_INSTS_VALU includes the MFMA instructions "
+              "(SQ_INSTS_MFMA), so for the network kernels the VALU issue figure counts their issue "
+              "slots too.  Ratios of two counters use only the runs that collected both.", ""]
     names = sorted(acc)
     counters = sorted({c for n in names for c in acc[n]["counters"]})
     lines += ["| kernel | dispatches | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
@@ -393,12 +401,19 @@ def counter_summary(out_name, command, dirs):
             row.append("%.4g" % tot[c] if v else "")
         lines.append("| " + " | ".join(row) + " |")
         # derived ratios per run that holds the needed counters
-        def per(c):
+        def per(c, runs=None):
             v = a["counters"].get(c)
             if not v:
                 return None
-            keys = list(v)
-            return sum(v.values()), sum(a["dispatch"][k] for k in keys)
+            keys = [k for k in v if runs is None or k[0] in runs]
+            return sum(v[k] for k in keys), sum(a["dispatch"][k] for k in keys)
+
+        def same_run(c1, c2):
+            """Sums of two counters over the runs that collected both."""
+            r1 = {k[0] for k in a["counters"].get(c1, {})}
+            r2 = {k[0] for k in a["counters"].get(c2, {})}
+            runs = r1 & r2
+            return (per(c1, runs), per(c2, runs)) if runs else (None, None)
         g = per("GRBM_GUI_ACTIVE")
         d = {"kernel": n}
         if g and g[1] > 0:
@@ -409,18 +424,23 @@ def counter_summary(out_name, command, dirs):
             x = per(c)
             if x and x[1] > 0:
                 d[label] = x[0] * scale / (1024.0 * cyc_per_s * x[1])
-        x, y = per("SQ_INSTS_VALU_FMA_F32"), per("SQ_INSTS_VALU")
-        if x and y and y[0] > 0 and x[1] == y[1]:
-            d["fma_share_of_valu"] = x[0] / y[0]
-        x, y = per("SQ_LDS_BANK_CONFLICT"), per("SQ_LDS_IDX_ACTIVE")
-        if x and y and y[0] > 0:
-            d["lds_conflict_share"] = x[0] / y[0]
-        x, y = per("SQ_INSTS_LDS"), per("SQ_INSTS_VALU")
-        if x and y and y[0] > 0 and x[1] == y[1]:
-            d["lds_per_valu"] = x[0] / y[0]
+        for num, den, label in (("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU", "fma_share_of_valu"),
+                                ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "lds_conflict_share"),
+                                ("SQ_INSTS_LDS", "SQ_INSTS_VALU", "lds_per_valu"),
+                                ("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "wait_share")):
+            x, y = same_run(num, den)
+            if x and y and y[0] > 0:
+                d[label] = x[0] / y[0]
+        x, y = same_run("TCC_HIT_sum", "TCC_MISS_sum")
+        if x and y and x[0] + y[0] > 0:
+            d["l2_hit"] = x[0] / (x[0] + y[0])
+        # the two come from different runs of the same program: compare per dispatch
+        x, y = a["counters"].get("SQ_INSTS_MFMA"), a["counters"].get("SQ_INSTS_VALU")
+        if x and y and sum(y.values()) > 0:
+            d["mfma_share_of_valu"] = (sum(x.values()) / len(x)) / (sum(y.values()) / len(y))
         derived.append(d)
-    keys = ["clock_GHz", "ms_per_dispatch", "valu_issue", "fma_share_of_valu", "lds_per_valu", "mfma_busy",
-            "lds_conflict_share"]
+    keys = ["clock_GHz", "ms_per_dispatch", "valu_issue", "mfma_share_of_valu", "fma_share_of_valu", "lds_per_valu",
+            "mfma_busy", "lds_conflict_share", "wait_share", "l2_hit"]
     lines += ["", "| kernel | " + " | ".join(keys) + " |", "|---|" + "---|" * len(keys)]
     for d in derived:
         lines.append("| `%s` | " % d["kernel"] + " | ".join("%.3f" % d[k] if k in d else "" for k in keys) + " |")
