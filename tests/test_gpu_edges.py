@@ -62,6 +62,47 @@ def test_generic_network_shape(env, prec, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 3e-2)])
+def test_network_at_maximum_widths(env, prec, tol):
+    """The widest network the build takes (128 inputs, hidden layers of 512,
+    256 outputs): the FP32 network falls back to 32-point tiles there (its
+    activations would not fit beside the epilogue at 64) and the BF16 one runs
+    at its largest LDS footprint."""
+    mala, ctx, torch = env
+    eg = (-5.0, 0.1, 256)
+    net = mala_synth.make_net([128, 512, 512, 256], 11, 8, egrid=eg, with_input_scaler=False)
+    B, _ = mala_synth.network_inputs(net, 300, 12)
+    w = ctx.weights(mala_synth.net_to_blob(net), prec)
+    ld = ctx.mala_ldos_infer(w, torch.as_tensor(B, device="cuda"), 256).cpu().double().numpy()
+    err = rel_rows(ld, oracle.mlp(B.astype(np.float64), net))
+    log("maximum widths prec", prec, "LDOS rel err", err)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_predict_at_maximum_widths(env, prec):
+    """The fused path (DOS, energy window, density) with hidden layers of 512
+    and 256 energies, on the whole 8,000-point grid against the oracle."""
+    mala, ctx, torch = env
+    s = mala_synth.small()
+    eg = (-5.0, 0.1, 256)
+    net = mala_synth.make_net([55, 512, 512, 256], 13, 8, egrid=eg)
+    ref = oracle.predict(s, net, eg)
+    w = ctx.weights(mala_synth.net_to_blob(net), prec)
+    dos, dens, res = ctx.mala_predict(w, s.positions, s.L, s.N, s.rcut, s.twojmax, eg, s.T, s.n_electrons)
+    r = mala.read_result(res)
+    assert r["status"] == 0
+    d_err = float(np.max(np.abs(dos.cpu().numpy() - ref["dos"])) / np.max(np.abs(ref["dos"])))
+    ef_err = abs(r["e_fermi"] - ref["e_fermi"])
+    n = dens.cpu().numpy()
+    n_err = float(np.max(np.abs(n - ref["density"])) / np.max(np.abs(ref["density"])))
+    log("maximum widths predict prec", prec, "DOS %.2e E_F %.2e eV density %.2e" % (d_err, ef_err, n_err))
+    if prec == 0:
+        assert d_err <= 1e-5 and ef_err <= 1e-5 and n_err <= 1e-5
+    else:
+        assert d_err <= 5e-2 and ef_err <= 5e-2 and n_err <= 5e-2
+
+
 def test_predict_no_root_leaves_density(env):
     mala, ctx, torch = env
     s, net = mala_synth.small(), mala_synth.small_net()
