@@ -16,6 +16,7 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<f
 constexpr int kAce4MaxN = 3;
 constexpr int kAce4MaxL = 3;
 constexpr size_t kAce4LdsBudget = 96 * 1024;     // dynamic LDS of the pair vectors of one L
+constexpr int kAce4MaxDescsL = 512;               // descriptors of one L (364 at nmax4 = lmax4 = 3)
 int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc);
 int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
                       std::vector<float>& coef, std::vector<int>& l_descs, std::vector<int4>& descs,

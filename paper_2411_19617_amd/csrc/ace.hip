@@ -387,6 +387,7 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
                                                           const int4* __restrict__ descs, int n4,
                                                           float* __restrict__ out, int64_t ps, int64_t ds) {
     __shared__ float2 sA[kAceN * kAceLm][kTile];
+    __shared__ int4 sD[kAce4MaxDescsL];     // this L's descriptor entries
     extern __shared__ float2 sP[];          // [slots][kTile]
 
     const int lane = threadIdx.x & 63;
@@ -399,6 +400,11 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
 
     float* o = out + (tl.valid ? tl.idx : 0) * ps;    // descriptor k at o[k * ds]
     for (int L = 0; L <= 2 * lmax4; ++L) {
+        // this L's descriptor entries into LDS, read back as broadcasts: a
+        // scalar load per descriptor would hold every LDS wait of the loop
+        // below until the scalar cache answered
+        const int d0 = l_descs[L], nd = l_descs[L + 1] - d0;
+        for (int i = threadIdx.x; i < nd; i += blockDim.x) sD[i] = descs[d0 + i];
         // coupled pairs of this L into sP
         const int u0 = l_units[L], u1 = l_units[L + 1];
         for (int u = u0 + wave; u < u1; u += kAce4Waves) {
@@ -416,12 +422,11 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
         }
         __syncthreads();
         // this L's descriptors, a contiguous share per wave
-        const int d0 = l_descs[L], nd = l_descs[L + 1] - d0;
-        const int db = d0 + nd * wave / kAce4Waves, de = d0 + nd * (wave + 1) / kAce4Waves;
+        const int db = nd * wave / kAce4Waves, de = nd * (wave + 1) / kAce4Waves;
         int cached = -1;
         float2 pa[2 * kAce4MaxL + 1];
         for (int d = db; d < de; ++d) {
-            const int4 q = descs[d];
+            const int4 q = sD[d];
             const int sa = __builtin_amdgcn_readfirstlane(q.x), sb = __builtin_amdgcn_readfirstlane(q.y);
             const int ok = __builtin_amdgcn_readfirstlane(q.z);
             const float f = __int_as_float(__builtin_amdgcn_readfirstlane(q.w));

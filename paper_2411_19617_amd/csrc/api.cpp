@@ -982,6 +982,9 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
         t.n4 = build_ace4_tables(nmax4, lmax4, l_units, units, coef, l_descs, descs, t.max_slots);
         if ((size_t)t.max_slots * kTile * sizeof(float2) > kAce4LdsBudget)
             return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: pair vectors exceed the LDS budget");
+        for (size_t L = 0; L + 1 < l_descs.size(); ++L)
+            if (l_descs[L + 1] - l_descs[L] > kAce4MaxDescsL)
+                return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: more descriptors of one L than staged in LDS");
         c->n_allocs += 5;
         HIP_TRY(hipMalloc(&t.l_units, sizeof(int) * l_units.size()));
         HIP_TRY(hipMalloc(&t.units, sizeof(int4) * (units.size() ? units.size() : 1)));
