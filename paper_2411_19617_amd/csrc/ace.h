@@ -10,8 +10,10 @@ constexpr int kAceMaxN = 4;      // radial functions
 constexpr int kAceMaxL = 4;      // angular momentum
 
 inline int ace_count_ranks12(int nmax, int lmax) { return nmax + (lmax + 1) * nmax * (nmax + 1) / 2; }
-int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef,
-                     std::vector<int>& outputs);
+// rank-3 groups (p1, p2, l3): a header of kAceGroupInts ints each, its
+// outputs (A row base of n3 | descriptor position << 7, at most kAceN) inline
+constexpr int kAceGroupInts = 12;
+int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef);
 // rank 4: descriptor set (p1, p2, p3, p4, L per entry) and its evaluation tables
 constexpr int kAce4MaxN = 3;
 constexpr int kAce4MaxL = 3;
@@ -31,7 +33,7 @@ hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts
                        const int4* units, const float* coef, const int* l_descs, const int4* descs, int max_slots,
                        int n4, float* out, int64_t ps, int64_t ds);   // descriptor k of point p at out[p ps + k ds]
 hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64_t n_pts, const int* groups,
-                      int n_groups, const float* coef, const int* outputs, int n_desc, float* out, int64_t ps,
+                      int n_groups, const float* coef, int n_desc, float* out, int64_t ps,
                       int64_t ds);
 
 }  // namespace mala

@@ -244,7 +244,7 @@ __host__ __device__ constexpr bool ace3_combo_valid(int c) {
 __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restrict__ Ag, int nmax, int lmax,
                                                         int64_t n_pts, const int* __restrict__ groups,
                                                         int n_groups, const float* __restrict__ coef,
-                                                        const int* __restrict__ outputs, int n_desc,
+                                                        int n_desc,
                                                         float* __restrict__ out, int64_t ps, int64_t ds) {
     __shared__ float2 sA[kAceN * kAceLm][kTile];
     const int lane = threadIdx.x & 63;
@@ -277,23 +277,24 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
     // rank 3 by groups (p1, p2, l3): P(m3) once, then every n3 of the group
     // the next group's header is loaded while the current group is formed
     // (a wave past the last group re-reads group 0, unused)
-    auto header = [&](int gi, int (&h)[8]) {
-        const int* gr = groups + 8 * (gi < n_groups ? gi : 0);
+    // (its outputs come with it: no load between the group and its LDS reads)
+    auto header = [&](int gi, int (&h)[kAceGroupInts]) {
+        const int* gr = groups + kAceGroupInts * (gi < n_groups ? gi : 0);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) h[i] = gr[i];
+        for (int i = 0; i < kAceGroupInts; ++i) h[i] = gr[i];
     };
-    int nxt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int nxt[kAceGroupInts] = {};
     if (n_groups > 0) header(wave, nxt);
     for (int gi = wave; gi < n_groups; gi += kAce3Waves) {
-        int h[8];
+        int h[kAceGroupInts];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) h[i] = nxt[i];
+        for (int i = 0; i < kAceGroupInts; ++i) h[i] = nxt[i];
         header(gi + kAce3Waves, nxt);
         const float* cf = coef + __builtin_amdgcn_readfirstlane(h[0]);
         const int l3 = __builtin_amdgcn_readfirstlane(h[1]);
-        const int o0 = __builtin_amdgcn_readfirstlane(h[2]), oc = __builtin_amdgcn_readfirstlane(h[3]);
-        const int combo = __builtin_amdgcn_readfirstlane(h[4]);
-        const int b1 = __builtin_amdgcn_readfirstlane(h[5]), b2 = __builtin_amdgcn_readfirstlane(h[6]);
+        const int oc = __builtin_amdgcn_readfirstlane(h[2]);
+        const int combo = __builtin_amdgcn_readfirstlane(h[3]);
+        const int b1 = __builtin_amdgcn_readfirstlane(h[4]), b2 = __builtin_amdgcn_readfirstlane(h[5]);
         float pr[9], pim[9];
         static_for<0, 125>([&](auto cc) {
             constexpr int C = decltype(cc)::value;
@@ -301,8 +302,10 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
                 if (combo == C) ace3_group<C / 25, (C / 5) % 5, C % 5>(sA, b1, b2, lane, cf, pr, pim);
             }
         });
-        for (int k = 0; k < oc; ++k) {
-            const int ok = __builtin_amdgcn_readfirstlane(outputs[o0 + k]);
+        static_for<0, kAceN>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if (k >= oc) return;
+            const int ok = __builtin_amdgcn_readfirstlane(h[6 + k]);
             const int base3 = ok & 127;
             float v = 0.f;
             static_for<0, 9>([&](auto sc) {
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
                 }
             });
             if (valid) o[(n12 + (ok >> 7)) * ds] = v;
-        }
+        });
     }
 }
 
@@ -481,13 +484,13 @@ hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts
 }
 
 hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64_t n_pts, const int* groups,
-                      int n_groups, const float* coef, const int* outputs, int n_desc, float* out, int64_t ps,
+                      int n_groups, const float* coef, int n_desc, float* out, int64_t ps,
                       int64_t ds) {
     if (n_pts <= 0) return hipSuccess;
     if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAce3Waves), 0, s, Ag, nmax, lmax, n_pts, groups,
-                       n_groups, coef, outputs, n_desc, out, ps, ds);
+                       n_groups, coef, n_desc, out, ps, ds);
     return hipGetLastError();
 }
 

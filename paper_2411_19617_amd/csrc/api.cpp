@@ -103,7 +103,6 @@ struct AceTables {
     int n3 = 0, n_groups = 0;
     int* groups = nullptr;
     float* coef = nullptr;
-    int* outputs = nullptr;
 };
 
 }  // namespace
@@ -570,7 +569,6 @@ mala_status mala_destroy(mala_ctx* c) {
         for (auto& a : row) {
             if (a.groups) (void)hipFree(a.groups);
             if (a.coef) (void)hipFree(a.coef);
-            if (a.outputs) (void)hipFree(a.outputs);
         }
     for (auto& row : c->ace4)
         for (auto& a : row) {
@@ -887,9 +885,9 @@ mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n
 
 int32_t mala_ace_count(int32_t nmax, int32_t lmax) {
     if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL) return MALA_E_UNSUPPORTED;
-    std::vector<int> groups, outs;
+    std::vector<int> groups;
     std::vector<float> coef;
-    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, groups, coef, outs);
+    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, groups, coef);
 }
 
 mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
@@ -909,17 +907,15 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
     DeviceGuard g(c->device);
     AceTables& t = c->ace[nmax][lmax];
     if (!t.ready) {
-        std::vector<int> groups, outs;
+        std::vector<int> groups;
         std::vector<float> coef;
-        t.n3 = build_ace_tables(nmax, lmax, groups, coef, outs);
-        t.n_groups = (int)(groups.size() / 8);
-        c->n_allocs += 3;
+        t.n3 = build_ace_tables(nmax, lmax, groups, coef);
+        t.n_groups = (int)(groups.size() / kAceGroupInts);
+        c->n_allocs += 2;
         HIP_TRY(hipMalloc(&t.groups, sizeof(int) * (groups.size() ? groups.size() : 1)));
         HIP_TRY(hipMalloc(&t.coef, sizeof(float) * (coef.size() ? coef.size() : 1)));
-        HIP_TRY(hipMalloc(&t.outputs, sizeof(int) * (outs.size() ? outs.size() : 1)));
         HIP_TRY(hipMemcpy(t.groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t.coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(t.outputs, outs.data(), sizeof(int) * outs.size(), hipMemcpyHostToDevice));
         t.ready = true;
     }
     const int n_desc = ace_count_ranks12(nmax, lmax) + t.n3;
@@ -937,7 +933,7 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
         HIP_TRY(staged(c, MALA_STAGE_ACE, n, [&] {
             hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
             if (e != hipSuccess) return e;
-            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, t.groups, t.n_groups, t.coef, t.outputs, n_desc,
+            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, t.groups, t.n_groups, t.coef, n_desc,
                               out + off * ps, ps, ds);
         }));
     }

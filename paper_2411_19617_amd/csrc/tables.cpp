@@ -206,11 +206,9 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
 // descriptor's rank-3 position (bits 7 and up).  The 3j symbol comes from the
 // coupled states of couple(): (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3)
 // <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
-int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef,
-                     std::vector<int>& outputs) {
+int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef) {
     groups.clear();
     coef.clear();
-    outputs.clear();
     std::vector<Coupling> cache(25 * 25);
     std::vector<bool> have(cache.size(), false);
     auto three_j = [&](int l1, int l2, int l3, int m1, int m2, int m3) {
@@ -261,10 +259,12 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<f
                             coef.push_back((float)three_j(l1, l2, l3, m1, m2, m3));
                         }
                 }
-                const int g[8] = {block_of[combo], l3, (int)outputs.size(), (int)outs.size(), combo,
-                                  n1 * 15 + l1 * (l1 + 1) / 2, n2 * 15 + l2 * (l2 + 1) / 2, 0};
-                for (int i = 0; i < 8; ++i) groups.push_back(g[i]);
-                for (int o : outs) outputs.push_back(o);
+                // header: coefficient block, l3, output count, combination, the
+                // two A row bases, then the outputs (one per n3 <= nmax <= 4)
+                int g[kAceGroupInts] = {block_of[combo], l3, (int)outs.size(), combo,
+                                        n1 * 15 + l1 * (l1 + 1) / 2, n2 * 15 + l2 * (l2 + 1) / 2};
+                for (size_t i = 0; i < outs.size(); ++i) g[6 + i] = outs[i];
+                for (int i = 0; i < kAceGroupInts; ++i) groups.push_back(g[i]);
             }
     return nd;
 }
