@@ -91,6 +91,7 @@ __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned
     const float rcf = (float)rcut;
     constexpr float kpi = 3.14159265358979323846f;
     constexpr float y00 = 0.28209479177387814f;            // 1 / sqrt(4 pi)
+    const float k2 = 2.f / rcf, kcut = kpi / rcf;          // per unit distance, formed once
     float ar[kAceLm], ai[kAceLm];
 #pragma unroll
     for (int e = 0; e < kAceLm; ++e) ar[e] = ai[e] = 0.f;
@@ -102,10 +103,12 @@ __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned
         const float3 o = tl.frame.at(c);
         const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        const float r = sqrtf(r2);
+        // 1/r and r from one hardware reciprocal square root (about 1 ulp)
+        const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+        const float r = r2 * inv;
         // radial: T_n(x) fc(r) by the three-term recurrence
-        const float x = 2.f * r / rcf - 1.f;
-        const float fc = 0.5f * (cosf(kpi * r / rcf) + 1.f);
+        const float x = r * k2 - 1.f;
+        const float fc = 0.5f * (cosf(kcut * r) + 1.f);
         float t0 = 1.f, t1 = x;
         for (int k = 2; k <= n; ++k) {
             const float t2 = 2.f * x * t1 - t0;
@@ -117,7 +120,6 @@ __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned
             ar[0] += R * y00;
             continue;
         }
-        const float inv = 1.f / r;
         const float t = dz * inv, ur = dx * inv, ui = dy * inv;
         // Q_l^m(t) for l <= 4, m >= 0, and ((x + i y)/r)^m
         float Q[kAceLm];

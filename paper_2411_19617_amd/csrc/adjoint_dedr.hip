@@ -209,7 +209,7 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
         if (wave != G) return;
         constexpr float kpi = 3.14159265358979323846f;
         constexpr float kRfac0 = 0.99363f;
-        const float kth = kRfac0 * kpi / rcf;
+        const float kth = kRfac0 * kpi / rcf, kcut = kpi / rcf;     // per unit distance, formed once
         for (int s = 0; s < nmax; ++s) {
             const bool act = s < nn;
             const int c = act ? nbr[s][lane] : 0;
@@ -218,8 +218,9 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
             const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const bool on = act && r2 > 0.f;       // an atom on the point has no derivative: left out
-            const float r = on ? sqrtf(r2) : 1.f;
-            const float inv = 1.f / r;
+            // 1/r and r from one hardware reciprocal square root (about 1 ulp)
+            const float inv = on ? __builtin_amdgcn_rsqf(r2) : 1.f;
+            const float r = on ? r2 * inv : 1.f;
             const float n[3] = {dx * inv, dy * inv, dz * inv};
             float sn, cs;
             sincosf(kth * r, &sn, &cs);
@@ -227,8 +228,8 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
             float A[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gu = 0.f;
             dedr_group<TJ, G>(yt, ar, ai, br, bi, A, gu);
             if (on) {
-                const float x = kpi * r / rcf;
-                const float fc = 0.5f * (cosf(x) + 1.f), dfc = -0.5f * kpi / rcf * sinf(x);
+                const float x = kcut * r;
+                const float fc = 0.5f * (cosf(x) + 1.f), dfc = -0.5f * kcut * sinf(x);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     // theta = kth r, n_i' = (delta_id - n_i n_d) / r

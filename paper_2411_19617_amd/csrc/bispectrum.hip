@@ -196,6 +196,9 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
         const int my_n = nnbr[lane];
         const int n_iter = wave_max_int(my_n);
         const float kpi = 3.14159265358979f;
+        // angle and cutoff phase per unit distance, formed once: a quotient
+        // per neighbour is a full-precision division (a dozen instructions)
+        const float kth = kRfac0 * kpi / rcf, kcut = kpi / rcf;
         for (int s = 0; s < n_iter; ++s) {
             float ar = 1.f, ai = 0.f, br = 0.f, bi = 0.f, fc = 0.f;
             if (s < my_n) {
@@ -203,15 +206,18 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
                 const float4 q = cand[c];
                 const float3 o = frame.at(c);
                 const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
-                const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-                const float inv = r > 0.f ? 1.f / r : 0.f;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                // 1/r and r from one hardware reciprocal square root (about
+                // 1 ulp; an atom on the point has r2 = 0 exactly)
+                const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                const float r = r2 * inv;
                 float sn, cs;
-                sincosf(kRfac0 * kpi * r / rcf, &sn, &cs);
+                sincosf(kth * r, &sn, &cs);
                 ar = cs;
                 ai = -dz * inv * sn;
                 br = -dy * inv * sn;
                 bi = -dx * inv * sn;
-                fc = 0.5f * (cosf(kpi * r / rcf) + 1.f);
+                fc = 0.5f * (cosf(kcut * r) + 1.f);
             }
             ui_neighbour<TJ, G, NACC>(ar, ai, br, bi, fc, accr, acci);
         }
