@@ -211,7 +211,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp(MlpArgs a, const float* __r
                 // every mode forms the same float LDOS value d = s y + c (affine map
                 // in FP64, rounded once), so that the stored LDOS, the DOS, the
                 // window, its prefix and a recomputed density all use identical numbers
-                const double sc = ev ? (double)a.out_scale[e] : 0.0, sh = ev ? (double)a.out_shift[e] : 0.0;
+                // the scaler rows are zero-padded to kMlpMaxOut: loaded unconditionally,
+                // so the sixteen loads of the epilogue issue together
+                const float scf = a.out_scale[e], shf = a.out_shift[e];
+                const double sc = ev ? (double)scf : 0.0, sh = ev ? (double)shf : 0.0;
                 double dsum = 0.0;
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
