@@ -188,7 +188,26 @@ hipError_t staged(mala_ctx* c, int stage, int64_t pts, F&& fn) {
     return e;
 }
 
-constexpr int kEstStride = 61;          // subsample stride of the E_F estimate
+// Subsample of the E_F estimate: every s-th point, s at least 61 and grown
+// on large grids so that about 2^18 points are sampled (the estimate only has
+// to place the stored energy window, whose margin is 0.3 eV; 65,000 points
+// already land within 2e-4 eV), s a prime that divides neither a row nor a
+// plane of the grid, so the samples do not line up with its structure.
+constexpr int64_t kEstStrideMin = 61;
+constexpr int64_t kEstSamples = int64_t(1) << 18;
+
+int64_t est_stride(const mala_cell_grid* cg) {
+    const int64_t row = cg->N[2], plane = (int64_t)cg->N[1] * cg->N[2];
+    const int64_t ntot = plane * cg->N[0];
+    int64_t s = ntot / kEstSamples > kEstStrideMin ? ntot / kEstSamples : kEstStrideMin;
+    auto prime = [](int64_t v) {
+        for (int64_t d = 2; d * d <= v; ++d)
+            if (v % d == 0) return false;
+        return true;
+    };
+    while (!prime(s) || row % s == 0 || plane % s == 0) ++s;
+    return s;
+}
 
 __global__ void k_set_covered(WindowRec* w, int v) {
     if (threadIdx.x == 0) {
@@ -412,7 +431,8 @@ PredictPlan plan_predict(const mala_cell_grid* cg, int32_t n_atoms, double rcut,
     p.partials = (size_t)mlp_blocks(ntot) * kMlpMaxOut;
     p.fermi_w = kMlpMaxOut;
     if (density && density_mode == 0) {
-        const int64_t n_est = (ntot + kEstStride - 1) / kEstStride;
+        const int64_t stride = est_stride(cg);
+        const int64_t n_est = (ntot + stride - 1) / stride;
         p.est_partials = (size_t)mlp_blocks(n_est) * kMlpMaxOut;
         p.window = (size_t)ntot * window_width(eg, T);
         p.prefix = (size_t)ntot;
@@ -1136,8 +1156,9 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
     o.de = eg->de;
     const bool window = density_out && c->density_mode == 0;
     if (window) {
-        // E_F estimate from every kEstStride-th point -> energy window of the stored LDOS
-        const int64_t n_est = (ntot + kEstStride - 1) / kEstStride;
+        // E_F estimate from every stride-th point -> energy window of the stored LDOS
+        const int64_t stride = est_stride(cg);
+        const int64_t n_est = (ntot + stride - 1) / stride;
         const int nbe = mlp_blocks(n_est);
         const double margin = kWindowMargin;            // eV, covers the estimate's error
         const int w_max = window_width(eg, T);
@@ -1147,9 +1168,9 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
         MlpOut oe;
         oe.partials = c->est_partials.p;
         HIP_TRY(staged(c, MALA_STAGE_ESTIMATE, n_est, [&] {
-            hipError_t e = launch_mlp(c->stream, w->args, kModeDos, B, n_est, kEstStride, nbe, oe);
+            hipError_t e = launch_mlp(c->stream, w->args, kModeDos, B, n_est, (int)stride, nbe, oe);
             if (e != hipSuccess) return e;
-            return launch_fermi_estimate(c->stream, c->est_partials.p, nbe, eg->n, dV * kEstStride, eg->e0, eg->de,
+            return launch_fermi_estimate(c->stream, c->est_partials.p, nbe, eg->n, dV * (double)stride, eg->e0, eg->de,
                                          kT, ne, c->win, c->li_coef, w_max, margin);
         }));
         o.win = c->win;
