@@ -491,7 +491,7 @@ mala_status mala_server_submit(mala_server* sv, const mala_request* q, uint64_t*
     r->dos_out = q->dos_out;
     r->density_out = q->density_out;
     r->n_pts = (int64_t)q->cell_grid.N[0] * q->cell_grid.N[1] * q->cell_grid.N[2];
-    if (r->n_pts <= 0 || r->twojmax < 2 || r->twojmax > mala::kMaxTwojmax || (r->twojmax & 1) ||
+    if (q->cell_grid.N[0] < 1 || q->cell_grid.N[1] < 1 || q->cell_grid.N[2] < 1 || r->twojmax < 2 || r->twojmax > mala::kMaxTwojmax || (r->twojmax & 1) ||
         r->eg.n < 2 || r->eg.n > mala::kMlpMaxOut || !(r->eg.de > 0) || !(r->T > 0))
         return MALA_E_INVALID_ARG;
     if (!(r->rcut > 0) || r->n_atoms > (1 << 24)) return MALA_E_INVALID_ARG;
@@ -555,7 +555,7 @@ mala_status mala_server_reserve(mala_server* sv, const mala_request* reqs, int32
     for (int32_t k = 0; k < n; ++k) {
         const mala_request& q = reqs[k];
         const int64_t np = (int64_t)q.cell_grid.N[0] * q.cell_grid.N[1] * q.cell_grid.N[2];
-        if (np <= 0 || q.n_atoms < 0 || q.twojmax < 2 || q.twojmax > mala::kMaxTwojmax || (q.twojmax & 1) ||
+        if (q.cell_grid.N[0] < 1 || q.cell_grid.N[1] < 1 || q.cell_grid.N[2] < 1 || q.n_atoms < 0 || q.twojmax < 2 || q.twojmax > mala::kMaxTwojmax || (q.twojmax & 1) ||
             q.egrid.n < 2 || q.egrid.n > mala::kMlpMaxOut || !(q.egrid.de > 0) || !(q.T_kelvin > 0) || !(q.rcut > 0))
             return sfail(MALA_E_INVALID_ARG, "reserve: invalid request");
         const mala::PredictPlan pk = mala::plan_predict(&q.cell_grid, q.n_atoms, q.rcut, q.twojmax, &q.egrid,

@@ -79,6 +79,10 @@ def test_invalid_requests(mala):
         sv.submit(pos, L, N, rc, 7, eg, T, ne)
     with pytest.raises(mala.MalaError):
         sv.submit(pos, L, N, rc, tj, eg, -5.0, ne)
+    with pytest.raises(mala.MalaError):                     # every grid dimension must be >= 1
+        sv.submit(pos, L, np.array([-1, -1, 5]), rc, tj, eg, T, ne)
+    with pytest.raises(mala.MalaError):
+        sv.reserve([(4, np.array([8.1] * 3), np.array([-2, -2, 40]), 4.67, 10, eg, 933.0)])
     sv.close()
 
 
