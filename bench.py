@@ -149,7 +149,7 @@ def kernel_source_hash():
 
 
 def measured_traffic(snapshot):
-    """HBM bytes per k_zb launch from the committed, calibrated rocprofv3 counters;
+    """HBM bytes per k_zb point from the committed, calibrated rocprofv3 counters;
     None if there are none for this snapshot or the kernel source changed since."""
     name = TRAFFIC_FILES.get(snapshot)
     path = os.path.join(ROOT, "profiles", name) if name else None
@@ -158,7 +158,7 @@ def measured_traffic(snapshot):
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv["traffic_bytes_per_point"])
 
 
 TRAFFIC_CMDS = """# commands (repository root = $REPO, output directory $OUT, after cd /tmp && export TMPDIR=/tmp):
@@ -802,6 +802,8 @@ def measure(ctx, mala, torch, snap, net, precision, steps, warmup, Bc, fl):
             tf = fl[fk] * prof[k][2] / (prof[k][0] * 1e-3) / 1e12
             stages[k].update({"tflops": tf, "peak_tflops": peak, "frac": tf / peak})
     ceiling = path_ceiling(fl, precision)
+    tpp = measured_traffic(snap.name)
+    traffic = tpp * zb_pts / max(zb_n, 1) if tpp is not None else None
     return {
         "value": value, "ms_per_step": 1000.0 * elapsed / steps, "steps": steps, "warmup": warmup,
         "dtype": "f32" if precision == "fp32" else "bf16",
@@ -813,8 +815,9 @@ def measure(ctx, mala, torch, snap, net, precision, steps, warmup, Bc, fl):
                        "kind": "single snapshot, back-to-back"},
         "roofline": {"kernel": "k_zb (Z/B contraction)", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": measured_traffic(snap.name),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
+                                     "per point x points per launch)",
                      "flops_per_point": fl["zb"], "points_per_launch": zb_pts / max(zb_n, 1),
                      "avg_launch_ms": zb_avg_ms},
         "path_roofline": {"ceiling_points_per_s": ceiling, "frac": value / ceiling,

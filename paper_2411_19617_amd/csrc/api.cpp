@@ -86,6 +86,10 @@ struct TjTables {
 };
 
 constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
+// grid points per descriptor chunk of the fused path: twice as many points
+// per k_ui / k_zb launch halve the share of each launch's tail, where the
+// last blocks finish alone (0.5% of a slab snapshot)
+constexpr int kPredictChunk = 1 << 20;
 constexpr double kWindowMargin = 0.3;     // eV around the E_F estimate kept in the stored LDOS window
 
 struct Ace4Tables {
@@ -315,9 +319,10 @@ size_t cell_entries(const mala_cell_grid* cg, double rcut) {
     return nc_est + 1;
 }
 
-// u scratch elements of one descriptor chunk of a grid of ntot points.
-size_t u_elements(int64_t ntot, int twojmax) {
-    const int64_t chunk = ntot < kChunk ? ntot : kChunk;
+// u scratch elements of one descriptor chunk (at most chunk_max points) of a
+// grid of ntot points.
+size_t u_elements(int64_t ntot, int twojmax, int64_t chunk_max = kChunk) {
+    const int64_t chunk = ntot < chunk_max ? ntot : chunk_max;
     return (size_t)((chunk + kTile - 1) / kTile) * n_half(twojmax) * kTile;
 }
 
@@ -345,14 +350,15 @@ mala_status bin_atoms(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, do
 }
 
 mala_status run_descriptors(mala_ctx* c, int32_t n_atoms, const mala_cell_grid* cg, double rcut,
-                            int32_t twojmax, int64_t pt_begin, int64_t pt_end, float* B_out) {
+                            int32_t twojmax, int64_t pt_begin, int64_t pt_end, float* B_out,
+                            int64_t chunk_max = kChunk) {
     BinState bs{};
     mala_status st = bin_atoms(c, n_atoms, cg, rcut, &bs);
     if (st) return st;
     const int nB = n_triples(twojmax);
     const int64_t total = pt_end - pt_begin;
-    const int64_t chunk = total < kChunk ? total : kChunk;
-    HIP_TRY(ensure(c->n_allocs, c->u, u_elements(total, twojmax)));
+    const int64_t chunk = total < chunk_max ? total : chunk_max;
+    HIP_TRY(ensure(c->n_allocs, c->u, u_elements(total, twojmax, chunk_max)));
     const TjTables& t = c->tj[twojmax];
     for (int64_t off = 0; off < total; off += chunk) {
         const int64_t n = (total - off) < chunk ? (total - off) : chunk;
@@ -426,7 +432,7 @@ PredictPlan plan_predict(const mala_cell_grid* cg, int32_t n_atoms, double rcut,
     p.pos = 3 * na;
     p.cells = cell_entries(cg, rcut);
     p.atoms = na;
-    p.u = u_elements(ntot, twojmax);
+    p.u = u_elements(ntot, twojmax, kPredictChunk);
     p.B = caller_b_cache ? 0 : (size_t)ntot * n_triples(twojmax);
     p.partials = (size_t)mlp_blocks(ntot) * kMlpMaxOut;
     p.fermi_w = kMlpMaxOut;
@@ -1145,7 +1151,7 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
         B = c->Bbuf.p;
     }
     if ((st = upload_positions(c, positions, n_atoms))) return st;
-    if ((st = run_descriptors(c, n_atoms, cg, rcut, twojmax, 0, ntot, B))) return st;
+    if ((st = run_descriptors(c, n_atoms, cg, rcut, twojmax, 0, ntot, B, kPredictChunk))) return st;
     const int nb = mlp_blocks(ntot);
     HIP_TRY(ensure(c->n_allocs, c->partials, (size_t)nb * kMlpMaxOut));
     HIP_TRY(ensure(c->n_allocs, c->fermi_w, kMlpMaxOut));
