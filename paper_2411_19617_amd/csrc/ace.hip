@@ -104,7 +104,8 @@ __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned
         const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         // 1/r and r from one hardware reciprocal square root (about 1 ulp)
-        const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+        const bool at_point = !(r2 > kMinR2);
+        const float inv = at_point ? 0.f : __builtin_amdgcn_rsqf(r2);
         const float r = r2 * inv;
         // radial: T_n(x) fc(r) by the three-term recurrence
         const float x = r * k2 - 1.f;
@@ -116,7 +117,7 @@ __device__ __forceinline__ void ace_project_n(const float4* cand, const unsigned
             t1 = t2;
         }
         const float R = (n == 0 ? 1.f : t1) * fc;
-        if (r2 == 0.f) {                                   // an atom on the point: l = 0 only
+        if (at_point) {                                    // an atom on the point: l = 0 only
             ar[0] += R * y00;
             continue;
         }

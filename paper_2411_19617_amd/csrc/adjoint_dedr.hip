@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64 * n_groups(TJ)) void k_dedr(BinState bins, int N
             const float3 o = frame.at(c);
             const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const bool on = act && r2 > 0.f;       // an atom on the point has no derivative: left out
+            const bool on = act && r2 > kMinR2;    // an atom on the point has no derivative: left out
             // 1/r and r from one hardware reciprocal square root (about 1 ulp)
             const float inv = on ? __builtin_amdgcn_rsqf(r2) : 1.f;
             const float r = on ? r2 * inv : 1.f;

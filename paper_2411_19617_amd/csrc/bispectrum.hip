@@ -208,8 +208,8 @@ __global__ __launch_bounds__(64 * n_groups(TJ), 2) void k_ui(BinState bins, int 
                 const float dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 // 1/r and r from one hardware reciprocal square root (about
-                // 1 ulp; an atom on the point has r2 = 0 exactly)
-                const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                // 1 ulp; an atom on the point gives r = 0)
+                const float inv = r2 > kMinR2 ? __builtin_amdgcn_rsqf(r2) : 0.f;
                 const float r = r2 * inv;
                 float sn, cs;
                 sincosf(kth * r, &sn, &cs);

@@ -146,6 +146,11 @@ __device__ __forceinline__ int gather_candidates(const BinState& bins, const Til
     return base;
 }
 
+// Squared displacements below this (r < 1e-15 A) count as an atom on the
+// point (r = 0): it keeps the hardware reciprocal square root away from
+// denormal inputs, and the terms left out are below FP32 resolution.
+constexpr float kMinR2 = 1e-30f;
+
 // A lane's point relative to the two origins its candidates are stored
 // against: candidate c is compared with at(c).
 struct PointFrame {
