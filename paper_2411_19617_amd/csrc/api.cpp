@@ -1196,7 +1196,7 @@ mala_status mala_predict(mala_ctx* c, const mala_weights* w, const double* posit
         if (window)
             HIP_TRY(staged(c, MALA_STAGE_DENSITY_WINDOW, ntot, [&] {
                 return launch_density_window(c->stream, c->prefix.p, c->window.p, ntot, c->win, result,
-                                             c->fermi_w.p, density_out);
+                                             c->fermi_w.p, density_out, window_width(eg, T));
             }));
         else
             HIP_TRY(set_covered(c, 0));

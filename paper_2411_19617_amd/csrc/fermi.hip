@@ -21,6 +21,8 @@
 // shrinking [lo, hi] and replaced by the midpoint whenever they leave it.
 #include <math.h>
 
+#include <mutex>
+
 #include "mala_internal.h"
 
 namespace mala {
@@ -326,21 +328,57 @@ __global__ __launch_bounds__(256) void k_fermi(const double* __restrict__ partia
 // n(p) = prefix(p) + sum over the stored window of w_e d_e(p), when the
 // window covers E_F +- 40 kT (outside it the Fermi weights equal the full
 // trapezoid weights or vanish to within e^-40).
+// n(p) = prefix(p) + sum over the window of w_e d_e(p).  A wave takes 64
+// points at a time: their window rows are 64 W contiguous floats, read with
+// consecutive lanes into LDS (row stride W: coalesced, where one lane per row
+// strides W floats between the lanes of every load) and then summed by the
+// row's lane in the fixed order of the energies (a tile's rows start on a
+// 256 W-byte boundary, so the copy moves 16 bytes per lane).  The block's four waves
+// move in step so that the staging area can be reused after a barrier.
+// Windows wider than w_stage (the LDS the host gave, per point) are summed
+// straight from memory.
 __global__ __launch_bounds__(256) void k_density_window(const double* __restrict__ prefix,
                                                         const float* __restrict__ window, int64_t n_pts,
                                                         const WindowRec* __restrict__ win,
                                                         const ResultRec* __restrict__ res,
-                                                        const double* __restrict__ w, double* __restrict__ dens) {
+                                                        const double* __restrict__ w, double* __restrict__ dens,
+                                                        int w_stage) {
     if (res->status != 0 || !win->covered) return;
     __shared__ double sw[kMlpMaxOut];
+    extern __shared__ float srow[];                      // [4 waves][64 rows][w_stage]
     const int lo = win->lo, W = win->hi - win->lo + 1;
     for (int i = threadIdx.x; i < W; i += blockDim.x) sw[i] = w[lo + i];
     __syncthreads();
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pts; p += (int64_t)gridDim.x * blockDim.x) {
-        double s = prefix[p];
-        const float* row = window + p * W;
-        for (int i = 0; i < W; ++i) s += sw[i] * (double)row[i];
-        dens[p] = s;
+    if (W > w_stage) {
+        for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pts;
+             p += (int64_t)gridDim.x * blockDim.x) {
+            double s = prefix[p];
+            const float* row = window + p * W;
+            for (int i = 0; i < W; ++i) s += sw[i] * (double)row[i];
+            dens[p] = s;
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float* rows = srow + wave * 64 * w_stage;
+    for (int64_t t0 = (int64_t)blockIdx.x * 4; t0 * 64 < n_pts; t0 += (int64_t)gridDim.x * 4) {
+        const int64_t p0 = (t0 + wave) * 64;
+        const int np = p0 < n_pts ? (int)(n_pts - p0 < 64 ? n_pts - p0 : 64) : 0;
+        // 64 W floats from 256 W-byte aligned rows: 16-byte loads, a few in flight
+        const float* src = window + p0 * W;
+        const int nf = np * W, n4 = nf >> 2;
+        const float4* src4 = reinterpret_cast<const float4*>(src);
+        float4* rows4 = reinterpret_cast<float4*>(rows);
+#pragma unroll 4
+        for (int i = lane; i < n4; i += 64) rows4[i] = src4[i];
+        for (int i = (n4 << 2) + lane; i < nf; i += 64) rows[i] = src[i];
+        __syncthreads();
+        if (lane < np) {
+            double s = prefix[p0 + lane];
+            for (int i = 0; i < W; ++i) s += sw[i] * (double)rows[lane * W + i];
+            dens[p0 + lane] = s;
+        }
+        __syncthreads();
     }
 }
 
@@ -395,12 +433,24 @@ hipError_t launch_fermi_estimate(hipStream_t s, const double* partials, int n_pa
 
 hipError_t launch_density_window(hipStream_t s, const double* prefix, const float* window, int64_t n_pts,
                                  const WindowRec* win, const void* result, const double* weights,
-                                 double* density) {
+                                 double* density, int w_max) {
     int64_t blocks = (n_pts + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_density_window, dim3((unsigned)blocks), dim3(256), 0, s, prefix, window, n_pts, win,
-                       static_cast<const ResultRec*>(result), weights, density);
+    // stage up to 96 energies per point (96 KB of LDS per block); wider
+    // windows (high temperatures on fine energy grids) take the direct path
+    const int w_stage = w_max <= kDensityStageMax ? (w_max > 0 ? w_max : 1) : 0;
+    const size_t lds = sizeof(float) * 256 * (size_t)w_stage;
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [] {
+        attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_density_window),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(float) * 256 * kDensityStageMax));
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    hipLaunchKernelGGL(k_density_window, dim3((unsigned)blocks), dim3(256), lds, s, prefix, window, n_pts, win,
+                       static_cast<const ResultRec*>(result), weights, density, w_stage);
     return hipGetLastError();
 }
 

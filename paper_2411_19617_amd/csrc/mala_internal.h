@@ -336,9 +336,10 @@ hipError_t launch_fermi(hipStream_t s, const double* partials, int n_parts, int 
 hipError_t launch_fermi_estimate(hipStream_t s, const double* partials, int n_parts, int n_e, double dV,
                                  double e0, double de, double kT, double n_target, WindowRec* win,
                                  const double* li_coef, int w_max, double margin);
+constexpr int kDensityStageMax = 96;       // window energies per point the density kernel stages in LDS
 hipError_t launch_density_window(hipStream_t s, const double* prefix, const float* window, int64_t n_pts,
                                  const WindowRec* win, const void* result, const double* weights,
-                                 double* density);
+                                 double* density, int w_max);
 
 hipError_t launch_density_from_ldos(hipStream_t s, const float* ldos, int64_t n_pts, int n_e,
                                     const double* weights, const void* result, double* density);
