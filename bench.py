@@ -894,7 +894,7 @@ def main():
         return
     if a.gpus != 1:
         print("bench.py measures one GPU: the path shards by grid slabs with one 2 KB DOS all-reduce, "
-              "but multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+              "which this library does not implement (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ extern "C" {
 typedef int32_t mala_status;
 #define MALA_OK 0
 #define MALA_E_INVALID_ARG (-1)  /* bad pointer, size, or parameter            */
-#define MALA_E_UNSUPPORTED (-2)  /* valid but outside this build (e.g. twojmax) */
+#define MALA_E_UNSUPPORTED (-2)  /* valid but not supported by the library (e.g. twojmax) */
 #define MALA_E_OOM (-3)          /* device allocation failed                   */
 #define MALA_E_NO_ROOT (-4)      /* N_e outside [N(e_0), N(e_last)]            */
 #define MALA_E_HIP (-5)          /* a HIP runtime call failed                  */
@@ -91,7 +91,7 @@ mala_status mala_check_device_errors(mala_ctx* ctx);
  *   per layer l: float64 W[w(l+1)][w(l)] row-major, float64 b[w(l+1)]
  *   float64  out_scale[wL], out_shift[wL] (LDOS = out_scale*y + out_shift)
  *   uint64   seed
- * This build supports n_layers = 3, w0 <= 128, hidden widths <= 512 and
+ * The library supports n_layers = 3, w0 <= 128, hidden widths <= 512 and
  * wL <= 256.  The blob is copied; the caller may free it after the call.
  * Weights live on the context's device but do not depend on the context
  * afterwards; mala_weights_free synchronises that device before freeing.    */

@@ -725,7 +725,7 @@ mala_status mala_weights_load(mala_ctx* c, const void* blob, size_t bytes, int32
         if (wid[i] < 1) return fail(MALA_E_INVALID_ARG, "bad layer width");
     const int n_in = wid[0], h1 = wid[1], h2 = wid[2], n_out = wid[3];
     if (n_in > kMlpMaxIn || h1 > kMlpMaxHidden || h2 > kMlpMaxHidden || n_out > kMlpMaxOut)
-        return fail(MALA_E_UNSUPPORTED, "layer width beyond this build's limits");
+        return fail(MALA_E_UNSUPPORTED, "layer width beyond the library's limits");
     std::vector<double> mean(n_in), sd(n_in), W1((size_t)h1 * n_in), b1(h1), W2((size_t)h2 * h1), b2(h2),
         W3((size_t)n_out * h2), b3(n_out), osc(n_out), osh(n_out);
     bool ok = take(mean.data(), 8 * n_in) && take(sd.data(), 8 * n_in) && take(W1.data(), 8 * W1.size()) &&
