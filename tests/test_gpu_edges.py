@@ -103,6 +103,24 @@ def test_predict_at_maximum_widths(env, prec):
         assert d_err <= 5e-2 and ef_err <= 5e-2 and n_err <= 5e-2
 
 
+def test_density_from_a_wide_window(env):
+    """At 1,500 K the stored energy window holds 112 energies, more than the
+    density kernel stages per point in LDS: its direct path, against the
+    oracle's density at every point of the 8,000-point grid."""
+    mala, ctx, torch = env
+    s, net = mala_synth.small(), mala_synth.small_net()
+    s.T = 1500.0
+    ref = oracle.predict(s, net, EG)
+    w = ctx.weights(mala_synth.net_to_blob(net), 0)
+    dos, dens, res = ctx.mala_predict(w, s.positions, s.L, s.N, s.rcut, s.twojmax, EG, s.T, s.n_electrons)
+    r = mala.read_result(res)
+    assert r["status"] == 0 and r["density_from_window"] == 1
+    n = dens.cpu().numpy()
+    err = float(np.max(np.abs(n - ref["density"])) / np.max(np.abs(ref["density"])))
+    log("wide window (1500 K): E_F %.2e eV, density %.2e" % (abs(r["e_fermi"] - ref["e_fermi"]), err))
+    assert abs(r["e_fermi"] - ref["e_fermi"]) <= 1e-4 and err <= 1e-5
+
+
 def test_predict_no_root_leaves_density(env):
     mala, ctx, torch = env
     s, net = mala_synth.small(), mala_synth.small_net()
