@@ -86,10 +86,11 @@ struct TjTables {
 };
 
 constexpr int kChunk = 1 << 19;          // grid points per descriptor chunk
-// grid points per descriptor chunk of the fused path: twice as many points
-// per k_ui / k_zb launch halve the share of each launch's tail, where the
-// last blocks finish alone (0.5% of a slab snapshot)
-constexpr int kPredictChunk = 1 << 20;
+// grid points per descriptor chunk of the fused path: more points per
+// k_ui / k_zb launch shrink the share of each launch's tail, where the last
+// blocks finish alone (2^19 -> 2^20 -> 2^21: 0.5% and 0.3% of a slab
+// snapshot; 4.5 GB of u scratch per context at twojmax 10)
+constexpr int kPredictChunk = 1 << 21;
 constexpr double kWindowMargin = 0.3;     // eV around the E_F estimate kept in the stored LDOS window
 
 struct Ace4Tables {

@@ -1,6 +1,6 @@
 """The 47,066,880-point fcc(111) slab (16,384 atoms, stacking fault, vacuum).
 
-The fused path (mala_predict, 64-point tiles in chunks of 2^20 points) writes
+The fused path (mala_predict, 64-point tiles in chunks of 2^21 points) writes
 its descriptors into a caller-owned B cache; its rows are compared with the
 oracle at seeded points and at forced ones (vacuum, surfaces, the fault plane,
 chunk seams, tiles that cross a z-row, the first and last point).  The
@@ -139,8 +139,8 @@ def forced_rows(snap):
     rows = [0, snap.n_points - 1]
     for k in (0, 3, 25, k_lo - 3, k_lo, k_fault - 1, k_fault, k_fault + 1, k_hi, k_hi + 3, Nz - 1):
         rows += [flat(5, 7, k), flat(Nx // 2, Ny // 2, k), flat(Nx - 1, Ny - 1, k)]
-    for m in (1, 2, 22, 44):                                # seams of the 2^20-point chunks
-        rows += [m * (1 << 20) - 1, m * (1 << 20), m * (1 << 20) + 1]
+    for m in (1, 11, 22):                                   # seams of the 2^21-point chunks
+        rows += [m * (1 << 21) - 1, m * (1 << 21), m * (1 << 21) + 1]
     for r in (1, 98_001, 9_801):                            # tiles crossing a z-row (odd rows)
         rows += [r * Nz - 1, r * Nz]
     rows = np.array(sorted(set(int(x) for x in rows if 0 <= x < snap.n_points)), dtype=np.int64)
