@@ -11,9 +11,20 @@ constexpr int kAceMaxL = 4;      // angular momentum
 
 inline int ace_count_ranks12(int nmax, int lmax) { return nmax + (lmax + 1) * nmax * (nmax + 1) / 2; }
 // rank-3 groups (p1, p2, l3): a header of kAceGroupInts ints each, its
-// outputs (A row base of n3 | descriptor position << 7, at most kAceN) inline
+// outputs (A row base of n3 | descriptor position << 7, at most kAceMaxN)
+// inline, then the first rank-3 position of its pair (p1, p2) and the pair's
+// width | (last group of the pair) << 8.  The outputs of a pair are
+// contiguous (at most kAceMaxPairCols).  Two tables: `groups` for
+// point-major output, laid out for kAce3Waves waves (entry k * kAce3Waves + w
+// is wave w's k-th group, each wave holding whole pairs, balanced by their
+// terms, padded with empty groups of combination -1), and `groups_dm` in
+// (p1, p2, l3) order for descriptor-major output (the waves take every
+// kAce3Waves-th group).
 constexpr int kAceGroupInts = 12;
-int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef);
+constexpr int kAce3Waves = 8;
+constexpr int kAceMaxPairCols = kAceMaxN * (kAceMaxL + 1);
+int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<int>& groups_dm,
+                     std::vector<float>& coef);
 // rank 4: descriptor set (p1, p2, p3, p4, L per entry) and its evaluation tables
 constexpr int kAce4MaxN = 3;
 constexpr int kAce4MaxL = 3;

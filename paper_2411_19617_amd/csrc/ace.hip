@@ -34,7 +34,6 @@ constexpr int kAceN = kAceMaxN;          // radial functions held per point
 constexpr int kAceL = kAceMaxL;          // largest l held
 constexpr int kAceLm = 15;               // (l, m >= 0) entries per n: l(l+1)/2 + m
 constexpr int kAceWaves = 4;            // projection: one wave per radial index
-constexpr int kAce3Waves = 8;           // rank 1-3 contraction
 
 __host__ __device__ constexpr double ace_fact(int n) {
     double f = 1.0;
@@ -243,17 +242,24 @@ __host__ __device__ constexpr bool ace3_combo_valid(int c) {
 }
 
 // Ranks 1-3 of one tile from its projected A (no register-heavy projection
-// here, so many blocks share a CU).
+// here, so many blocks share a CU).  STAGE: point-major output through LDS;
+// the descriptor-major form stores directly and keeps the LDS for more blocks.
+template <bool STAGE>
 __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restrict__ Ag, int nmax, int lmax,
                                                         int64_t n_pts, const int* __restrict__ groups,
                                                         int n_groups, const float* __restrict__ coef,
                                                         int n_desc,
                                                         float* __restrict__ out, int64_t ps, int64_t ds) {
     __shared__ float2 sA[kAceN * kAceLm][kTile];
+    // point-major output: each wave gathers a pair's (contiguous) columns for
+    // the tile's 64 points here, then writes them as row segments, several
+    // rows per store instruction, instead of 64 values a row apart per store
+    __shared__ float sO[STAGE ? kAce3Waves : 1][STAGE ? kAceMaxPairCols : 1][kTile + 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t idx = (int64_t)blockIdx.x * kTile + lane;
     const bool valid = idx < n_pts;
+    constexpr bool stage = STAGE;
     ace_load_tile(Ag, sA);
     __syncthreads();
 
@@ -298,6 +304,7 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
         const int oc = __builtin_amdgcn_readfirstlane(h[2]);
         const int combo = __builtin_amdgcn_readfirstlane(h[3]);
         const int b1 = __builtin_amdgcn_readfirstlane(h[4]), b2 = __builtin_amdgcn_readfirstlane(h[5]);
+        const int col0 = __builtin_amdgcn_readfirstlane(h[10]), pw = __builtin_amdgcn_readfirstlane(h[11]);
         float pr[9], pim[9];
         static_for<0, 125>([&](auto cc) {
             constexpr int C = decltype(cc)::value;
@@ -322,8 +329,25 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
                     v = fmaf(sg, pr[slot] * c.x - pim[slot] * cy, v);    // Re(P A)
                 }
             });
-            if (valid) o[(n12 + (ok >> 7)) * ds] = v;
+            if constexpr (stage) sO[wave][(ok >> 7) - col0][lane] = v;
+            else if (valid) o[(n12 + (ok >> 7)) * ds] = v;
         });
+        if (stage && (pw >> 8)) {                     // the pair's last group: write its columns
+            const int ncol = pw & 255;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int rows = kTile / ncol, r_l = lane / ncol, c_l = lane - r_l * ncol;
+            const int64_t t0 = (int64_t)blockIdx.x * kTile;
+            for (int r0 = 0; r0 < kTile; r0 += rows) {
+                const int r = r0 + r_l;
+                if (r_l < rows && r < kTile && t0 + r < n_pts)
+                    out[(t0 + r) * ps + (n12 + col0 + c_l)] = sO[wave][c_l][r];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 
@@ -492,8 +516,12 @@ hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64
     if (n_pts <= 0) return hipSuccess;
     if (nmax < 1 || nmax > kAceN || lmax < 0 || lmax > kAceL) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_ace, dim3((unsigned)n_tiles), dim3(64 * kAce3Waves), 0, s, Ag, nmax, lmax, n_pts, groups,
-                       n_groups, coef, n_desc, out, ps, ds);
+    if (ds == 1)
+        hipLaunchKernelGGL(k_ace<true>, dim3((unsigned)n_tiles), dim3(64 * kAce3Waves), 0, s, Ag, nmax, lmax, n_pts,
+                           groups, n_groups, coef, n_desc, out, ps, ds);
+    else
+        hipLaunchKernelGGL(k_ace<false>, dim3((unsigned)n_tiles), dim3(64 * kAce3Waves), 0, s, Ag, nmax, lmax, n_pts,
+                           groups, n_groups, coef, n_desc, out, ps, ds);
     return hipGetLastError();
 }
 

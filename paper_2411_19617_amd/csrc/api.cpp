@@ -106,7 +106,9 @@ struct Ace4Tables {
 struct AceTables {
     bool ready = false;
     int n3 = 0, n_groups = 0;
-    int* groups = nullptr;
+    int* groups = nullptr;            // point-major plan
+    int* groups_dm = nullptr;         // descriptor-major order
+    int n_groups_dm = 0;
     float* coef = nullptr;
 };
 
@@ -595,6 +597,7 @@ mala_status mala_destroy(mala_ctx* c) {
     for (auto& row : c->ace)
         for (auto& a : row) {
             if (a.groups) (void)hipFree(a.groups);
+            if (a.groups_dm) (void)hipFree(a.groups_dm);
             if (a.coef) (void)hipFree(a.coef);
         }
     for (auto& row : c->ace4)
@@ -912,9 +915,10 @@ mala_status mala_descriptors_vjp(mala_ctx* c, const double* positions, int32_t n
 
 int32_t mala_ace_count(int32_t nmax, int32_t lmax) {
     if (nmax < 1 || nmax > kAceMaxN || lmax < 0 || lmax > kAceMaxL) return MALA_E_UNSUPPORTED;
-    std::vector<int> groups;
+    std::vector<int> groups, groups_dm;
     std::vector<float> coef;
-    return ace_count_ranks12(nmax, lmax) + build_ace_tables(nmax, lmax, groups, coef);
+    const int n3 = build_ace_tables(nmax, lmax, groups, groups_dm, coef);
+    return n3 < 0 ? MALA_E_UNSUPPORTED : ace_count_ranks12(nmax, lmax) + n3;
 }
 
 mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n_atoms, const mala_cell_grid* cg,
@@ -934,14 +938,18 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
     DeviceGuard g(c->device);
     AceTables& t = c->ace[nmax][lmax];
     if (!t.ready) {
-        std::vector<int> groups;
+        std::vector<int> groups, groups_dm;
         std::vector<float> coef;
-        t.n3 = build_ace_tables(nmax, lmax, groups, coef);
+        t.n3 = build_ace_tables(nmax, lmax, groups, groups_dm, coef);
+        if (t.n3 < 0) return fail(MALA_E_UNSUPPORTED, "grid ACE: a pair's outputs exceed the staging columns");
         t.n_groups = (int)(groups.size() / kAceGroupInts);
-        c->n_allocs += 2;
+        t.n_groups_dm = (int)(groups_dm.size() / kAceGroupInts);
+        c->n_allocs += 3;
         HIP_TRY(hipMalloc(&t.groups, sizeof(int) * (groups.size() ? groups.size() : 1)));
+        HIP_TRY(hipMalloc(&t.groups_dm, sizeof(int) * (groups_dm.size() ? groups_dm.size() : 1)));
         HIP_TRY(hipMalloc(&t.coef, sizeof(float) * (coef.size() ? coef.size() : 1)));
         HIP_TRY(hipMemcpy(t.groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t.groups_dm, groups_dm.data(), sizeof(int) * groups_dm.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(t.coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice));
         t.ready = true;
     }
@@ -960,8 +968,9 @@ mala_status mala_ace_descriptors(mala_ctx* c, const double* positions, int32_t n
         HIP_TRY(staged(c, MALA_STAGE_ACE, n, [&] {
             hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
             if (e != hipSuccess) return e;
-            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, t.groups, t.n_groups, t.coef, n_desc,
-                              out + off * ps, ps, ds);
+            const bool pm = ds == 1;              // staged point-major rows, else plain stores
+            return launch_ace(c->stream, c->aceA.p, nmax, lmax, n, pm ? t.groups : t.groups_dm,
+                              pm ? t.n_groups : t.n_groups_dm, t.coef, n_desc, out + off * ps, ps, ds);
         }));
     }
     return MALA_OK;

@@ -206,8 +206,10 @@ void plan_y_units(int twojmax, int c_lo, int c_hi, int n_waves, int* wave_units,
 // descriptor's rank-3 position (bits 7 and up).  The 3j symbol comes from the
 // coupled states of couple(): (l1 l2 l3; m1 m2 m3) = (-1)^(l1-l2-m3)
 // <l1 m1 l2 m2 | l3 -m3> / sqrt(2 l3 + 1).
-int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<float>& coef) {
+int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<int>& groups_dm,
+                     std::vector<float>& coef) {
     groups.clear();
+    groups_dm.clear();
     coef.clear();
     std::vector<Coupling> cache(25 * 25);
     std::vector<bool> have(cache.size(), false);
@@ -237,8 +239,15 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<f
                 pos_of[(p1 * np + p2) * np + p3] = nd++;
             }
     std::vector<int> block_of(125, -1);
+    struct Pair {
+        std::vector<std::array<int, kAceGroupInts>> groups;
+        int col0 = -1, ncol = 0;
+        long cost = 0;
+    };
+    std::vector<Pair> pairs;
     for (int p1 = 0; p1 < np; ++p1)
-        for (int p2 = p1; p2 < np; ++p2)
+        for (int p2 = p1; p2 < np; ++p2) {
+            Pair pr;
             for (int l3 = 0; l3 <= lmax; ++l3) {
                 const int n1 = p1 / (lmax + 1), l1 = p1 % (lmax + 1), n2 = p2 / (lmax + 1), l2 = p2 % (lmax + 1);
                 if (l3 < abs(l1 - l2) || l3 > l1 + l2 || (l1 + l2 + l3) % 2) continue;
@@ -250,6 +259,10 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<f
                 }
                 if (outs.empty()) continue;
                 const int combo = l1 * 25 + l2 * 5 + l3;
+                int terms = 0;                   // structural terms (m3, m1) of the combination
+                for (int m3 = -l3; m3 <= l3; ++m3)
+                    for (int m1 = -l1; m1 <= l1; ++m1)
+                        terms += abs(m1 + m3) <= l2;
                 if (block_of[combo] < 0) {
                     block_of[combo] = (int)coef.size();
                     for (int m3 = -l3; m3 <= l3; ++m3)
@@ -260,12 +273,71 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<f
                         }
                 }
                 // header: coefficient block, l3, output count, combination, the
-                // two A row bases, then the outputs (one per n3 <= nmax <= 4)
-                int g[kAceGroupInts] = {block_of[combo], l3, (int)outs.size(), combo,
-                                        n1 * 15 + l1 * (l1 + 1) / 2, n2 * 15 + l2 * (l2 + 1) / 2};
-                for (size_t i = 0; i < outs.size(); ++i) g[6 + i] = outs[i];
-                for (int i = 0; i < kAceGroupInts; ++i) groups.push_back(g[i]);
+                // two A row bases, the outputs (one per n3 <= nmax <= 4), then
+                // the pair's columns (filled below)
+                std::array<int, kAceGroupInts> g{};
+                g[0] = block_of[combo];
+                g[1] = l3;
+                g[2] = (int)outs.size();
+                g[3] = combo;
+                g[4] = n1 * 15 + l1 * (l1 + 1) / 2;
+                g[5] = n2 * 15 + l2 * (l2 + 1) / 2;
+                for (size_t i = 0; i < outs.size(); ++i) {
+                    g[6 + i] = outs[i];
+                    const int pos = outs[i] >> 7;
+                    if (pr.col0 < 0 || pos < pr.col0) pr.col0 = pos;
+                    ++pr.ncol;
+                }
+                pr.cost += terms + (long)outs.size() * (2 * l3 + 1);
+                pr.groups.push_back(g);
             }
+            if (pr.groups.empty()) continue;
+            // the kernel stages a pair's outputs by column - col0: they must be
+            // exactly the columns col0 .. col0 + ncol - 1
+            std::vector<int> cols;
+            for (const auto& g : pr.groups)
+                for (int i = 0; i < g[2]; ++i) cols.push_back(g[6 + i] >> 7);
+            std::sort(cols.begin(), cols.end());
+            for (size_t i = 0; i < cols.size(); ++i)
+                if (cols[i] != pr.col0 + (int)i) return -1;
+            if (pr.ncol > kAceMaxPairCols) return -1;
+            for (const auto& g : pr.groups)                     // (p1, p2, l3) order
+                for (int i = 0; i < kAceGroupInts; ++i) groups_dm.push_back(g[i]);
+            pairs.push_back(pr);
+        }
+    // whole pairs to the waves, longest first to the least loaded (LPT)
+    std::vector<int> order(pairs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pairs[a].cost > pairs[b].cost; });
+    std::vector<long> load(kAce3Waves, 0);
+    std::vector<std::vector<int>> wave_pairs(kAce3Waves);
+    for (int i : order) {
+        const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[w] += pairs[i].cost;
+        wave_pairs[w].push_back(i);
+    }
+    std::vector<std::vector<std::array<int, kAceGroupInts>>> lists(kAce3Waves);
+    size_t longest = 0;
+    for (int w = 0; w < kAce3Waves; ++w) {
+        std::sort(wave_pairs[w].begin(), wave_pairs[w].end());
+        for (int i : wave_pairs[w]) {
+            const Pair& pr = pairs[i];
+            for (size_t k = 0; k < pr.groups.size(); ++k) {
+                std::array<int, kAceGroupInts> g = pr.groups[k];
+                g[10] = pr.col0;
+                g[11] = pr.ncol | ((k + 1 == pr.groups.size() ? 1 : 0) << 8);
+                lists[w].push_back(g);
+            }
+        }
+        longest = std::max(longest, lists[w].size());
+    }
+    std::array<int, kAceGroupInts> empty{};
+    empty[3] = -1;
+    for (size_t k = 0; k < longest; ++k)
+        for (int w = 0; w < kAce3Waves; ++w) {
+            const std::array<int, kAceGroupInts>& g = k < lists[w].size() ? lists[w][k] : empty;
+            for (int i = 0; i < kAceGroupInts; ++i) groups.push_back(g[i]);
+        }
     return nd;
 }
 
