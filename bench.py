@@ -342,6 +342,7 @@ def probe_kernels():
 
 
 COUNTER_KERNELS = ["mala::k_ui<", "mala::k_zb<", "mala::k_mlp<0", "mala::k_mlp<1", "mala::k_ace4", "mala::k_ace",
+                   "mala::k_planes_to_rows",
                    "mala::k_mlp_vjp", "mala::k_yi", "mala::k_dedr"]
 
 

@@ -198,6 +198,8 @@ mala_status mala_ace_descriptors(mala_ctx* ctx, const double* positions, int32_t
  *  out: device float32 [pt_end - pt_begin][mala_ace4_count(nmax4, lmax4)]
  *  (MALA_LAYOUT_POINT_MAJOR) or its transpose (MALA_LAYOUT_DESCRIPTOR_MAJOR),
  *  descriptors in the order of mala_ace4_list.
+ * Point-major output goes through descriptor planes of 65,536-point chunks
+ * in a context buffer (65,536 x count floats, 246 MB at nmax4 = lmax4 = 3).
  * mala_ace4_list writes (p1, p2, p3, p4, L) per descriptor into out[5 n]
  * (host int32, cap entries of five) and returns the count, or < 0 if the
  * sizes are unsupported or cap is too small.  Empty ranges are a no-op.    */

@@ -30,6 +30,9 @@ constexpr int kAce4MaxN = 3;
 constexpr int kAce4MaxL = 3;
 constexpr size_t kAce4LdsBudget = 96 * 1024;     // dynamic LDS of the pair vectors of one L
 constexpr int kAce4MaxDescsL = 512;               // descriptors of one L (364 at nmax4 = lmax4 = 3)
+// point-major rank 4 runs in chunks of kAce4RowChunk points: descriptor
+// planes of the chunk (246 MB at 939 per point), then rows
+constexpr int64_t kAce4RowChunk = 1 << 16;
 int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc);
 int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
                       std::vector<float>& coef, std::vector<int>& l_descs, std::vector<int4>& descs,
@@ -43,6 +46,8 @@ hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], 
 hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts, const int* l_units,
                        const int4* units, const float* coef, const int* l_descs, const int4* descs, int max_slots,
                        int n4, float* out, int64_t ps, int64_t ds);   // descriptor k of point p at out[p ps + k ds]
+// out[p n_cols + k] = in[k ld + p] (p < n_rows <= ld, k < n_cols)
+hipError_t launch_planes_to_rows(hipStream_t s, const float* in, int64_t ld, int64_t n_rows, int n_cols, float* out);
 hipError_t launch_ace(hipStream_t s, const float2* Ag, int nmax, int lmax, int64_t n_pts, const int* groups,
                       int n_groups, const float* coef, int n_desc, float* out, int64_t ps,
                       int64_t ds);

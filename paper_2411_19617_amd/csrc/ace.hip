@@ -481,6 +481,32 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
     }
 }
 
+// Point-major rows from descriptor planes: out[p * n_cols + k] = in[k * ld + p]
+// for p < n_rows, k < n_cols, through a 64 x 64 LDS block (both sides
+// coalesced); neighbouring blocks take neighbouring row tiles, so the reads
+// of one plane stay together (one block per row tile walking every column
+// block, or column blocks as neighbours, measured slower).
+// Rank 4 writes its planes this way: the columns of one L are spread over
+// the whole row, so its direct point-major stores put every lane's value in
+// a line of its own.
+__global__ __launch_bounds__(256) void k_planes_to_rows(const float* __restrict__ in, int64_t ld, int64_t n_rows,
+                                                        int n_cols, float* __restrict__ out) {
+    __shared__ float sT[64][kTile + 1];
+    const int64_t p0 = (int64_t)blockIdx.x * kTile;
+    const int c0 = blockIdx.y * 64;
+    const int rows = (int)(n_rows - p0 < kTile ? n_rows - p0 : kTile);
+    const int cols = n_cols - c0 < 64 ? n_cols - c0 : 64;
+    for (int e = threadIdx.x; e < 64 * kTile; e += blockDim.x) {
+        const int c = e / kTile, r = e % kTile;
+        if (c < cols && r < rows) sT[c][r] = in[(int64_t)(c0 + c) * ld + p0 + r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTile * 64; e += blockDim.x) {
+        const int r = e / 64, c = e % 64;
+        if (c < cols && r < rows) out[(p0 + r) * n_cols + c0 + c] = sT[c][r];
+    }
+}
+
 hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], double rcut, int64_t pt_begin,
                            int64_t n_pts, float2* Ag, int* err) {
     if (n_pts <= 0) return hipSuccess;
@@ -507,6 +533,15 @@ hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, Ag, lmax4, n_pts, l_units,
                        units, coef, l_descs, descs, n4, out, ps, ds);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_to_rows(hipStream_t s, const float* in, int64_t ld, int64_t n_rows, int n_cols, float* out) {
+    if (n_rows <= 0 || n_cols <= 0) return hipSuccess;
+    if (ld < n_rows) return hipErrorInvalidValue;
+    const int64_t row_tiles = (n_rows + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_planes_to_rows, dim3((unsigned)row_tiles, (unsigned)((n_cols + 63) / 64)), dim3(256), 0, s,
+                       in, ld, n_rows, n_cols, out);
     return hipGetLastError();
 }
 

@@ -126,6 +126,7 @@ struct mala_ctx {
     DevBuf<float2> u;
     DevBuf<float2> yadj;                 // dL/du of the descriptor adjoint, laid out like u
     DevBuf<float2> aceA;                 // projected grid ACE basis of one chunk [tile][60][64]
+    DevBuf<float> ace4S;                 // rank-4 descriptor planes of one point-major chunk
     DevBuf<float> Bbuf;
     DevBuf<double> partials, est_partials;
     DevBuf<double> fermi_w;
@@ -516,6 +517,7 @@ void ctx_trim(mala_ctx* c) {
     release(c->u);
     release(c->yadj);
     release(c->aceA);
+    release(c->ace4S);
     release(c->Bbuf);
     release(c->window);
     release(c->prefix);
@@ -584,6 +586,7 @@ mala_status mala_destroy(mala_ctx* c) {
     release(c->u);
     release(c->yadj);
     release(c->aceA);
+    release(c->ace4S);
     release(c->Bbuf);
     release(c->partials);
     release(c->est_partials);
@@ -1034,17 +1037,24 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
     BinState bs{};
     if ((st = bin_atoms(c, n_atoms, cg, rcut, &bs))) return st;
     const int64_t total = pt_end - pt_begin;
-    const int64_t chunk = total < kChunk ? total : kChunk;
-    const int64_t ps4 = layout == MALA_LAYOUT_POINT_MAJOR ? t.n4 : 1;
-    const int64_t ds4 = layout == MALA_LAYOUT_POINT_MAJOR ? 1 : total;
+    const bool pm = layout == MALA_LAYOUT_POINT_MAJOR;
+    // point-major: descriptor planes of each chunk into ace4S, then rows
+    const int64_t chunk_max = pm ? kAce4RowChunk : kChunk;
+    const int64_t chunk = total < chunk_max ? total : chunk_max;
     HIP_TRY(ensure(c->n_allocs, c->aceA, (size_t)((chunk + kTile - 1) / kTile) * kAceAPerPoint * kTile));
+    if (pm) HIP_TRY(ensure(c->n_allocs, c->ace4S, (size_t)chunk * t.n4));
     for (int64_t off = 0; off < total; off += chunk) {
         const int64_t n = (total - off) < chunk ? (total - off) : chunk;
         HIP_TRY(staged(c, MALA_STAGE_ACE4, n, [&] {
             hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
             if (e != hipSuccess) return e;
-            return launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
-                               t.max_slots, t.n4, out + off * ps4, ps4, ds4);
+            if (!pm)
+                return launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
+                                   t.max_slots, t.n4, out + off, 1, total);
+            e = launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
+                            t.max_slots, t.n4, c->ace4S.p, 1, chunk);
+            if (e != hipSuccess) return e;
+            return launch_planes_to_rows(c->stream, c->ace4S.p, chunk, n, t.n4, out + off * t.n4);
         }));
     }
     return MALA_OK;

@@ -152,9 +152,9 @@ def test_ace4_empty_and_unsupported(env):
 @pytest.mark.parametrize("rank", [3, 4])
 def test_ace_descriptor_major_layout_is_the_transpose(env, rank):
     """The descriptor-major output is the transpose of the point-major one
-    over a range that spans two 2^19-point chunks (to FP32 rounding: the
-    projection adds the waves' parts with LDS float atomics, so the last bits
-    of two calls may differ)."""
+    over a range that spans two 2^19-point chunks, and for rank 4 nine of
+    the 65,536-point chunks its point-major staging runs in, the last one
+    ragged."""
     mala, ctx, torch = env
     s = mala_synth.paper_solid()
     b, e = 100_000, 100_000 + (1 << 19) + 777
