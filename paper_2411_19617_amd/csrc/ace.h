@@ -29,11 +29,15 @@ int build_ace_tables(int nmax, int lmax, std::vector<int>& groups, std::vector<i
 constexpr int kAce4MaxN = 3;
 constexpr int kAce4MaxL = 3;
 constexpr size_t kAce4LdsBudget = 96 * 1024;     // dynamic LDS of the pair vectors of one L
-constexpr int kAce4MaxDescsL = 512;               // descriptors of one L (364 at nmax4 = lmax4 = 3)
+constexpr int kAce4MaxDescsL = 1024;              // descriptors of one phase (364 for L = 2 at nmax4 = lmax4 = 3)
 // point-major rank 4 runs in chunks of kAce4RowChunk points: descriptor
 // planes of the chunk (246 MB at 939 per point), then rows
 constexpr int64_t kAce4RowChunk = 1 << 16;
 int ace4_descriptor_set(int nmax4, int lmax4, std::vector<int>& desc);
+// The evaluation runs in phases, each one or more couplings L whose pair
+// slots fit the LDS budget together: l_units / l_descs are offsets per
+// phase; a descriptor entry is (first pair slot | L << 16, second pair slot,
+// output, factor bits), slots counted within the phase.
 int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vector<int4>& units,
                       std::vector<float>& coef, std::vector<int>& l_descs, std::vector<int4>& descs,
                       int& max_slots);
@@ -43,7 +47,7 @@ int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vect
 constexpr int kAceAPerPoint = kAceMaxN * 15;
 hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], double rcut, int64_t pt_begin,
                            int64_t n_pts, float2* Ag, int* err);
-hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts, const int* l_units,
+hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int n_phases, int64_t n_pts, const int* l_units,
                        const int4* units, const float* coef, const int* l_descs, const int4* descs, int max_slots,
                        int n4, float* out, int64_t ps, int64_t ds);   // descriptor k of point p at out[p ps + k ds]
 // out[p n_cols + k] = in[k ld + p] (p < n_rows <= ld, k < n_cols)

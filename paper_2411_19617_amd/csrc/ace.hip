@@ -400,16 +400,16 @@ __host__ __device__ constexpr bool ace4_combo_valid(int c) {
 }
 
 // Rank 4 (one intermediate coupling L).  Sixteen waves per 64-point tile
-// (the projected A of the tile in LDS): for every L the coupled pairs
-// P_a(M) = sum_m1 <l1 m1 l2 m2|L M> A_p1 A_p2 (M = 0..L) the descriptors of
-// that L need are formed into LDS (every wave takes every sixteenth pair, all
-// its M by code specialised for (l1, l2, L)), then every wave evaluates a contiguous share of that L's
-// descriptors, B = f (Re P_a(0) conj P_b(0) + 2 sum_{M>0} Re P_a(M) conj P_b(M))
+// (the projected A of the tile in LDS), in phases of one or more L: the
+// coupled pairs P_a(M) = sum_m1 <l1 m1 l2 m2|L M> A_p1 A_p2 (M = 0..L) the
+// descriptors of the phase need are formed into LDS (every wave takes every
+// sixteenth pair, all its M by code specialised for (l1, l2, L)), then every
+// wave evaluates a contiguous share of the phase's descriptors, B = f (Re P_a(0) conj P_b(0) + 2 sum_{M>0} Re P_a(M) conj P_b(M))
 // (f = (-1)^(l3+l4) / sqrt(2L+1)), keeping P_a in registers while consecutive
 // descriptors share it.  Terms and descriptors come from wave-uniform loads.
 constexpr int kAce4Waves = 16;
 
-__global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restrict__ Ag, int lmax4, int64_t n_pts,
+__global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restrict__ Ag, int n_phases, int64_t n_pts,
                                                           const int* __restrict__ l_units,
                                                           const int4* __restrict__ units,
                                                           const float* __restrict__ coef,
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
                                                           const int4* __restrict__ descs, int n4,
                                                           float* __restrict__ out, int64_t ps, int64_t ds) {
     __shared__ float2 sA[kAceN * kAceLm][kTile];
-    __shared__ int4 sD[kAce4MaxDescsL];     // this L's descriptor entries
+    __shared__ int4 sD[kAce4MaxDescsL];     // this phase's descriptor entries
     extern __shared__ float2 sP[];          // [slots][kTile]
 
     const int lane = threadIdx.x & 63;
@@ -429,14 +429,14 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
     __syncthreads();
 
     float* o = out + (tl.valid ? tl.idx : 0) * ps;    // descriptor k at o[k * ds]
-    for (int L = 0; L <= 2 * lmax4; ++L) {
-        // this L's descriptor entries into LDS, read back as broadcasts: a
-        // scalar load per descriptor would hold every LDS wait of the loop
+    for (int ph = 0; ph < n_phases; ++ph) {
+        // this phase's descriptor entries into LDS, read back as broadcasts:
+        // a scalar load per descriptor would hold every LDS wait of the loop
         // below until the scalar cache answered
-        const int d0 = l_descs[L], nd = l_descs[L + 1] - d0;
+        const int d0 = l_descs[ph], nd = l_descs[ph + 1] - d0;
         for (int i = threadIdx.x; i < nd; i += blockDim.x) sD[i] = descs[d0 + i];
-        // coupled pairs of this L into sP
-        const int u0 = l_units[L], u1 = l_units[L + 1];
+        // coupled pairs of this phase's couplings L into sP
+        const int u0 = l_units[ph], u1 = l_units[ph + 1];
         for (int u = u0 + wave; u < u1; u += kAce4Waves) {
             const int4 h = units[u];
             const float* cf = coef + __builtin_amdgcn_readfirstlane(h.x);
@@ -451,13 +451,14 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
             });
         }
         __syncthreads();
-        // this L's descriptors, a contiguous share per wave
+        // this phase's descriptors, a contiguous share per wave
         const int db = nd * wave / kAce4Waves, de = nd * (wave + 1) / kAce4Waves;
         int cached = -1;
         float2 pa[2 * kAce4MaxL + 1];
         for (int d = db; d < de; ++d) {
             const int4 q = sD[d];
-            const int sa = __builtin_amdgcn_readfirstlane(q.x), sb = __builtin_amdgcn_readfirstlane(q.y);
+            const int sx = __builtin_amdgcn_readfirstlane(q.x), sb = __builtin_amdgcn_readfirstlane(q.y);
+            const int sa = sx & 0xffff, L = sx >> 16;             // a slot identifies its L too
             const int ok = __builtin_amdgcn_readfirstlane(q.z);
             const float f = __int_as_float(__builtin_amdgcn_readfirstlane(q.w));
             if (sa != cached) {
@@ -516,7 +517,7 @@ hipError_t launch_ace_proj(hipStream_t s, const BinState& bins, const int N[3], 
     return hipGetLastError();
 }
 
-hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts, const int* l_units,
+hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int n_phases, int64_t n_pts, const int* l_units,
                        const int4* units, const float* coef, const int* l_descs, const int4* descs, int max_slots,
                        int n4, float* out, int64_t ps, int64_t ds) {
     if (n_pts <= 0 || n4 <= 0) return hipSuccess;
@@ -531,7 +532,7 @@ hipError_t launch_ace4(hipStream_t s, const float2* Ag, int lmax4, int64_t n_pts
     if (attr_err != hipSuccess) return attr_err;
     if (lds > kAce4LdsBudget) return hipErrorInvalidValue;
     const int64_t n_tiles = (n_pts + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, Ag, lmax4, n_pts, l_units,
+    hipLaunchKernelGGL(k_ace4, dim3((unsigned)n_tiles), dim3(64 * kAce4Waves), lds, s, Ag, n_phases, n_pts, l_units,
                        units, coef, l_descs, descs, n4, out, ps, ds);
     return hipGetLastError();
 }

@@ -95,8 +95,8 @@ constexpr double kWindowMargin = 0.3;     // eV around the E_F estimate kept in 
 
 struct Ace4Tables {
     bool ready = false;
-    int n4 = 0, max_slots = 0;
-    int* l_units = nullptr;
+    int n4 = 0, max_slots = 0, n_phases = 0;
+    int* l_units = nullptr;           // unit and descriptor offsets per phase
     int4* units = nullptr;
     float* coef = nullptr;
     int* l_descs = nullptr;
@@ -1017,9 +1017,10 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
         t.n4 = build_ace4_tables(nmax4, lmax4, l_units, units, coef, l_descs, descs, t.max_slots);
         if ((size_t)t.max_slots * kTile * sizeof(float2) > kAce4LdsBudget)
             return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: pair vectors exceed the LDS budget");
-        for (size_t L = 0; L + 1 < l_descs.size(); ++L)
-            if (l_descs[L + 1] - l_descs[L] > kAce4MaxDescsL)
+        for (size_t ph = 0; ph + 1 < l_descs.size(); ++ph)
+            if (l_descs[ph + 1] - l_descs[ph] > kAce4MaxDescsL)
                 return fail(MALA_E_UNSUPPORTED, "rank-4 grid ACE: more descriptors of one L than staged in LDS");
+        t.n_phases = (int)l_descs.size() - 1;
         c->n_allocs += 5;
         HIP_TRY(hipMalloc(&t.l_units, sizeof(int) * l_units.size()));
         HIP_TRY(hipMalloc(&t.units, sizeof(int4) * (units.size() ? units.size() : 1)));
@@ -1049,9 +1050,9 @@ mala_status mala_ace4_descriptors(mala_ctx* c, const double* positions, int32_t 
             hipError_t e = launch_ace_proj(c->stream, bs, cg->N, rcut, pt_begin + off, n, c->aceA.p, c->err);
             if (e != hipSuccess) return e;
             if (!pm)
-                return launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
+                return launch_ace4(c->stream, c->aceA.p, lmax4, t.n_phases, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
                                    t.max_slots, t.n4, out + off, 1, total);
-            e = launch_ace4(c->stream, c->aceA.p, lmax4, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
+            e = launch_ace4(c->stream, c->aceA.p, lmax4, t.n_phases, n, t.l_units, t.units, t.coef, t.l_descs, t.descs,
                             t.max_slots, t.n4, c->ace4S.p, 1, chunk);
             if (e != hipSuccess) return e;
             return launch_planes_to_rows(c->stream, c->ace4S.p, chunk, n, t.n4, out + off * t.n4);

@@ -458,54 +458,95 @@ int build_ace4_tables(int nmax4, int lmax4, std::vector<int>& l_units, std::vect
     coef.clear();
     descs.clear();
     max_slots = 0;
-    std::vector<int> block_of(4 * 4 * 7, -1);        // (l1, l2, L) with l <= 3, L <= 6
-    for (int L = 0; L <= 2 * lmax4; ++L) {
-        // the pairs this L needs, in first-use order, each with L+1 slots
+    // per L: the pairs it needs, in first-use order, each with L+1 slots,
+    // and its descriptors (first pair slot, second pair slot, output, l3+l4)
+    struct LPart {
         std::vector<std::pair<int, int>> pairs;
-        auto slot_of = [&](int pa, int pb) {
-            for (size_t i = 0; i < pairs.size(); ++i)
-                if (pairs[i].first == pa && pairs[i].second == pb) return (int)i * (L + 1);
-            pairs.push_back({pa, pb});
-            return (int)(pairs.size() - 1) * (L + 1);
-        };
         std::vector<std::array<int, 4>> dl;
+        int slots() const { return (int)pairs.size(); }
+    };
+    std::vector<LPart> part(2 * lmax4 + 1);
+    for (int L = 0; L <= 2 * lmax4; ++L) {
+        LPart& P = part[L];
+        auto slot_of = [&](int pa, int pb) {
+            for (size_t i = 0; i < P.pairs.size(); ++i)
+                if (P.pairs[i].first == pa && P.pairs[i].second == pb) return (int)i * (L + 1);
+            P.pairs.push_back({pa, pb});
+            return (int)(P.pairs.size() - 1) * (L + 1);
+        };
         for (int k = 0; k < n4; ++k) {
             const int* d = &set[5 * k];
             if (d[4] != L) continue;
-            dl.push_back({slot_of(d[0], d[1]), slot_of(d[2], d[3]), k, (d[2] % nl + d[3] % nl)});
+            P.dl.push_back({slot_of(d[0], d[1]), slot_of(d[2], d[3]), k, (d[2] % nl + d[3] % nl)});
+        }
+    }
+    // phases: several L share one pass (one pair formation, one evaluation,
+    // two barriers) while their slots fit the LDS budget and their entries
+    // the staged table; first fit, largest L first
+    const int slot_cap = (int)(kAce4LdsBudget / (sizeof(float) * 2 * 64));
+    std::vector<int> order;
+    for (int L = 0; L <= 2 * lmax4; ++L)
+        if (!part[L].dl.empty()) order.push_back(L);
+    auto slots_of = [&](int L) { return part[L].slots() * (L + 1); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return slots_of(a) > slots_of(b); });
+    std::vector<std::vector<int>> phases;
+    std::vector<int> ph_slots, ph_descs;
+    for (int L : order) {
+        size_t i = 0;
+        for (; i < phases.size(); ++i)
+            if (ph_slots[i] + slots_of(L) <= slot_cap && ph_descs[i] + (int)part[L].dl.size() <= kAce4MaxDescsL)
+                break;
+        if (i == phases.size()) {
+            phases.push_back({});
+            ph_slots.push_back(0);
+            ph_descs.push_back(0);
+        }
+        phases[i].push_back(L);
+        ph_slots[i] += slots_of(L);
+        ph_descs[i] += (int)part[L].dl.size();
+    }
+    std::vector<int> block_of(4 * 4 * 7, -1);        // (l1, l2, L) with l <= 3, L <= 6
+    for (auto& ph : phases) {
+        std::sort(ph.begin(), ph.end());
+        std::vector<std::array<int, 5>> dl;           // slot a, slot b, output, l3+l4, L
+        int base = 0;
+        for (int L : ph) {
+            const LPart& P = part[L];
+            for (const auto& x : P.dl) dl.push_back({x[0] + base, x[1] + base, x[2], x[3], L});
+            // one unit per pair: P_a(M) for M = 0..L by code specialised for
+            // (l1, l2, L), with the Clebsch-Gordan coefficients of that
+            // combination in one block, ordered M = 0..L, m1 = -l1..l1 with
+            // |M - m1| <= l2 (zeros included)
+            for (size_t i = 0; i < P.pairs.size(); ++i) {
+                const int pa = P.pairs[i].first, pb = P.pairs[i].second;
+                const int n1 = pa / nl, l1 = pa % nl, n2 = pb / nl, l2 = pb % nl;
+                const int combo = (l1 * 4 + l2) * 7 + L;
+                if (block_of[combo] < 0) {
+                    block_of[combo] = (int)coef.size();
+                    for (int M = 0; M <= L; ++M)
+                        for (int m1 = -l1; m1 <= l1; ++m1) {
+                            const int m2 = M - m1;
+                            if (abs(m2) > l2) continue;
+                            coef.push_back((float)cg(l1, m1, l2, m2, L, M));
+                        }
+                }
+                const int base1 = n1 * 15 + l1 * (l1 + 1) / 2, base2 = n2 * 15 + l2 * (l2 + 1) / 2;
+                units.push_back(make_int4(block_of[combo], combo, base + (int)i * (L + 1), base1 | (base2 << 8)));
+            }
+            base += slots_of(L);
         }
         // descriptors sharing their first pair next to each other
-        std::stable_sort(dl.begin(), dl.end(), [](const std::array<int, 4>& x, const std::array<int, 4>& y) {
+        std::stable_sort(dl.begin(), dl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
             return x[0] < y[0];
         });
         for (const auto& x : dl) {
-            const double f = ((x[3] & 1) ? -1.0 : 1.0) / sqrt(2.0 * L + 1.0);     // (-1)^(l3+l4-L) (-1)^L
+            const double f = ((x[3] & 1) ? -1.0 : 1.0) / sqrt(2.0 * x[4] + 1.0);   // (-1)^(l3+l4-L) (-1)^L
             float ff = (float)f;
             int fb;
             memcpy(&fb, &ff, 4);
-            descs.push_back(make_int4(x[0], x[1], x[2], fb));
+            descs.push_back(make_int4(x[0] | (x[4] << 16), x[1], x[2], fb));
         }
-        // one unit per pair: P_a(M) for M = 0..L by code specialised for
-        // (l1, l2, L), with the Clebsch-Gordan coefficients of that
-        // combination in one block, ordered M = 0..L, m1 = -l1..l1 with
-        // |M - m1| <= l2 (zeros included)
-        for (size_t i = 0; i < pairs.size(); ++i) {
-            const int pa = pairs[i].first, pb = pairs[i].second;
-            const int n1 = pa / nl, l1 = pa % nl, n2 = pb / nl, l2 = pb % nl;
-            const int combo = (l1 * 4 + l2) * 7 + L;
-            if (block_of[combo] < 0) {
-                block_of[combo] = (int)coef.size();
-                for (int M = 0; M <= L; ++M)
-                    for (int m1 = -l1; m1 <= l1; ++m1) {
-                        const int m2 = M - m1;
-                        if (abs(m2) > l2) continue;
-                        coef.push_back((float)cg(l1, m1, l2, m2, L, M));
-                    }
-            }
-            const int base1 = n1 * 15 + l1 * (l1 + 1) / 2, base2 = n2 * 15 + l2 * (l2 + 1) / 2;
-            units.push_back(make_int4(block_of[combo], combo, (int)i * (L + 1), base1 | (base2 << 8)));
-        }
-        max_slots = std::max(max_slots, (int)pairs.size() * (L + 1));
+        max_slots = std::max(max_slots, base);
         l_units.push_back((int)units.size());
         l_descs.push_back((int)descs.size());
     }
