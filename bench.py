@@ -286,7 +286,8 @@ def stats_summary(prof_dir, bench_json, out_name, command):
         if name.startswith("mala::k_zb<"):
             zb = float(r["AverageNs"]) / 1e6
     lines += ["", "The metric's step runs the cell list, `k_ui`, `k_zb`, `k_mlp` and `k_fermi` "
-              "(and `k_density_window`); `k_gauss`, `k_mlp_vjp`, `k_yi`, `k_dedr`, `k_ace` and `k_ace4` come "
+              "(and `k_density_window`); `k_gauss`, `k_mlp_vjp`, `k_yi`, `k_dedr`, `k_ace_proj`, `k_ace`, `k_ace4` and "
+              "`k_planes_to_rows` come "
               "from the lines outside the metric (Gaussian descriptors, both VJPs, grid ACE) when they are run."]
     if b is None:
         with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
