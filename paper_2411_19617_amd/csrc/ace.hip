@@ -461,21 +461,25 @@ __global__ __launch_bounds__(64 * kAce4Waves) void k_ace4(const float2* __restri
             const int sa = sx & 0xffff, L = sx >> 16;             // a slot identifies its L too
             const int ok = __builtin_amdgcn_readfirstlane(q.z);
             const float f = __int_as_float(__builtin_amdgcn_readfirstlane(q.w));
-            if (sa != cached) {
+            // code per L: a descriptor's LDS reads issue together, with no
+            // branch per M between them
+            float v = 0.f;
+            static_for<0, 2 * kAce4MaxL + 1>([&](auto lc) {
+                constexpr int LL = decltype(lc)::value;
+                if (L != LL) return;
+                if (sa != cached) {
 #pragma unroll
-                for (int M = 0; M <= 2 * kAce4MaxL; ++M)
-                    if (M <= L) pa[M] = sP[(sa + M) * kTile + lane];
-                cached = sa;
-            }
-            const float2 b0 = sP[sb * kTile + lane];
-            float acc = 0.f;
-#pragma unroll
-            for (int M = 1; M <= 2 * kAce4MaxL; ++M)
-                if (M <= L) {
-                    const float2 b = sP[(sb + M) * kTile + lane];
-                    acc = fmaf(pa[M].x, b.x, fmaf(pa[M].y, b.y, acc));
+                    for (int M = 0; M <= LL; ++M) pa[M] = sP[(sa + M) * kTile + lane];
+                    cached = sa;
                 }
-            const float v = f * fmaf(2.f, acc, pa[0].x * b0.x + pa[0].y * b0.y);
+                float2 b[LL + 1];
+#pragma unroll
+                for (int M = 0; M <= LL; ++M) b[M] = sP[(sb + M) * kTile + lane];
+                float acc = 0.f;
+#pragma unroll
+                for (int M = 1; M <= LL; ++M) acc = fmaf(pa[M].x, b[M].x, fmaf(pa[M].y, b[M].y, acc));
+                v = f * fmaf(2.f, acc, pa[0].x * b[0].x + pa[0].y * b[0].y);
+            });
             if (tl.valid) o[ok * ds] = v;
         }
         __syncthreads();
