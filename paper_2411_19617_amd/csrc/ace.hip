@@ -312,25 +312,31 @@ __global__ __launch_bounds__(64 * kAce3Waves) void k_ace(const float2* __restric
                 if (combo == C) ace3_group<C / 25, (C / 5) % 5, C % 5>(sA, b1, b2, lane, cf, pr, pim);
             }
         });
-        static_for<0, kAceN>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            if (k >= oc) return;
-            const int ok = __builtin_amdgcn_readfirstlane(h[6 + k]);
-            const int base3 = ok & 127;
-            float v = 0.f;
-            static_for<0, 9>([&](auto sc) {
-                constexpr int slot = decltype(sc)::value;
-                constexpr int m3 = slot - 4, am = m3 < 0 ? -m3 : m3;
-                if (am <= l3) {
+        // every n3 of the group, by code specialised for l3: the A reads of
+        // an output issue together, with no branch per m3 between them
+        static_for<0, kAceMaxL + 1>([&](auto lc) {
+            constexpr int L3 = decltype(lc)::value;
+            if (l3 != L3) return;
+            static_for<0, kAceN>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if (k >= oc) return;
+                const int ok = __builtin_amdgcn_readfirstlane(h[6 + k]);
+                const int base3 = ok & 127;
+                float2 c[L3 + 1];
+#pragma unroll
+                for (int am = 0; am <= L3; ++am) c[am] = sA[base3 + am][lane];
+                float v = 0.f;
+                static_for<4 - L3, 5 + L3>([&](auto sc) {
+                    constexpr int slot = decltype(sc)::value;
+                    constexpr int m3 = slot - 4, am = m3 < 0 ? -m3 : m3;
                     // A_{l3,m3} = A_{l3,|m3|} for m3 >= 0, (-1)^|m3| conj(A_{l3,|m3|}) below
-                    const float2 c = sA[base3 + am][lane];
                     constexpr float sg = (m3 < 0 && (am & 1)) ? -1.f : 1.f;
-                    const float cy = m3 < 0 ? -c.y : c.y;
-                    v = fmaf(sg, pr[slot] * c.x - pim[slot] * cy, v);    // Re(P A)
-                }
+                    const float cy = m3 < 0 ? -c[am].y : c[am].y;
+                    v = fmaf(sg, pr[slot] * c[am].x - pim[slot] * cy, v);    // Re(P A)
+                });
+                if constexpr (stage) sO[wave][(ok >> 7) - col0][lane] = v;
+                else if (valid) o[(n12 + (ok >> 7)) * ds] = v;
             });
-            if constexpr (stage) sO[wave][(ok >> 7) - col0][lane] = v;
-            else if (valid) o[(n12 + (ok >> 7)) * ds] = v;
         });
         if (stage && (pw >> 8)) {                     // the pair's last group: write its columns
             const int ncol = pw & 255;
